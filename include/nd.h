@@ -1,0 +1,175 @@
+/*
+ * nd.h -- C ABI of libnd.so, the MI355X (gfx950) hot path for the network
+ * dynamics method of Sudakov & Maistrenko, arXiv 2410.19075.
+ *
+ * The paper states the problem as: models with per-group parameters, a
+ * coupling topology given at run time, initial values of the dynamical
+ * variables, and a trajectory (or derived observables) returned at specified
+ * times (Sec. II, last paragraph; Sec. III.A).  Its integrator calls the
+ * per-oscillator right-hand side once per solver stage for every element in
+ * parallel (Sec. III.A, Sec. III.D).  This library evaluates that right-hand
+ * side -- including each element's coupling sum over its neighbourhood --
+ * inside the four stages of a fixed-step classical Runge-Kutta integrator,
+ * entirely on the GPU.
+ *
+ * Models (Sec. II):
+ *   ND_KURAMOTO  Eq. (3) with m = 0, eps = 1 and a natural frequency:
+ *                dphi_i/dt = omega + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
+ *                L = number of neighbours (the paper's Alg. 1 divides by the link count).
+ *                params = {omega, mu, alpha}.  Topology ND_RING or ND_CUBE3D.
+ *   ND_FHN       Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational coupling
+ *                matrix B(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] applied to
+ *                (u_j - u_i, v_j - v_i), averaged over the 2P ring neighbours, inside the
+ *                eps-scaled fast equation.  params = {eps, a, sigma, phi}.  ND_RING only.
+ *   ND_HH        Eq. (1) for the squid axon (Na, K, leak; textbook rate functions, rest
+ *                -65 mV) with an instantaneous sigmoidal synapse:
+ *                C dV_i/dt = I_i - I_ion + (Esyn - V_i) sum_{e in in(i)} w_e S(V_src(e)),
+ *                S(V) = 1 / (1 + exp(-(V - theta_s)/k_s)).
+ *                params = {C, gNa, gK, gL, ENa, EK, EL, Esyn, theta_s, k_s}; per_elem = I_i.
+ *                ND_CSR only.
+ *
+ * Topologies (Sec. IV; Sec. III.C for general coupling matrices):
+ *   ND_RING      element i couples to i +- 1 .. i +- P (periodic), requires 1 <= P, 2P+1 <= n.
+ *   ND_CUBE3D    periodic n1 x n2 x n3 lattice, index x + n1*y + n1*n2*z (the paper's 3D index
+ *                map), neighbours = the (2h+1)^3 cube minus the element itself; n1,n2,n3 >= 2h+1.
+ *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,
+ *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
+ *
+ * State layout: variable-major FP64, length nvars * n: Kuramoto phi[n] (unwrapped, never reduced
+ * mod 2 pi); FHN u[n] then v[n]; HH V[n], m[n], h[n], n[n].
+ *
+ * Precision: ND_FP64 computes everything in IEEE double.  ND_FP32_BULK computes the per-element
+ * maps (sin/cos, sigmoid, rate functions) and the local right-hand side in float and stores the
+ * stage slopes k in float, while every neighbourhood sum, the state y and the RK accumulator stay
+ * double.
+ *
+ * Ownership: the caller owns every pointer it passes.  nd_create copies topology, weights and
+ * per-element data (host pointers) to the device, so the caller may free them on return.  The
+ * library owns its device buffers; nd_destroy frees them.  Pointers passed with on_device = 1 are
+ * device pointers that must stay valid until the work enqueued on the stream has completed.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued asynchronously
+ * on it; only the getters with on_device = 0 synchronise it.
+ *
+ * Errors: every call returns ND_OK (0) or a negative nd_status.  Argument errors are detected on
+ * the host before any device work and return ND_ERR_INVALID_ARG; nd_last_error() then returns a
+ * thread-local description.  No C++ exception crosses this interface.
+ *
+ * Threading: one handle must not be used from two threads at once; different handles may.
+ */
+#ifndef ND_H
+#define ND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nd_status;
+#define ND_OK 0
+#define ND_ERR_INVALID_ARG (-1)
+#define ND_ERR_OUT_OF_MEMORY (-2)
+#define ND_ERR_DEVICE (-3)
+#define ND_ERR_NOT_READY (-4)
+#define ND_ERR_NUMERIC (-5)
+#define ND_ERR_UNSUPPORTED (-6)
+
+#define ND_KURAMOTO 0
+#define ND_FHN 1
+#define ND_HH 2
+
+#define ND_RING 0
+#define ND_CUBE3D 1
+#define ND_CSR 2
+
+#define ND_FP64 0
+#define ND_FP32_BULK 1
+
+#define ND_MAX_PARAMS 12
+
+/* A network: model, parameters, topology, precision.  All pointers are host pointers. */
+typedef struct nd_problem {
+    int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH */
+    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR */
+    int32_t precision;  /* ND_FP64, ND_FP32_BULK */
+    int32_t reserved;   /* must be 0 */
+    int64_t n;          /* number of elements */
+    int64_t radius;     /* ring: P; cube: half-width h */
+    int64_t n1, n2, n3; /* cube extents, n = n1*n2*n3 */
+    const int64_t* row_ptr; /* CSR: n+1 offsets, row_ptr[0] = 0, non-decreasing */
+    const int32_t* col;     /* CSR: nnz sources in [0, n) */
+    const double* weight;   /* CSR: nnz weights */
+    int64_t nnz;            /* CSR: number of edges = row_ptr[n] */
+    const double* per_elem; /* HH: applied current per neuron (n values); else NULL */
+    double params[ND_MAX_PARAMS]; /* model parameters, see above; unused entries ignored */
+} nd_problem;
+
+/* What to record during nd_run. */
+typedef struct nd_observe {
+    int64_t record_every;  /* > 0: record the order parameter R at run steps 0, r, 2r, ... (r =
+                              record_every), i.e. steps/r + 1 values; 0: record nothing.
+                              R = |sum_j exp(i theta_j)| / n, theta = phi (Kuramoto) or
+                              atan2(v, u) (FHN); the paper's synchronisation analysis at each
+                              output (Sec. V).  Not defined for HH (must be 0). */
+    int64_t mv_start_step; /* >= 0: record the mean phase velocity of every element over run steps
+                              [mv_start_step, steps), (theta(t_end) - theta(t_start)) / (t_end -
+                              t_start) on unwrapped phases (the paper's average-frequency
+                              profiles, Sec. IV); FHN unwraps atan2(v, u) step by step.
+                              -1: do not record.  Not defined for HH. */
+} nd_observe;
+
+typedef struct nd_net* nd_handle;
+
+/* Validate `p`, allocate device buffers and copy topology / weights / per-element data. */
+nd_status nd_create(const nd_problem* p, nd_handle* out);
+
+/* Device bytes nd_create would allocate for `p` (state, RK buffers, exchange buffers,
+ * topology), excluding observables. */
+nd_status nd_footprint(const nd_problem* p, int64_t* bytes);
+
+/* Copy the state (nvars*n doubles, layout above) into the network. */
+nd_status nd_set_state(nd_handle h, const double* y, int64_t len, int32_t on_device, void* stream);
+
+/* Integrate `steps` classical RK4 steps of size dt from the current state:
+ *   k1 = F(y), k2 = F(y + dt/2 k1), k3 = F(y + dt/2 k2), k4 = F(y + dt k3),
+ *   y <- y + dt/6 (k1 + 2 k2 + 2 k3 + k4).
+ * obs may be NULL (record nothing).  Asynchronous on `stream`. */
+nd_status nd_run(nd_handle h, double dt, int64_t steps, const nd_observe* obs, void* stream);
+
+/* Integrate several networks together: one set of batched launches covers all of them, each with
+ * its own dt, step count and observation settings (obs may be NULL or an array of `count`).
+ * Every network's arithmetic is the same as in nd_run. */
+nd_status nd_run_batch(const nd_handle* hs, int32_t count, const double* dt, const int64_t* steps,
+                       const nd_observe* obs, void* stream);
+
+/* Copy the current state out (nvars*n doubles). */
+nd_status nd_get_state(nd_handle h, double* y, int64_t len, int32_t on_device, void* stream);
+
+/* Copy the observables of the last nd_run: R (r_len must equal steps/record_every + 1) and/or the
+ * mean phase velocity (mv_len must equal n).  Pass NULL / 0 to skip either. */
+nd_status nd_get_observables(nd_handle h, double* R, int64_t r_len, double* mean_vel, int64_t mv_len,
+                             int32_t on_device, void* stream);
+
+nd_status nd_destroy(nd_handle h);
+
+/* Kernel configuration (chosen by the autotuner; callers normally leave it alone). */
+typedef struct nd_kernel_config {
+    int32_t tile;   /* ring: elements per tile (multiple of the block size); cube: tile x-y edge;
+                       CSR: lanes per row group (4..64, power of two) */
+    int32_t block;  /* threads per workgroup (64..1024, multiple of 64) */
+    int32_t grid;   /* persistent grid size in workgroups; 0 = one workgroup per work item */
+    int32_t chunk;  /* steps per captured graph chunk (serving) */
+} nd_kernel_config;
+
+nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
+nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);
+
+const char* nd_status_str(nd_status s);
+const char* nd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ND_H */

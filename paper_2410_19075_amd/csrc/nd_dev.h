@@ -1,0 +1,135 @@
+// Shared host/device definitions of libnd: the per-network descriptor that every
+// kernel reads, and wave/block primitives for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nd.h"
+
+namespace nd {
+
+constexpr int kWave = 64;
+
+// Per-network descriptor, one per network of a batch, resident in device memory.
+// The chunk-position fields (g0, nsteps, ypar) advance on the device at the end
+// of every chunk, so a captured chunk graph can be replayed without host writes.
+struct NetDesc {
+    int64_t n;          // elements
+    int64_t P;          // ring radius / cube half-width
+    int32_t n1, n2, n3; // cube extents
+    int32_t G;          // ring: number of tiles
+    int32_t model, prec, obs, tile;
+    double dt;
+    double p[12];       // derived model constants (layout per model, see runtime)
+    double* y[2];       // state, double-buffered across steps
+    double* acc;        // RK accumulator y + dt/6 k1 + dt/3 k2
+    void* k[3];         // k1, k2, k3 in the bulk type (double or float)
+    double* tsum[2];    // ring: per-tile sums of the mapped stage values, 2 comps
+    double* rsum;       // FHN: per-tile sums of the unit phase vectors (u, v)/|(u, v)|
+    void* sx[2];        // HH: exchanged synaptic activations S(V) per stage
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const void* w;
+    const double* iapp;
+    double* R;          // order parameter per recorded step
+    int64_t r_every;
+    double* mv;         // mean phase velocity accumulator / result
+    int64_t mv_start;
+    double mv_scale;    // 1 / (t_end - t_start)
+    int64_t g0;         // run step index at the start of the current chunk
+    int64_t nsteps;     // steps still to do at the start of the current chunk
+    int32_t ypar;       // which y buffer holds the state at the start of the chunk
+    int32_t status;     // non-zero: a non-finite value was produced
+};
+
+enum : int32_t { OBS_R = 1, OBS_MV = 2 };
+
+__device__ __forceinline__ int64_t ring_wrap(int64_t i, int64_t n) {
+    // valid for i in [-n, 2n)
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// ---------------------------------------------------------------- wave/block
+// All reductions below use a fixed combination tree, so every lane and every
+// launch produces bitwise identical sums for identical inputs.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;  // identical in all lanes: IEEE addition is commutative
+}
+
+__device__ __forceinline__ double wave_incl_scan(double x) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        double t = __shfl_up(x, d, kWave);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
+// Sum NV values over the block (result in every thread). lds: NV * (BS/64) doubles.
+template <int BS, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+    constexpr int NW = BS / kWave;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[q * NW + wid] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += lds[q * NW + w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+// One pass over LDS that returns, in every thread, the block sums of NR values
+// and the block-exclusive prefix of NS values (thread order).
+// lds: (NR + NS) * (BS/64) doubles.
+template <int BS, int NR, int NS>
+__device__ __forceinline__ void block_sum_and_exscan(double (&r)[NR], double (&s)[NS], double* lds) {
+    constexpr int NW = BS / kWave;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) r[q] = wave_sum(r[q]);
+    double incl[NS], excl[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        incl[q] = wave_incl_scan(s[q]);
+        double t = __shfl_up(incl[q], 1, kWave);
+        excl[q] = lane == 0 ? 0.0 : t;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) lds[q * NW + wid] = r[q];
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) lds[(NR + q) * NW + wid] = incl[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a += lds[q * NW + w];
+        r[q] = a;
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double a = 0.0;
+        for (int w = 0; w < wid; ++w) a += lds[(NR + q) * NW + w];
+        s[q] = a + excl[q];
+    }
+    __syncthreads();
+}
+
+}  // namespace nd

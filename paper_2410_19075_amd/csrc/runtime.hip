@@ -1,0 +1,525 @@
+// Host runtime of libnd: argument validation, device buffers, batched launch
+// sequences and the C ABI declared in include/nd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nd_dev.h"
+#include "runtime.h"
+
+namespace nd {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+nd_status fail(nd_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+nd_status hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return fail(ND_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+    return fail(ND_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPC(expr)                                        \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+// ------------------------------------------------------------ validation
+int nvars_of(int model) { return model == ND_KURAMOTO ? 1 : (model == ND_FHN ? 2 : 4); }
+
+static bool finite_all(const double* p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+nd_status validate_problem(const nd_problem* p) {
+    if (!p) return fail(ND_ERR_INVALID_ARG, "problem is NULL");
+    if (p->reserved != 0) return fail(ND_ERR_INVALID_ARG, "reserved field must be 0");
+    if (p->precision != ND_FP64 && p->precision != ND_FP32_BULK)
+        return fail(ND_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+    if (p->n < 1) return fail(ND_ERR_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)p->n);
+    if (p->n > (int64_t(1) << 31) - 1) return fail(ND_ERR_INVALID_ARG, "n must be < 2^31");
+    const int np = p->model == ND_KURAMOTO ? 3 : (p->model == ND_FHN ? 4 : 10);
+    if (p->model < 0 || p->model > 2) return fail(ND_ERR_INVALID_ARG, "unknown model %d", p->model);
+    if (!finite_all(p->params, np)) return fail(ND_ERR_INVALID_ARG, "model parameters must be finite");
+    if (p->model == ND_FHN && p->params[0] == 0.0) return fail(ND_ERR_INVALID_ARG, "FHN eps must be non-zero");
+    if (p->model == ND_HH && (p->params[0] == 0.0 || p->params[9] == 0.0))
+        return fail(ND_ERR_INVALID_ARG, "HH C and k_s must be non-zero");
+    switch (p->topo) {
+        case ND_RING:
+            if (p->model == ND_HH) return fail(ND_ERR_INVALID_ARG, "HH needs the CSR topology");
+            if (p->radius < 1 || 2 * p->radius + 1 > p->n)
+                return fail(ND_ERR_INVALID_ARG, "ring radius P must satisfy 1 <= P and 2P+1 <= n (n=%lld, P=%lld)",
+                            (long long)p->n, (long long)p->radius);
+            break;
+        case ND_CUBE3D: {
+            if (p->model != ND_KURAMOTO) return fail(ND_ERR_INVALID_ARG, "the cube topology is for Kuramoto");
+            const int64_t side = 2 * p->radius + 1;
+            if (p->radius < 1 || p->n1 < side || p->n2 < side || p->n3 < side)
+                return fail(ND_ERR_INVALID_ARG, "cube extents must be >= 2h+1");
+            if (p->n1 * p->n2 * p->n3 != p->n) return fail(ND_ERR_INVALID_ARG, "n must equal n1*n2*n3");
+            break;
+        }
+        case ND_CSR: {
+            if (p->model != ND_HH) return fail(ND_ERR_INVALID_ARG, "the CSR topology is for HH");
+            if (!p->row_ptr || (p->nnz > 0 && (!p->col || !p->weight)) || !p->per_elem)
+                return fail(ND_ERR_INVALID_ARG, "CSR needs row_ptr, col, weight and per_elem");
+            if (p->row_ptr[0] != 0 || p->row_ptr[p->n] != p->nnz)
+                return fail(ND_ERR_INVALID_ARG, "row_ptr must start at 0 and end at nnz");
+            for (int64_t i = 0; i < p->n; ++i)
+                if (p->row_ptr[i + 1] < p->row_ptr[i]) return fail(ND_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+            for (int64_t e = 0; e < p->nnz; ++e)
+                if (p->col[e] < 0 || p->col[e] >= p->n) return fail(ND_ERR_INVALID_ARG, "col[%lld] out of range", (long long)e);
+            if (!finite_all(p->weight, (int)std::min<int64_t>(p->nnz, INT32_MAX)))
+                return fail(ND_ERR_INVALID_ARG, "weights must be finite");
+            if (!finite_all(p->per_elem, (int)p->n)) return fail(ND_ERR_INVALID_ARG, "per_elem must be finite");
+            break;
+        }
+        default:
+            return fail(ND_ERR_INVALID_ARG, "unknown topology %d", p->topo);
+    }
+    return ND_OK;
+}
+
+// ------------------------------------------------------------ configuration
+nd_kernel_config default_config(const nd_problem* p) {
+    nd_kernel_config c{};
+    c.grid = 0;
+    c.chunk = 64;
+    if (p->topo == ND_RING) {
+        c.tile = p->n <= (int64_t(1) << 16) ? 1024 : (p->n <= (int64_t(1) << 20) ? 2048 : 4096);
+        c.block = c.tile == 4096 ? 512 : (c.tile == 512 ? 128 : 256);
+    } else if (p->topo == ND_CUBE3D) {
+        c.tile = 16;
+        c.block = 256;
+    } else {
+        c.tile = 16;
+        c.block = 256;
+    }
+    return c;
+}
+
+static int64_t bulk_bytes(int prec) { return prec == ND_FP64 ? 8 : 4; }
+
+static int64_t ring_tiles(int64_t n, int tile) { return (n + tile - 1) / tile; }
+
+int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
+    const int64_t V = nvars_of(p->model), n = p->n, kb = bulk_bytes(p->precision);
+    int64_t b = 3 * V * n * 8 + 3 * V * n * kb;  // y[2], acc, k[3]
+    if (p->topo == ND_RING) b += 3 * 2 * ring_tiles(n, c.tile) * 8;
+    if (p->topo == ND_CSR) b += (n + 1) * 8 + p->nnz * (4 + kb) + n * 8 + 2 * n * kb;
+    b += sizeof(NetDesc) + 64;
+    return b;
+}
+
+// -------------------------------------------------------------- allocation
+nd_status Net::alloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    allocs.push_back(*ptr);
+    return ND_OK;
+}
+
+Net::~Net() {
+    for (void* q : allocs) (void)hipFree(q);
+}
+
+static void derive_params(const nd_problem* p, NetDesc& d) {
+    std::memset(d.p, 0, sizeof d.p);
+    if (p->model == ND_KURAMOTO) {
+        const double L = p->topo == ND_RING ? 2.0 * (double)p->radius
+                                            : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
+        d.p[0] = p->params[0];
+        d.p[1] = p->params[1] / L;
+        d.p[2] = std::cos(p->params[2]);
+        d.p[3] = std::sin(p->params[2]);
+    } else if (p->model == ND_FHN) {
+        d.p[0] = p->params[0];
+        d.p[1] = p->params[1];
+        d.p[2] = p->params[2] / (2.0 * (double)p->radius);
+        d.p[3] = std::cos(p->params[3]);
+        d.p[4] = std::sin(p->params[3]);
+        d.p[5] = 2.0 * (double)p->radius;
+    } else {
+        for (int i = 0; i < 10; ++i) d.p[i] = p->params[i];
+    }
+}
+
+nd_status Net::create(const nd_problem* pr) {
+    prob = *pr;
+    prob.row_ptr = nullptr;
+    prob.col = nullptr;
+    prob.weight = nullptr;
+    prob.per_elem = nullptr;
+    cfg = default_config(pr);
+    const int64_t V = nvars_of(pr->model), n = pr->n, kb = bulk_bytes(pr->precision);
+    std::memset(&tmpl, 0, sizeof tmpl);
+    NetDesc& d = tmpl;
+    d.n = n;
+    d.P = pr->radius;
+    d.n1 = (int32_t)pr->n1;
+    d.n2 = (int32_t)pr->n2;
+    d.n3 = (int32_t)pr->n3;
+    d.model = pr->model;
+    d.prec = pr->precision;
+    derive_params(pr, d);
+    nd_status s;
+    for (int b = 0; b < 2; ++b)
+        if ((s = alloc((void**)&d.y[b], V * n * 8))) return s;
+    if ((s = alloc((void**)&d.acc, V * n * 8))) return s;
+    for (int b = 0; b < 3; ++b)
+        if ((s = alloc(&d.k[b], V * n * kb))) return s;
+    if (pr->topo == ND_RING) {
+        d.tile = cfg.tile;
+        d.G = (int32_t)ring_tiles(n, cfg.tile);
+        for (int b = 0; b < 2; ++b)
+            if ((s = alloc((void**)&d.tsum[b], 2 * d.G * 8))) return s;
+        if ((s = alloc((void**)&d.rsum, 2 * d.G * 8))) return s;
+    }
+    if (pr->topo == ND_CSR) {
+        if ((s = alloc((void**)&d.row_ptr, (n + 1) * 8))) return s;
+        if ((s = alloc((void**)&d.col, std::max<int64_t>(pr->nnz, 1) * 4))) return s;
+        if ((s = alloc((void**)&d.w, std::max<int64_t>(pr->nnz, 1) * kb))) return s;
+        if ((s = alloc((void**)&d.iapp, n * 8))) return s;
+        for (int b = 0; b < 2; ++b)
+            if ((s = alloc(&d.sx[b], n * kb))) return s;
+        HIPC(hipMemcpy((void*)d.row_ptr, pr->row_ptr, (n + 1) * 8, hipMemcpyHostToDevice));
+        if (pr->nnz > 0) {
+            HIPC(hipMemcpy((void*)d.col, pr->col, pr->nnz * 4, hipMemcpyHostToDevice));
+            if (kb == 8) {
+                HIPC(hipMemcpy((void*)d.w, pr->weight, pr->nnz * 8, hipMemcpyHostToDevice));
+            } else {
+                std::vector<float> wf(pr->nnz);
+                for (int64_t e = 0; e < pr->nnz; ++e) wf[e] = (float)pr->weight[e];
+                HIPC(hipMemcpy((void*)d.w, wf.data(), pr->nnz * 4, hipMemcpyHostToDevice));
+            }
+        }
+        HIPC(hipMemcpy((void*)d.iapp, pr->per_elem, n * 8, hipMemcpyHostToDevice));
+    }
+    // single-network launch arrays (descriptor, work map, counts)
+    const int64_t nwork = work_items();
+    if ((s = alloc((void**)&solo_desc, sizeof(NetDesc)))) return s;
+    if ((s = alloc((void**)&solo_work, nwork * sizeof(int2)))) return s;
+    if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
+    std::vector<int2> wk;
+    append_work(0, wk);
+    HIPC(hipMemcpy(solo_work, wk.data(), wk.size() * sizeof(int2), hipMemcpyHostToDevice));
+    int cnt[2] = {(int)wk.size(), 1};
+    HIPC(hipMemcpy(solo_count, cnt, sizeof cnt, hipMemcpyHostToDevice));
+    return ND_OK;
+}
+
+int64_t Net::work_items() const {
+    if (prob.topo == ND_RING) return tmpl.G;
+    return 1;
+}
+
+void Net::append_work(int desc_index, std::vector<int2>& wk) const {
+    const int64_t m = work_items();
+    for (int64_t t = 0; t < m; ++t) wk.push_back(make_int2(desc_index, (int)t));
+}
+
+nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs) {
+    last_steps = steps;
+    r_every = 0;
+    mv_start = -1;
+    if (!obs) return ND_OK;
+    if (obs->record_every < 0) return fail(ND_ERR_INVALID_ARG, "record_every must be >= 0");
+    if (obs->mv_start_step < -1) return fail(ND_ERR_INVALID_ARG, "mv_start_step must be >= -1");
+    const bool want_r = obs->record_every > 0, want_mv = obs->mv_start_step >= 0;
+    if ((want_r || want_mv) && prob.model == ND_HH)
+        return fail(ND_ERR_INVALID_ARG, "R and mean phase velocity are not defined for HH");
+    if ((want_r || want_mv) && steps < 1) return fail(ND_ERR_INVALID_ARG, "recording observables needs steps >= 1");
+    if (want_mv && obs->mv_start_step >= steps) return fail(ND_ERR_INVALID_ARG, "mv_start_step must be < steps");
+    nd_status s;
+    if (want_r) {
+        const int64_t len = steps / obs->record_every + 1;
+        if (len > R_cap) {
+            if (R_dev) {
+                (void)hipFree(R_dev);
+                allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)R_dev));
+            }
+            if ((s = alloc((void**)&R_dev, len * 8))) return s;
+            R_cap = len;
+        }
+        r_every = obs->record_every;
+    }
+    if (want_mv) {
+        if (!mv_dev && (s = alloc((void**)&mv_dev, prob.n * 8))) return s;
+        mv_start = obs->mv_start_step;
+    }
+    return ND_OK;
+}
+
+NetDesc Net::run_desc(double dt, int64_t steps) const {
+    NetDesc d = tmpl;
+    d.dt = dt;
+    d.obs = (r_every > 0 ? OBS_R : 0) | (mv_start >= 0 ? OBS_MV : 0);
+    d.R = R_dev;
+    d.r_every = r_every > 0 ? r_every : 1;
+    d.mv = mv_dev;
+    d.mv_start = mv_start;
+    d.mv_scale = mv_start >= 0 ? 1.0 / ((double)(steps - mv_start) * dt) : 0.0;
+    d.g0 = 0;
+    d.nsteps = steps;
+    d.ypar = ypar;
+    d.status = 0;
+    return d;
+}
+
+// ----------------------------------------------------------- launch groups
+__global__ void k_advance(NetDesc* D, int ndesc, int chunk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ndesc) {
+        NetDesc& d = D[i];
+        if (d.nsteps > 0) {
+            const int64_t done = d.nsteps < chunk ? d.nsteps : (int64_t)chunk;
+            d.g0 += done;
+            d.nsteps -= done;
+            d.ypar ^= (int)(done & 1);
+        }
+    }
+}
+
+// Enqueue one chunk of `chunk` steps for a group of networks of one kernel
+// class.  Each network runs min(chunk, remaining) steps.
+nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
+    const int grid = g.grid;
+    hipError_t e;
+    if (g.topo == ND_RING) {
+        RingLaunch L;
+        if (!ring_select(g.model, g.prec, g.tile, &L)) return fail(ND_ERR_UNSUPPORTED, "no ring kernel for tile %d", g.tile);
+        if ((e = ring_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess) return hip_fail(e, "ring prologue");
+        for (int j = 0; j < chunk; ++j)
+            for (int s = 1; s <= 4; ++s)
+                if ((e = ring_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j)) != hipSuccess)
+                    return hip_fail(e, "ring stage");
+        if ((e = ring_launch_epilogue(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
+            return hip_fail(e, "ring epilogue");
+    } else {
+        return fail(ND_ERR_UNSUPPORTED, "topology %d not supported yet", g.topo);
+    }
+    hipLaunchKernelGGL(k_advance, dim3((g.ndesc + 255) / 256), dim3(256), 0, st, g.desc, g.ndesc, chunk);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "advance");
+    return ND_OK;
+}
+
+// Run a set of networks (possibly of different classes) for their own step counts.
+nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t* steps, const nd_observe* obs,
+                   hipStream_t st) {
+    // validate and prepare observables
+    for (int i = 0; i < count; ++i) {
+        if (!nets[i]) return fail(ND_ERR_INVALID_ARG, "handle %d is NULL", i);
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(ND_ERR_INVALID_ARG, "dt must be finite and > 0");
+        if (steps[i] < 0) return fail(ND_ERR_INVALID_ARG, "steps must be >= 0");
+        for (int k = 0; k < i; ++k)
+            if (nets[k] == nets[i]) return fail(ND_ERR_INVALID_ARG, "a handle appears twice in one batch");
+    }
+    nd_status s;
+    for (int i = 0; i < count; ++i)
+        if ((s = nets[i]->prepare_observe(steps[i], obs ? &obs[i] : nullptr))) return s;
+    // group by kernel class
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+        if (steps[i] == 0) continue;
+        const Net* n = nets[i];
+        groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile)].push_back(i);
+    }
+    for (auto& kv : groups) {
+        const std::vector<int>& idx = kv.second;
+        Group g{};
+        g.model = std::get<0>(kv.first);
+        g.topo = std::get<1>(kv.first);
+        g.prec = std::get<2>(kv.first);
+        g.tile = std::get<3>(kv.first);
+        g.ndesc = (int)idx.size();
+        int64_t maxsteps = 0;
+        std::vector<NetDesc> descs;
+        std::vector<int2> work;
+        for (int q = 0; q < (int)idx.size(); ++q) {
+            Net* n = nets[idx[q]];
+            descs.push_back(n->run_desc(dt[idx[q]], steps[idx[q]]));
+            n->append_work(q, work);
+            maxsteps = std::max(maxsteps, steps[idx[q]]);
+        }
+        const bool solo = idx.size() == 1;
+        void* scratch = nullptr;
+        if (solo) {
+            Net* n = nets[idx[0]];
+            g.desc = n->solo_desc;
+            g.work = n->solo_work;
+            g.nwork = n->solo_count;
+        } else {
+            const size_t bd = descs.size() * sizeof(NetDesc), bw = work.size() * sizeof(int2);
+            HIPC(hipMallocAsync(&scratch, bd + bw + 16, st));
+            g.desc = (NetDesc*)scratch;
+            g.work = (int2*)((char*)scratch + bd);
+            g.nwork = (int*)((char*)scratch + bd + bw);
+            HIPC(hipMemcpyAsync(g.work, work.data(), bw, hipMemcpyHostToDevice, st));
+            int nw = (int)work.size();
+            HIPC(hipMemcpyAsync(g.nwork, &nw, sizeof nw, hipMemcpyHostToDevice, st));
+        }
+        HIPC(hipMemcpyAsync(g.desc, descs.data(), descs.size() * sizeof(NetDesc), hipMemcpyHostToDevice, st));
+        const int cfg_grid = nets[idx[0]]->cfg.grid;
+        g.grid = cfg_grid > 0 ? std::min<int>(cfg_grid, (int)work.size()) : (int)work.size();
+        const int chunk = (int)std::min<int64_t>(maxsteps, 1 << 30);
+        if ((s = enqueue_chunk(g, chunk, st))) return s;
+        if (scratch) HIPC(hipFreeAsync(scratch, st));
+        // pageable sources of the async copies above must stay alive until consumed
+        HIPC(hipStreamSynchronize(st));
+    }
+    for (int i = 0; i < count; ++i) nets[i]->ypar ^= (int)(steps[i] & 1);
+    return ND_OK;
+}
+
+}  // namespace nd
+
+// =================================================================== C ABI
+using namespace nd;
+
+extern "C" {
+
+nd_status nd_create(const nd_problem* p, nd_handle* out) {
+    if (!out) return fail(ND_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    nd_status s = validate_problem(p);
+    if (s) return s;
+    Net* n = new (std::nothrow) Net();
+    if (!n) return fail(ND_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if ((s = n->create(p))) {
+        delete n;
+        return s;
+    }
+    *out = reinterpret_cast<nd_handle>(n);
+    return ND_OK;
+}
+
+nd_status nd_footprint(const nd_problem* p, int64_t* bytes) {
+    if (!bytes) return fail(ND_ERR_INVALID_ARG, "bytes is NULL");
+    nd_status s = validate_problem(p);
+    if (s) return s;
+    *bytes = footprint_bytes(p, default_config(p));
+    return ND_OK;
+}
+
+static Net* as_net(nd_handle h) { return reinterpret_cast<Net*>(h); }
+
+nd_status nd_set_state(nd_handle h, const double* y, int64_t len, int32_t on_device, void* stream) {
+    Net* n = as_net(h);
+    if (!n || !y) return fail(ND_ERR_INVALID_ARG, "NULL handle or state");
+    const int64_t want = nvars_of(n->prob.model) * n->prob.n;
+    if (len != want) return fail(ND_ERR_INVALID_ARG, "state length %lld, expected %lld", (long long)len, (long long)want);
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(hipMemcpyAsync(n->tmpl.y[n->ypar], y, len * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    if (!on_device) HIPC(hipStreamSynchronize(st));
+    return ND_OK;
+}
+
+nd_status nd_get_state(nd_handle h, double* y, int64_t len, int32_t on_device, void* stream) {
+    Net* n = as_net(h);
+    if (!n || !y) return fail(ND_ERR_INVALID_ARG, "NULL handle or state");
+    const int64_t want = nvars_of(n->prob.model) * n->prob.n;
+    if (len != want) return fail(ND_ERR_INVALID_ARG, "state length %lld, expected %lld", (long long)len, (long long)want);
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(hipMemcpyAsync(y, n->tmpl.y[n->ypar], len * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (!on_device) HIPC(hipStreamSynchronize(st));
+    return ND_OK;
+}
+
+nd_status nd_run(nd_handle h, double dt, int64_t steps, const nd_observe* obs, void* stream) {
+    Net* n = as_net(h);
+    if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle");
+    return run_nets(&n, 1, &dt, &steps, obs, (hipStream_t)stream);
+}
+
+nd_status nd_run_batch(const nd_handle* hs, int32_t count, const double* dt, const int64_t* steps,
+                       const nd_observe* obs, void* stream) {
+    if (!hs || !dt || !steps || count < 0) return fail(ND_ERR_INVALID_ARG, "bad batch arguments");
+    std::vector<Net*> nets(count);
+    for (int i = 0; i < count; ++i) nets[i] = as_net(hs[i]);
+    return run_nets(nets.data(), count, dt, steps, obs, (hipStream_t)stream);
+}
+
+nd_status nd_get_observables(nd_handle h, double* R, int64_t r_len, double* mean_vel, int64_t mv_len,
+                             int32_t on_device, void* stream) {
+    Net* n = as_net(h);
+    if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle");
+    hipStream_t st = (hipStream_t)stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (R) {
+        if (n->r_every <= 0) return fail(ND_ERR_INVALID_ARG, "the last run recorded no R");
+        const int64_t want = n->last_steps / n->r_every + 1;
+        if (r_len != want) return fail(ND_ERR_INVALID_ARG, "r_len %lld, expected %lld", (long long)r_len, (long long)want);
+        HIPC(hipMemcpyAsync(R, n->R_dev, want * 8, kind, st));
+    }
+    if (mean_vel) {
+        if (n->mv_start < 0) return fail(ND_ERR_INVALID_ARG, "the last run recorded no mean velocity");
+        if (mv_len != n->prob.n) return fail(ND_ERR_INVALID_ARG, "mv_len must equal n");
+        HIPC(hipMemcpyAsync(mean_vel, n->mv_dev, mv_len * 8, kind, st));
+    }
+    if (!on_device) HIPC(hipStreamSynchronize(st));
+    return ND_OK;
+}
+
+nd_status nd_destroy(nd_handle h) {
+    Net* n = as_net(h);
+    if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle");
+    (void)hipDeviceSynchronize();
+    delete n;
+    return ND_OK;
+}
+
+nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg) {
+    Net* n = as_net(h);
+    if (!n || !cfg) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    *cfg = n->cfg;
+    return ND_OK;
+}
+
+nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
+    Net* n = as_net(h);
+    if (!n || !cfg) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    if (cfg->grid < 0 || cfg->chunk < 1) return fail(ND_ERR_INVALID_ARG, "grid must be >= 0 and chunk >= 1");
+    if (n->prob.topo == ND_RING && cfg->tile != n->cfg.tile)
+        return fail(ND_ERR_INVALID_ARG, "the ring tile is fixed at nd_create (tiles size the buffers)");
+    n->cfg.grid = cfg->grid;
+    n->cfg.chunk = cfg->chunk;
+    return ND_OK;
+}
+
+const char* nd_status_str(nd_status s) {
+    switch (s) {
+        case ND_OK: return "ok";
+        case ND_ERR_INVALID_ARG: return "invalid argument";
+        case ND_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case ND_ERR_DEVICE: return "device error";
+        case ND_ERR_NOT_READY: return "not ready";
+        case ND_ERR_NUMERIC: return "non-finite value";
+        case ND_ERR_UNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* nd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+"""ctypes binding of libnd.so with the names of include/nd.h.
+
+Argument marshalling only: every step of the hot path runs in the HIP library.
+Importing this module loads the library and fails loudly when it has not been
+built (python -m paper_2410_19075_amd.build); there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+ND_OK = 0
+ND_ERR_INVALID_ARG = -1
+ND_ERR_OUT_OF_MEMORY = -2
+ND_ERR_DEVICE = -3
+ND_ERR_NOT_READY = -4
+ND_ERR_NUMERIC = -5
+ND_ERR_UNSUPPORTED = -6
+
+ND_KURAMOTO, ND_FHN, ND_HH = 0, 1, 2
+ND_RING, ND_CUBE3D, ND_CSR = 0, 1, 2
+ND_FP64, ND_FP32_BULK = 0, 1
+ND_MAX_PARAMS = 12
+NVARS = {ND_KURAMOTO: 1, ND_FHN: 2, ND_HH: 4}
+
+_c_i32, _c_i64, _c_dbl, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class nd_problem(ctypes.Structure):
+    _fields_ = [("model", _c_i32), ("topo", _c_i32), ("precision", _c_i32), ("reserved", _c_i32),
+                ("n", _c_i64), ("radius", _c_i64), ("n1", _c_i64), ("n2", _c_i64), ("n3", _c_i64),
+                ("row_ptr", _c_vp), ("col", _c_vp), ("weight", _c_vp), ("nnz", _c_i64),
+                ("per_elem", _c_vp), ("params", _c_dbl * ND_MAX_PARAMS)]
+
+
+class nd_observe(ctypes.Structure):
+    _fields_ = [("record_every", _c_i64), ("mv_start_step", _c_i64)]
+
+
+class nd_kernel_config(ctypes.Structure):
+    _fields_ = [("tile", _c_i32), ("block", _c_i32), ("grid", _c_i32), ("chunk", _c_i32)]
+
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnd.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libnd.so is not built ({LIB_PATH}); run python -m paper_2410_19075_amd.build")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.POINTER
+_sig = {
+    "nd_create": [_P(nd_problem), _P(_c_vp)],
+    "nd_footprint": [_P(nd_problem), _P(_c_i64)],
+    "nd_set_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
+    "nd_run": [_c_vp, _c_dbl, _c_i64, _P(nd_observe), _c_vp],
+    "nd_run_batch": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_i64), _P(nd_observe), _c_vp],
+    "nd_get_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
+    "nd_get_observables": [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp],
+    "nd_destroy": [_c_vp],
+    "nd_get_config": [_c_vp, _P(nd_kernel_config)],
+    "nd_set_config": [_c_vp, _P(nd_kernel_config)],
+}
+for _name, _args in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _c_i32
+_lib.nd_status_str.argtypes = [_c_i32]
+_lib.nd_status_str.restype = ctypes.c_char_p
+_lib.nd_last_error.argtypes = []
+_lib.nd_last_error.restype = ctypes.c_char_p
+
+
+class NDError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.nd_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.nd_status_str(status).decode()} ({status}): {msg}")
+
+
+def _check(status, where):
+    if status != ND_OK:
+        raise NDError(status, where)
+    return status
+
+
+def _ptr(a):
+    """Device or host pointer of a torch tensor / numpy array (None -> NULL)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def problem(model, topo, n, params, precision=ND_FP64, radius=0, dims=(0, 0, 0), row_ptr=None, col=None,
+            weight=None, per_elem=None):
+    """Build an nd_problem.  The numpy arrays must stay alive until nd_create returns
+    (the struct keeps references in `_keep`)."""
+    p = nd_problem()
+    p.model, p.topo, p.precision, p.reserved = model, topo, precision, 0
+    p.n, p.radius = int(n), int(radius)
+    p.n1, p.n2, p.n3 = (int(d) for d in dims)
+    keep = []
+
+    def arr(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    p.row_ptr = arr(row_ptr, np.int64)
+    p.col = arr(col, np.int32)
+    p.weight = arr(weight, np.float64)
+    p.nnz = 0 if row_ptr is None else int(np.asarray(row_ptr)[-1])
+    p.per_elem = arr(per_elem, np.float64)
+    for i, v in enumerate(params):
+        p.params[i] = float(v)
+    p._keep = keep
+    return p
+
+
+def nd_create(p):
+    h = _c_vp()
+    _check(_lib.nd_create(ctypes.byref(p), ctypes.byref(h)), "nd_create")
+    return h.value
+
+
+def nd_footprint(p):
+    b = _c_i64()
+    _check(_lib.nd_footprint(ctypes.byref(p), ctypes.byref(b)), "nd_footprint")
+    return b.value
+
+
+def nd_set_state(h, y, on_device=None, stream=None):
+    on = int(hasattr(y, "is_cuda") and y.is_cuda) if on_device is None else int(on_device)
+    n = y.numel() if hasattr(y, "numel") else y.size
+    _check(_lib.nd_set_state(h, _ptr(y), n, on, _stream(stream)), "nd_set_state")
+
+
+def nd_get_state(h, y, on_device=None, stream=None):
+    on = int(hasattr(y, "is_cuda") and y.is_cuda) if on_device is None else int(on_device)
+    n = y.numel() if hasattr(y, "numel") else y.size
+    _check(_lib.nd_get_state(h, _ptr(y), n, on, _stream(stream)), "nd_get_state")
+
+
+def observe(record_every=0, mv_start_step=-1):
+    return nd_observe(int(record_every), int(mv_start_step))
+
+
+def nd_run(h, dt, steps, obs=None, stream=None):
+    _check(_lib.nd_run(h, float(dt), int(steps), ctypes.byref(obs) if obs is not None else None,
+                       _stream(stream)), "nd_run")
+
+
+def nd_run_batch(handles, dts, steps, obs=None, stream=None):
+    k = len(handles)
+    hs = (_c_vp * k)(*handles)
+    dd = (_c_dbl * k)(*[float(x) for x in dts])
+    ss = (_c_i64 * k)(*[int(x) for x in steps])
+    oo = (nd_observe * k)(*obs) if obs is not None else None
+    _check(_lib.nd_run_batch(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch")
+
+
+def nd_get_observables(h, R=None, mean_vel=None, on_device=None, stream=None):
+    ref = R if R is not None else mean_vel
+    on = int(hasattr(ref, "is_cuda") and ref.is_cuda) if on_device is None else int(on_device)
+
+    def size(a):
+        return 0 if a is None else (a.numel() if hasattr(a, "numel") else a.size)
+
+    _check(_lib.nd_get_observables(h, _ptr(R), size(R), _ptr(mean_vel), size(mean_vel), on, _stream(stream)),
+           "nd_get_observables")
+
+
+def nd_destroy(h):
+    _check(_lib.nd_destroy(h), "nd_destroy")
+
+
+def nd_get_config(h):
+    c = nd_kernel_config()
+    _check(_lib.nd_get_config(h, ctypes.byref(c)), "nd_get_config")
+    return c
+
+
+def nd_set_config(h, c):
+    _check(_lib.nd_set_config(h, ctypes.byref(c)), "nd_set_config")
+
+
+def nd_status_str(s):
+    return _lib.nd_status_str(s).decode()
+
+
+def nd_last_error():
+    return _lib.nd_last_error().decode()
+
+
+# ------------------------------------------------------------ conveniences
+def simulate(p, y0, dt, steps, record_every=0, mv_start_step=-1, stream=None):
+    """Create a network, run it from host state y0 and return (y, R, mean_vel) as
+    numpy arrays (all work on the GPU)."""
+    h = nd_create(p)
+    try:
+        y0 = np.ascontiguousarray(y0, dtype=np.float64)
+        nd_set_state(h, y0, on_device=0, stream=stream)
+        nd_run(h, dt, steps, observe(record_every, mv_start_step), stream=stream)
+        y = np.empty_like(y0)
+        nd_get_state(h, y, on_device=0, stream=stream)
+        R = np.empty(steps // record_every + 1) if record_every else None
+        mv = np.empty(p.n) if mv_start_step >= 0 else None
+        if R is not None or mv is not None:
+            nd_get_observables(h, R, mv, on_device=0, stream=stream)
+        return y, R, mv
+    finally:
+        nd_destroy(h)

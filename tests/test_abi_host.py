@@ -1,0 +1,129 @@
+"""Host-side checks of the C-ABI library: it loads, exports what include/nd.h
+declares, and rejects bad arguments before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_19075_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:nd_status|const char\*)\s+(nd_\w+)\s*\(", txt, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_19075_amd import nd
+    lib = ctypes.CDLL(nd.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    from paper_2410_19075_amd import nd
+    assert nd.nd_status_str(0) == "ok"
+    assert nd.nd_status_str(-1) == "invalid argument"
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(model=0, topo=0, n=10, radius=5), "2P+1"),
+    (dict(model=0, topo=0, n=10, radius=0), "2P+1"),
+    (dict(model=2, topo=0, n=10, radius=2), "CSR"),
+    (dict(model=0, topo=1, n=8 ** 3, radius=4, dims=(8, 8, 8)), "2h+1"),
+    (dict(model=0, topo=1, n=999, radius=4, dims=(10, 10, 10)), "n1*n2*n3"),
+    (dict(model=1, topo=1, n=1000, radius=1, dims=(10, 10, 10)), "Kuramoto"),
+    (dict(model=7, topo=0, n=10, radius=1), "model"),
+])
+def test_invalid_problems_are_rejected_on_the_host(kw, needle):
+    from paper_2410_19075_amd import nd
+    p = nd.problem(kw["model"], kw["topo"], kw["n"], [1.0, 1.0, 1.0, 0.5, 0, 0, 0, 0, 0, 1.0],
+                   radius=kw["radius"], dims=kw.get("dims", (0, 0, 0)))
+    with pytest.raises(nd.NDError) as ei:
+        nd.nd_footprint(p)
+    assert ei.value.status == nd.ND_ERR_INVALID_ARG
+    assert needle in str(ei.value)
+
+
+def test_nonfinite_parameters_rejected():
+    from paper_2410_19075_amd import nd
+    p = nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 100, [0.0, float("nan"), 1.0], radius=3)
+    with pytest.raises(nd.NDError):
+        nd.nd_footprint(p)
+
+
+def test_csr_validation():
+    from paper_2410_19075_amd import nd
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    prm = [1, 120, 36, 0.3, 50, -77, -54.387, 0, 0, 2]
+    good = nd.problem(nd.ND_HH, nd.ND_CSR, 2, prm, row_ptr=rp, col=np.array([1, 0]), weight=np.array([.1, .1]),
+                      per_elem=np.zeros(2))
+    assert nd.nd_footprint(good) > 0
+    bad = nd.problem(nd.ND_HH, nd.ND_CSR, 2, prm, row_ptr=rp, col=np.array([1, 5]), weight=np.array([.1, .1]),
+                     per_elem=np.zeros(2))
+    with pytest.raises(nd.NDError):
+        nd.nd_footprint(bad)
+
+
+def test_footprint_grows_with_precision_and_size():
+    from paper_2410_19075_amd import nd
+    f64 = nd.nd_footprint(nd.problem(nd.ND_FHN, nd.ND_RING, 65536, [0.05, 0.5, 0.1, 1.47], radius=22937))
+    f32 = nd.nd_footprint(nd.problem(nd.ND_FHN, nd.ND_RING, 65536, [0.05, 0.5, 0.1, 1.47], radius=22937,
+                                     precision=nd.ND_FP32_BULK))
+    assert f64 > f32 > 2 * 65536 * 8 * 3
+
+
+# ------------------------------------------------------------ input generators
+def test_generators_are_deterministic_and_in_range():
+    a = inputs.kuramoto_phases(7, 1000)
+    assert np.array_equal(a, inputs.kuramoto_phases(7, 1000))
+    assert not np.array_equal(a, inputs.kuramoto_phases(8, 1000))
+    assert a.min() >= -np.pi and a.max() < np.pi
+    assert abs(a.mean()) < 0.2
+    u = inputs.uniform(1, 1, 200000)
+    assert abs(u.mean() - 0.5) < 0.005 and abs(u.var() - 1 / 12) < 0.002
+    y = inputs.fhn_circle(3, 500)
+    assert np.allclose(y[:500] ** 2 + y[500:] ** 2, 4.0)
+
+
+def test_splitmix64_reference_values():
+    """SplitMix64 as published: state += 0x9E3779B97F4A7C15, then the two
+    xor-shift-multiply rounds.  From state 0 the first outputs are the
+    generator's well-known test vector."""
+    z = np.array([0x9E3779B97F4A7C15, 2 * 0x9E3779B97F4A7C15 % 2 ** 64], dtype=np.uint64)
+    out = inputs._mix(z)
+    assert int(out[0]) == 0xE220A8397B1DCDAF
+    assert int(out[1]) == 0x6E789E6AA1B965F4
+
+
+def test_random_graph_structure():
+    rp, col, w = inputs.random_out_graph(5, 2000, 30)
+    assert rp[0] == 0 and rp[-1] == 2000 * 30 and np.all(np.diff(rp) >= 0)
+    tgt = np.repeat(np.arange(2000), np.diff(rp))
+    assert np.all(col != tgt)
+    # distinct targets per source, ascending sources per target
+    assert len(set(zip(col.tolist(), tgt.tolist()))) == col.size
+    for i in range(0, 2000, 97):
+        seg = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+    assert np.all(np.bincount(col, minlength=2000) == 30)
+    assert w.min() >= 0 and w.max() < 0.1
+
+
+def test_patch_is_planted():
+    phi = inputs.cube_phases_with_patch(3, 20)
+    vals, counts = np.unique(phi, return_counts=True)
+    big = counts.max()
+    # a ball of radius 4 holds 257 lattice points
+    assert big == 257
