@@ -155,11 +155,14 @@ nd_status nd_destroy(nd_handle h);
 
 /* Kernel configuration (chosen by the autotuner; callers normally leave it alone). */
 typedef struct nd_kernel_config {
-    int32_t tile;   /* ring: elements per tile (multiple of the block size); cube: tile x-y edge;
-                       CSR: lanes per row group (4..64, power of two) */
-    int32_t block;  /* threads per workgroup (64..1024, multiple of 64) */
+    int32_t tile;   /* ring: elements per tile (256, 512, 1024, 2048 or 4096);
+                       cube: output tile extent along x; CSR: rows per workgroup */
+    int32_t block;  /* threads per workgroup (derived; ignored by nd_set_config) */
     int32_t grid;   /* persistent grid size in workgroups; 0 = one workgroup per work item */
-    int32_t chunk;  /* steps per captured graph chunk (serving) */
+    int32_t chunk;  /* steps per captured graph chunk */
+    int32_t tile_y; /* cube: output tile extent along y ((tile+2h)*(tile_y+2h) <= 1024);
+                       CSR: lanes per row (4..64, power of two) */
+    int32_t tile_z; /* cube: planes per work item */
 } nd_kernel_config;
 
 nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);

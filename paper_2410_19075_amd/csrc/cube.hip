@@ -1,0 +1,338 @@
+// Kuramoto-Sakaguchi on a periodic n1 x n2 x n3 lattice, stage kernels for gfx950.
+//
+// Element (x, y, z) (index x + n1*y + n1*n2*z, the paper's 3D index map, Sec. IV)
+// couples to every element of the cube [x-H, x+H] x [y-H, y+H] x [z-H, z+H]
+// except itself; the sum of sin(z_j - z_i - alpha) is normalised by the
+// (2H+1)^3 - 1 neighbours, as Alg. 1 divides by its link count.  The paper's
+// own 3D runs use a ball neighbourhood; the cube is the separable case.
+//
+// Each work item owns a cx x cy column tile and a run of cz planes and streams
+// through z (a 2.5D scheme):
+//   * one thread per halo column (cx+2H) x (cy+2H) maps its stage values
+//     (cos z, sin z) plane by plane and keeps the last 2H+1 of them in
+//     registers, so the z-direction sum is a register sum;
+//   * the z-sums go to LDS, an x-pass and a y-pass (each 2H+1 terms) finish
+//     the cube sum for the cx x cy outputs of the plane;
+//   * the RHS and the RK bookkeeping follow the 13-access schedule of the ring
+//     kernels (y double-buffered, k in the bulk type).
+// The next plane's column values and RK operands are prefetched one plane
+// ahead, and the plane loop synchronises through LDS-only barriers so those
+// loads stay in flight.  All sums are double and every sum has a fixed order.
+#include "models.h"
+#include "runtime.h"
+
+namespace nd {
+
+__device__ __forceinline__ int wrapm(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Block sum for a runtime block size (<= 1024). lds: NV * 16 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_rt(double (&v)[NV], double* lds) {
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[q * 16 + wid] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[q * 16 + w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+template <class KT, int H, int STAGE, bool MV>
+__global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                    const int* __restrict__ nwork_p, int j) {
+    using M = RingModel<ND_KURAMOTO, KT>;
+    constexpr int S = 2 * H + 1;
+    constexpr int stage = STAGE;
+    extern __shared__ double2 smem[];
+    __shared__ double lds[2 * 16];
+    const int nwork = *nwork_p;
+    const int nvb = ((nwork + 7) >> 3) << 3;
+    const int tid = threadIdx.x;
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int w = xcd_work(vb, nwork);
+        if (w < 0) continue;
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (j >= d.nsteps) continue;  // uniform over the block
+        const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
+        const int64_t n = d.n;
+        const int64_t plane = (int64_t)n1 * n2;
+        const int cx = d.cx, cy = d.cy, cz = d.cz, gx = d.gx, gy = d.gy;
+        const int HX = cx + 2 * H, HY = cy + 2 * H;
+        const int t = wk.y;
+        const int tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
+        const int x0 = tx * cx, y0 = ty * cy, z0 = tz * cz;
+        const int ex = min(cx, n1 - x0), ey = min(cy, n2 - y0);
+        const int nz = min(cz, n3 - z0);
+        const int64_t g = d.g0 + j;
+        const int par = (d.ypar + j) & 1;
+        const double* __restrict__ y = d.y[par];
+        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage > 1 ? stage - 2 : 0];
+        const double* __restrict__ acc = d.acc;
+        const double dt = d.dt;
+        const double cdt = stage == 4 ? dt : 0.5 * dt;
+
+        // ---- order parameter R(g) from the stage-1 partial sums (stage 2, item 0)
+        if (stage == 2 && t == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
+            double s[2] = {0.0, 0.0};
+            for (int u = tid; u < d.G; u += blockDim.x) {
+                s[0] += d.tsum[0][2 * u];
+                s[1] += d.tsum[0][2 * u + 1];
+            }
+            block_sum_rt<2>(s, lds);
+            if (tid == 0) d.R[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
+        }
+
+        double2* S1 = smem;                  // [2][HY][HX] z-sums per halo column
+        double2* S0 = S1 + 2 * HX * HY;      // [2][cy][cx] mapped centre values
+        double2* S2 = S0 + 2 * cx * cy;      // [2][HY][cx] x-pass sums
+
+        // halo-column thread
+        const bool col = tid < HX * HY;
+        const int hx = col ? tid % HX : 0, hy = col ? tid / HX : 0;
+        const bool inner = col && hx >= H && hx < H + cx && hy >= H && hy < H + cy;
+        const int64_t colbase = wrapm(x0 - H + hx, n1) + (int64_t)n1 * wrapm(y0 - H + hy, n2);
+        // output thread
+        const bool outv = tid < cx * cy && (tid % cx) < ex && (tid / cx) < ey;
+        const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
+        const int64_t obase = (int64_t)(x0 + ox) + (int64_t)n1 * (y0 + oy);
+
+        double2 rb[S];
+#pragma unroll
+        for (int u = 0; u < 2 * H; ++u) {
+            double z[1];
+            stage_z<1, KT>(y, kp, cdt, n, colbase + plane * wrapm(z0 - H + u, n3), z);
+            rb[u] = M::map(z);
+        }
+        rb[2 * H] = make_double2(0.0, 0.0);
+        // prefetched operands: the next new column plane and the RK operands
+        double cyv, ckv = 0.0, ry, rk = 0.0, ra = 0.0;
+        {
+            const int64_t ci = colbase + plane * wrapm(z0 + H, n3);
+            cyv = y[ci];
+            if (stage != 1) ckv = (double)kp[ci];
+            const int64_t oi = obase + plane * z0;
+            ry = y[oi];
+            if (stage == 2 || stage == 4) rk = (double)kp[oi];
+            if (stage == 4) ra = acc[oi];
+        }
+        double part[2] = {0.0, 0.0};  // stage 1: sums of map(y) for R
+        for (int zb = 0; zb < nz; zb += S) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) {
+                if (zb + u < nz) {
+                    const int zo = z0 + zb + u;
+                    const double zc = stage == 1 ? cyv : fma(cdt, ckv, cyv);
+                    const double cry = ry, crk = rk, cra = ra;
+                    if (zb + u + 1 < nz) {
+                        const int64_t ci = colbase + plane * wrapm(zo + 1 + H, n3);
+                        cyv = y[ci];
+                        if (stage != 1) ckv = (double)kp[ci];
+                        const int64_t oi = obase + plane * (zo + 1);
+                        ry = y[oi];
+                        if (stage == 2 || stage == 4) rk = (double)kp[oi];
+                        if (stage == 4) ra = acc[oi];
+                    }
+                    {
+                        double z[1] = {zc};
+                        rb[(u + 2 * H) % S] = M::map(z);
+                    }
+                    double2 sz = make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int dz = -H; dz <= H; ++dz) {
+                        sz.x += rb[(u + dz + H) % S].x;
+                        sz.y += rb[(u + dz + H) % S].y;
+                    }
+                    const int buf = (zb + u) & 1;
+                    if (col) S1[buf * HX * HY + tid] = sz;
+                    if (inner) S0[buf * cx * cy + (hy - H) * cx + (hx - H)] = rb[(u + H) % S];
+                    lds_barrier();
+                    // x-pass over the HY rows
+                    for (int q = tid; q < HY * cx; q += blockDim.x) {
+                        const int row = q / cx, xx = q - row * cx;
+                        const double2* src = S1 + buf * HX * HY + row * HX + xx;
+                        double2 a = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int dx = 0; dx < S; ++dx) {
+                            a.x += src[dx].x;
+                            a.y += src[dx].y;
+                        }
+                        S2[buf * HY * cx + q] = a;
+                    }
+                    lds_barrier();
+                    // y-pass, RHS, RK bookkeeping
+                    if (outv) {
+                        const double2* src = S2 + buf * HY * cx + oy * cx + ox;
+                        double2 bsum = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int dy = 0; dy < S; ++dy) {
+                            bsum.x += src[dy * cx].x;
+                            bsum.y += src[dy * cx].y;
+                        }
+                        const double2 xo = S0[buf * cx * cy + oy * cx + ox];
+                        const double2 W = make_double2(bsum.x - xo.x, bsum.y - xo.y);
+                        double zdummy[1] = {0.0};
+                        double k[1];
+                        M::rhs(d, zdummy, xo, W, k);
+                        const int64_t q = obase + plane * zo;
+                        const double kk = kq<KT>(k[0]);
+                        if (stage == 1) {
+                            ((KT*)d.k[0])[q] = (KT)kk;
+                            part[0] += xo.x;
+                            part[1] += xo.y;
+                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) d.mv[q] = cry;
+                        } else if (stage == 2) {
+                            ((KT*)d.k[1])[q] = (KT)kk;
+                            d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, crk, cry));
+                        } else if (stage == 3) {
+                            ((KT*)d.k[2])[q] = (KT)kk;
+                        } else {
+                            d.y[par ^ 1][q] = fma(dt / 6.0, kk, fma(dt / 3.0, crk, cra));
+                        }
+                    }
+                }
+            }
+        }
+        if (stage == 1) {
+            block_sum_rt<2>(part, lds);
+            if (tid == 0) {
+                d.tsum[0][2 * t] = part[0];
+                d.tsum[0][2 * t + 1] = part[1];
+            }
+        } else {
+            __syncthreads();  // LDS reuse by the next work item
+        }
+    }
+}
+
+// After the last step of a run: partial sums of map(y) over flat element ranges
+// (one per work item) and the mean phase velocity.
+template <class KT>
+__global__ __launch_bounds__(256) void k_cube_final_partials(const NetDesc* __restrict__ D,
+                                                             const int2* __restrict__ work,
+                                                             const int* __restrict__ nwork_p, int chunk) {
+    using M = RingModel<ND_KURAMOTO, KT>;
+    __shared__ double lds[2 * 16];
+    const int nwork = *nwork_p;
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (d.nsteps <= 0 || d.nsteps > chunk) continue;
+        const int64_t n = d.n;
+        const int64_t per = (n + d.G - 1) / d.G;
+        const int64_t b = (int64_t)wk.y * per, e = min(n, b + per);
+        const double* y = d.y[(d.ypar + (int)d.nsteps) & 1];
+        double s[2] = {0.0, 0.0};
+        for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+            double z[1] = {y[i]};
+            const double2 x = M::map(z);
+            s[0] += x.x;
+            s[1] += x.y;
+            if (d.obs & OBS_MV) d.mv[i] = (y[i] - d.mv[i]) * d.mv_scale;
+        }
+        block_sum_rt<2>(s, lds);
+        if (threadIdx.x == 0) {
+            d.tsum[1][2 * wk.y] = s[0];
+            d.tsum[1][2 * wk.y + 1] = s[1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cube_final_R(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                      const int* __restrict__ nwork_p, int chunk) {
+    __shared__ double lds[2 * 16];
+    const int nwork = *nwork_p;
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (wk.y != 0 || d.nsteps <= 0 || d.nsteps > chunk || !(d.obs & OBS_R)) continue;
+        const int64_t gend = d.g0 + d.nsteps;
+        if (gend % d.r_every) continue;
+        double s[2] = {0.0, 0.0};
+        for (int u = threadIdx.x; u < d.G; u += blockDim.x) {
+            s[0] += d.tsum[1][2 * u];
+            s[1] += d.tsum[1][2 * u + 1];
+        }
+        block_sum_rt<2>(s, lds);
+        if (threadIdx.x == 0) d.R[gend / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)d.n;
+    }
+}
+
+// ------------------------------------------------------------------ launch
+template <class KT, int H>
+static void cube_entry(CubeLaunch* r) {
+    r->stage[0] = k_cube_stage<KT, H, 1, false>;
+    r->stage[1] = k_cube_stage<KT, H, 2, false>;
+    r->stage[2] = k_cube_stage<KT, H, 3, false>;
+    r->stage[3] = k_cube_stage<KT, H, 4, false>;
+    r->stage_mv[0] = k_cube_stage<KT, H, 1, true>;
+    r->stage_mv[1] = k_cube_stage<KT, H, 2, true>;
+    r->stage_mv[2] = k_cube_stage<KT, H, 3, true>;
+    r->stage_mv[3] = k_cube_stage<KT, H, 4, true>;
+    r->final_partials = k_cube_final_partials<KT>;
+    r->final_R = k_cube_final_R;
+}
+
+bool cube_select(int prec, int h, CubeLaunch* out) {
+    if (h < 1 || h > 4) return false;
+    if (prec == ND_FP64) {
+        switch (h) {
+            case 1: cube_entry<double, 1>(out); break;
+            case 2: cube_entry<double, 2>(out); break;
+            case 3: cube_entry<double, 3>(out); break;
+            default: cube_entry<double, 4>(out); break;
+        }
+    } else {
+        switch (h) {
+            case 1: cube_entry<float, 1>(out); break;
+            case 2: cube_entry<float, 2>(out); break;
+            case 3: cube_entry<float, 3>(out); break;
+            default: cube_entry<float, 4>(out); break;
+        }
+    }
+    return true;
+}
+
+size_t cube_smem_bytes(int h, int cx, int cy) {
+    const size_t HX = cx + 2 * h, HY = cy + 2 * h;
+    return (2 * HX * HY + 2 * (size_t)cx * cy + 2 * HY * cx) * sizeof(double2);
+}
+
+int cube_block(int h, int cx, int cy) {
+    const int cols = (cx + 2 * h) * (cy + 2 * h);
+    return ((cols + kWave - 1) / kWave) * kWave;
+}
+
+hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,
+                             const int2* work, const int* nwork, int stage, int j, bool mv) {
+    auto f = mv ? L.stage_mv[stage - 1] : L.stage[stage - 1];
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(f, dim3(grid), dim3(block), smem, s, D, work, nwork, j);
+    return hipGetLastError();
+}
+
+hipError_t cube_launch_final(const CubeLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                             const int* nwork, int chunk) {
+    hipLaunchKernelGGL(L.final_partials, dim3(grid), dim3(256), 0, s, D, work, nwork, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(L.final_R, dim3(grid), dim3(256), 0, s, D, work, nwork, chunk);
+    return hipGetLastError();
+}
+
+}  // namespace nd

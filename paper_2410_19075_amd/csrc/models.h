@@ -1,0 +1,109 @@
+// Per-element model arithmetic shared by the ring and lattice kernels: the
+// stage value, the coupling map and the local right-hand side.
+#pragma once
+
+#include "nd_dev.h"
+
+namespace nd {
+
+// Barrier for exchanges through LDS only: waits for this wave's LDS traffic
+// but lets outstanding global loads stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ------------------------------------------------------------------ models
+template <int MODEL, class KT>
+struct RingModel;
+
+// Kuramoto-Sakaguchi, Eq. (3) with m = 0, eps = 1:
+//   k_i = omega + mu/(2P) sum_j sin(z_j - z_i - alpha)
+//       = omega + mu/(2P) [cos(z_i + alpha) S_i - sin(z_i + alpha) C_i]
+// with (C_i, S_i) the window sums of (cos z_j, sin z_j).
+// p = {omega, mu/(2P), cos alpha, sin alpha}
+template <class KT>
+struct RingModel<ND_KURAMOTO, KT> {
+    static constexpr int V = 1;
+    __device__ static __forceinline__ double2 map(const double* z) {
+        double s, c;
+        if constexpr (sizeof(KT) == 8) {
+            sincos(z[0], &s, &c);
+        } else {
+            // bulk float: reduce to revolutions in double, then the hardware
+            // sin/cos (their argument is in revolutions)
+            double r = z[0] * 0.15915494309189535;  // 1 / (2 pi)
+            r -= rint(r);
+            float rf = (float)r;
+            s = (double)__builtin_amdgcn_sinf(rf);
+            c = (double)__builtin_amdgcn_cosf(rf);
+        }
+        return make_double2(c, s);
+    }
+    __device__ static __forceinline__ void rhs(const NetDesc& d, const double* z, double2 xo, double2 W,
+                                               double* k) {
+        (void)z;
+        if constexpr (sizeof(KT) == 8) {
+            const double ca = xo.x * d.p[2] - xo.y * d.p[3];
+            const double sa = xo.y * d.p[2] + xo.x * d.p[3];
+            k[0] = d.p[0] + d.p[1] * (ca * W.y - sa * W.x);
+        } else {
+            const float cf = (float)xo.x, sf = (float)xo.y;
+            const float ca = cf * (float)d.p[2] - sf * (float)d.p[3];
+            const float sa = sf * (float)d.p[2] + cf * (float)d.p[3];
+            k[0] = d.p[0] + d.p[1] * ((double)ca * W.y - (double)sa * W.x);
+        }
+    }
+};
+
+// FitzHugh-Nagumo, Eq. (2) (tau = 0, D = 0, I_app = 0) with the rotational
+// coupling B(phi) on (u_j - u_i, v_j - v_i), kappa = sigma / 2P:
+//   eps du = u - u^3/3 - v + kappa ( cos phi Du + sin phi Dv)
+//       dv = u + a         + kappa (-sin phi Du + cos phi Dv)
+// Du = sum_j u_j - 2P u_i, Dv likewise (double, before any rounding to float).
+// p = {eps, a, kappa, cos phi, sin phi, 2P}
+template <class KT>
+struct RingModel<ND_FHN, KT> {
+    static constexpr int V = 2;
+    __device__ static __forceinline__ double2 map(const double* z) { return make_double2(z[0], z[1]); }
+    __device__ static __forceinline__ void rhs(const NetDesc& d, const double* z, double2 xo, double2 W,
+                                               double* k) {
+        (void)xo;
+        const double u = z[0], v = z[1];
+        const double Du = W.x - d.p[5] * u;
+        const double Dv = W.y - d.p[5] * v;
+        if constexpr (sizeof(KT) == 8) {
+            const double cu = d.p[2] * (d.p[3] * Du + d.p[4] * Dv);
+            const double cv = d.p[2] * (d.p[3] * Dv - d.p[4] * Du);
+            k[0] = (u - u * u * u / 3.0 - v + cu) / d.p[0];
+            k[1] = u + d.p[1] + cv;
+        } else {
+            const float uf = (float)u, vf = (float)v, duf = (float)Du, dvf = (float)Dv;
+            const float kap = (float)d.p[2], cph = (float)d.p[3], sph = (float)d.p[4];
+            const float cu = kap * (cph * duf + sph * dvf);
+            const float cv = kap * (cph * dvf - sph * duf);
+            k[0] = (double)((uf - uf * uf * uf / 3.0f - vf + cu) / (float)d.p[0]);
+            k[1] = (double)(uf + (float)d.p[1] + cv);
+        }
+    }
+};
+
+template <class KT>
+__device__ __forceinline__ double kq(double k) {
+    return (double)(KT)k;  // the value that is stored (and that every reader sees)
+}
+
+// Stage value z_v(idx) = y + c dt k_prev (stage 1: y).  Written once here so the
+// producer of the tile sums and every reader of the window ends agree bitwise.
+template <int V, class KT>
+__device__ __forceinline__ void stage_z(const double* __restrict__ y, const KT* __restrict__ kp, double cdt,
+                                        int64_t n, int64_t idx, double* z) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const double yy = y[v * n + idx];
+        z[v] = kp ? fma(cdt, (double)kp[v * n + idx], yy) : yy;
+    }
+}
+
+}  // namespace nd

@@ -20,6 +20,8 @@ struct NetDesc {
     int32_t n1, n2, n3; // cube extents
     int32_t G;          // ring: number of tiles
     int32_t model, prec, obs, tile;
+    int32_t cx, cy, cz; // cube: output tile extents per work item (x, y, z)
+    int32_t gx, gy;     // cube: tiles along x and y
     double dt;
     double p[12];       // derived model constants (layout per model, see runtime)
     double* y[2];       // state, double-buffered across steps
@@ -48,6 +50,18 @@ enum : int32_t { OBS_R = 1, OBS_MV = 2 };
 __device__ __forceinline__ int64_t ring_wrap(int64_t i, int64_t n) {
     // valid for i in [-n, 2n)
     return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Work item -> tile mapping that keeps consecutive work items (the tiles of one
+// ring) on one XCD: workgroups are dispatched to the 8 XCDs round-robin by id,
+// so block b runs on XCD b % 8; XCD x takes the contiguous work range
+// [start(x), start(x) + cnt(x)).  A bijection on [0, nwork) when the number of
+// virtual blocks is nwork.
+__device__ __forceinline__ int xcd_work(int vb, int nwork) {
+    const int x = vb & 7, s = vb >> 3;
+    const int q = nwork >> 3, r = nwork & 7;
+    const int cnt = q + (x < r ? 1 : 0);
+    return s < cnt ? x * q + min(x, r) + s : -1;
 }
 
 // ---------------------------------------------------------------- wave/block

@@ -19,102 +19,10 @@
 //   stage 3: z = y + dt/2 k2     -> write k3
 //   stage 4: z = y + dt k3       -> y' = acc + dt/3 k3 + dt/6 k4
 // and every stage also writes the per-tile sums of map(z) for the next stage.
-#include "nd_dev.h"
+#include "models.h"
 #include "runtime.h"
 
 namespace nd {
-
-// ------------------------------------------------------------------ models
-template <int MODEL, class KT>
-struct RingModel;
-
-// Kuramoto-Sakaguchi, Eq. (3) with m = 0, eps = 1:
-//   k_i = omega + mu/(2P) sum_j sin(z_j - z_i - alpha)
-//       = omega + mu/(2P) [cos(z_i + alpha) S_i - sin(z_i + alpha) C_i]
-// with (C_i, S_i) the window sums of (cos z_j, sin z_j).
-// p = {omega, mu/(2P), cos alpha, sin alpha}
-template <class KT>
-struct RingModel<ND_KURAMOTO, KT> {
-    static constexpr int V = 1;
-    __device__ static __forceinline__ double2 map(const double* z) {
-        double s, c;
-        if constexpr (sizeof(KT) == 8) {
-            sincos(z[0], &s, &c);
-        } else {
-            // bulk float: reduce to revolutions in double, then the hardware
-            // sin/cos (their argument is in revolutions)
-            double r = z[0] * 0.15915494309189535;  // 1 / (2 pi)
-            r -= rint(r);
-            float rf = (float)r;
-            s = (double)__builtin_amdgcn_sinf(rf);
-            c = (double)__builtin_amdgcn_cosf(rf);
-        }
-        return make_double2(c, s);
-    }
-    __device__ static __forceinline__ void rhs(const NetDesc& d, const double* z, double2 xo, double2 W,
-                                               double* k) {
-        (void)z;
-        if constexpr (sizeof(KT) == 8) {
-            const double ca = xo.x * d.p[2] - xo.y * d.p[3];
-            const double sa = xo.y * d.p[2] + xo.x * d.p[3];
-            k[0] = d.p[0] + d.p[1] * (ca * W.y - sa * W.x);
-        } else {
-            const float cf = (float)xo.x, sf = (float)xo.y;
-            const float ca = cf * (float)d.p[2] - sf * (float)d.p[3];
-            const float sa = sf * (float)d.p[2] + cf * (float)d.p[3];
-            k[0] = d.p[0] + d.p[1] * ((double)ca * W.y - (double)sa * W.x);
-        }
-    }
-};
-
-// FitzHugh-Nagumo, Eq. (2) (tau = 0, D = 0, I_app = 0) with the rotational
-// coupling B(phi) on (u_j - u_i, v_j - v_i), kappa = sigma / 2P:
-//   eps du = u - u^3/3 - v + kappa ( cos phi Du + sin phi Dv)
-//       dv = u + a         + kappa (-sin phi Du + cos phi Dv)
-// Du = sum_j u_j - 2P u_i, Dv likewise (double, before any rounding to float).
-// p = {eps, a, kappa, cos phi, sin phi, 2P}
-template <class KT>
-struct RingModel<ND_FHN, KT> {
-    static constexpr int V = 2;
-    __device__ static __forceinline__ double2 map(const double* z) { return make_double2(z[0], z[1]); }
-    __device__ static __forceinline__ void rhs(const NetDesc& d, const double* z, double2 xo, double2 W,
-                                               double* k) {
-        (void)xo;
-        const double u = z[0], v = z[1];
-        const double Du = W.x - d.p[5] * u;
-        const double Dv = W.y - d.p[5] * v;
-        if constexpr (sizeof(KT) == 8) {
-            const double cu = d.p[2] * (d.p[3] * Du + d.p[4] * Dv);
-            const double cv = d.p[2] * (d.p[3] * Dv - d.p[4] * Du);
-            k[0] = (u - u * u * u / 3.0 - v + cu) / d.p[0];
-            k[1] = u + d.p[1] + cv;
-        } else {
-            const float uf = (float)u, vf = (float)v, duf = (float)Du, dvf = (float)Dv;
-            const float kap = (float)d.p[2], cph = (float)d.p[3], sph = (float)d.p[4];
-            const float cu = kap * (cph * duf + sph * dvf);
-            const float cv = kap * (cph * dvf - sph * duf);
-            k[0] = (double)((uf - uf * uf * uf / 3.0f - vf + cu) / (float)d.p[0]);
-            k[1] = (double)(uf + (float)d.p[1] + cv);
-        }
-    }
-};
-
-template <class KT>
-__device__ __forceinline__ double kq(double k) {
-    return (double)(KT)k;  // the value that is stored (and that every reader sees)
-}
-
-// Stage value z_v(idx) = y + c dt k_prev (stage 1: y).  Written once here so the
-// producer of the tile sums and every reader of the window ends agree bitwise.
-template <int V, class KT>
-__device__ __forceinline__ void stage_z(const double* __restrict__ y, const KT* __restrict__ kp, double cdt,
-                                        int64_t n, int64_t idx, double* z) {
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const double yy = y[v * n + idx];
-        z[v] = kp ? fma(cdt, (double)kp[v * n + idx], yy) : yy;
-    }
-}
 
 // ------------------------------------------------------------ prologue
 // Tile sums of map(y) for the first stage of a run (networks with g0 == 0).
@@ -135,7 +43,9 @@ __global__ __launch_bounds__(BS) void k_ring_prologue(const NetDesc* __restrict_
         double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int m = threadIdx.x * EPT + e;
+            // same element order and grouping as the stage kernel's next-stage
+            // sums, so a restarted run reproduces a continuous one bitwise
+            const int m = e * BS + threadIdx.x;
             if (m < cnt) {
                 double z[V];
                 stage_z<V, KT>(y, (const KT*)nullptr, 0.0, n, t0 + m, z);
@@ -162,15 +72,21 @@ __global__ __launch_bounds__(BS) void k_ring_prologue(const NetDesc* __restrict_
 }
 
 // ---------------------------------------------------------------- stage
-template <int MODEL, class KT, int BS, int EPT>
+template <int MODEL, class KT, int BS, int EPT, int STAGE, bool MV>
 __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
-                                                   const int* __restrict__ nwork_p, int stage, int j) {
+                                                   const int* __restrict__ nwork_p, int j) {
+    constexpr int stage = STAGE;
     using M = RingModel<MODEL, KT>;
     constexpr int V = M::V, T = BS * EPT, NW = BS / kWave;
+    __shared__ double2 sd[T];  // x_right - x_left, then the inclusive window sums
     __shared__ double lds[8 * NW];
     const int nwork = *nwork_p;
     const int tid = threadIdx.x;
-    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    // virtual block ids keep blockIdx.x % 8 (grid is a multiple of 8 or == nwork)
+    const int nvb = ((nwork + 7) >> 3) << 3;
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int w = xcd_work(vb, nwork);
+        if (w < 0) continue;
         const int2 wk = work[w];
         const NetDesc& d = D[wk.x];
         if (j >= d.nsteps) continue;  // uniform over the block
@@ -181,7 +97,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         const int64_t g = d.g0 + j;
         const int par = (d.ypar + j) & 1;
         const double* __restrict__ y = d.y[par];
-        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage - 2];
+        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage > 1 ? stage - 2 : 0];
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
         const double* __restrict__ tin = d.tsum[(stage - 1) & 1];
@@ -198,7 +114,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
             if (tid == 0) d.R[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
         }
 
-        // ---- window ends: x over [A, A+T) and [B, B+T), A = t0-P, B = t0+P+1
+        // ---- geometry of the window ends [A, A+T) and [B, B+T)
         const int64_t A = t0 - P, B = t0 + P + 1;
         const int64_t a = A < 0 ? A + n : A;
         const int64_t b = B >= n ? B - n : B;
@@ -212,78 +128,117 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         // one period of the ring, so a single conditional wrap is exact
         const int lneed = max(hlen, cnt), rneed = max(tlen, cnt);
 
+        // ---- phase 1 (coalesced, element m = e*BS + tid): own stage values,
+        // window-end differences into LDS, head / tail-remainder partial sums
         double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // head(2), tail remainder(2), tiles(2)
-        double dl[EPT][2];
-        double dsum[2] = {0.0, 0.0};
+        double zo[EPT][V];
+        double2 xo[EPT];
+        {
+            // all loads first, from always-valid (clamped) indices, so they are
+            // issued back to back; masks are applied to the values afterwards
+            double zl[EPT][V], zr[EPT][V];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int m = tid * EPT + e;
-            double2 xl = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
-            if (m < lneed) {
-                double z[V];
-                stage_z<V, KT>(y, kp, cdt, n, ring_wrap(A + m, n), z);
-                xl = M::map(z);
+            for (int e = 0; e < EPT; ++e) {
+                const int m = e * BS + tid;
+                const int64_t il = m < lneed ? ring_wrap(A + m, n) : t0;
+                const int64_t ir = m < rneed ? ring_wrap(B + m, n) : t0;
+                const int64_t io = m < cnt ? t0 + m : t0;
+                stage_z<V, KT>(y, kp, cdt, n, il, zl[e]);
+                stage_z<V, KT>(y, kp, cdt, n, ir, zr[e]);
+                stage_z<V, KT>(y, kp, cdt, n, io, zo[e]);
             }
-            if (m < rneed) {
-                double z[V];
-                stage_z<V, KT>(y, kp, cdt, n, ring_wrap(B + m, n), z);
-                xr = M::map(z);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int m = e * BS + tid;
+                double2 xl = M::map(zl[e]), xr = M::map(zr[e]);
+                xo[e] = M::map(zo[e]);
+                if (m >= lneed) xl = make_double2(0.0, 0.0);
+                if (m >= rneed) xr = make_double2(0.0, 0.0);
+                if (m < hlen) {
+                    red[0] += xl.x;
+                    red[1] += xl.y;
+                }
+                if (m < tlen) {
+                    red[2] += xr.x;
+                    red[3] += xr.y;
+                }
+                sd[m] = make_double2(xr.x - xl.x, xr.y - xl.y);
             }
-            if (m < hlen) {
-                red[0] += xl.x;
-                red[1] += xl.y;
-            }
-            if (m < tlen) {
-                red[2] += xr.x;
-                red[3] += xr.y;
-            }
-            dl[e][0] = xr.x - xl.x;
-            dl[e][1] = xr.y - xl.y;
-            dsum[0] += dl[e][0];
-            dsum[1] += dl[e][1];
         }
         for (int u = ua + 1 + tid; u <= ub; u += BS) {
             const int uu = u < 0 ? u + G : (u >= G ? u - G : u);
             red[4] += tin[2 * uu];
             red[5] += tin[2 * uu + 1];
         }
-        block_sum_and_exscan<BS, 6, 2>(red, dsum, lds);
-        const double w0x = (red[0] + red[4]) - red[2];
-        const double w0y = (red[1] + red[5]) - red[3];
+        __syncthreads();
 
-        // ---- own elements: RHS and RK bookkeeping
-        double nx[4] = {0.0, 0.0, 0.0, 0.0};  // next-stage tile sums (2) + FHN phase vectors (2)
-        double run0 = dsum[0], run1 = dsum[1];  // exclusive prefix of d before this thread's first element
-        const KT* __restrict__ k1 = (const KT*)d.k[0];
+        // ---- phase 2 (blocked, elements EPT*tid ..): exclusive scan of the
+        // differences; LDS then holds the inclusive window sum of every element
+        double2 dv[EPT];
+        double tot[2] = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int m = tid * EPT + e;
+            dv[e] = sd[tid * EPT + e];
+            tot[0] += dv[e].x;
+            tot[1] += dv[e].y;
+        }
+        block_sum_and_exscan<BS, 6, 2>(red, tot, lds);
+        {
+            const double w0x = (red[0] + red[4]) - red[2];
+            const double w0y = (red[1] + red[5]) - red[3];
+            double r0 = tot[0], r1 = tot[1];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                sd[tid * EPT + e] = make_double2(w0x + r0, w0y + r1);
+                r0 += dv[e].x;
+                r1 += dv[e].y;
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 3 (coalesced): RHS, RK bookkeeping, next-stage tile sums
+        // (loads from clamped indices issue together; only stores are masked)
+        double nx[4] = {0.0, 0.0, 0.0, 0.0};
+        double yv[EPT][V], kv[EPT][V], av[EPT][V];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int m = e * BS + tid;
+            const int64_t i = t0 + (m < cnt ? m : 0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int64_t q = v * n + i;
+                yv[e][v] = y[q];
+                kv[e][v] = (stage == 2 || stage == 4) ? (double)kp[q] : 0.0;
+                av[e][v] = stage == 4 ? d.acc[q] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int m = e * BS + tid;
             if (m < cnt) {
                 const int64_t i = t0 + m;
-                double z[V];
-                stage_z<V, KT>(y, kp, cdt, n, i, z);
-                const double2 xo = M::map(z);
-                const double2 W = make_double2((w0x + run0) - xo.x, (w0y + run1) - xo.y);
+                const double2 wi = sd[m];
+                const double2 W = make_double2(wi.x - xo[e].x, wi.y - xo[e].y);
                 double k[V];
-                M::rhs(d, z, xo, W, k);
+                M::rhs(d, zo[e], xo[e], W, k);
                 double zn[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int64_t q = v * n + i;
-                    const double yy = y[q];
+                    const double yy = yv[e][v];
                     const double kk = kq<KT>(k[v]);
                     if (stage == 1) {
                         ((KT*)d.k[0])[q] = (KT)kk;
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 2) {
                         ((KT*)d.k[1])[q] = (KT)kk;
-                        d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, (double)k1[q], yy));
+                        d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[e][v], yy));
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 3) {
                         ((KT*)d.k[2])[q] = (KT)kk;
                         zn[v] = fma(dt, kk, yy);
                     } else {
-                        const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, (double)kp[q], d.acc[q]));
+                        const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[e][v], av[e][v]));
                         d.y[par ^ 1][q] = yo;
                         zn[v] = yo;
                     }
@@ -298,13 +253,13 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                         nx[3] += zn[1] / r;
                     }
                 }
-                // mean phase velocity
-                if ((d.obs & OBS_MV) && g >= d.mv_start) {
+                // mean phase velocity (compiled only into the MV variants)
+                if (MV && (d.obs & OBS_MV) && g >= d.mv_start) {
                     if constexpr (MODEL == ND_KURAMOTO) {
-                        if (stage == 1 && g == d.mv_start) d.mv[i] = y[i];
+                        if (stage == 1 && g == d.mv_start) d.mv[i] = yv[e][0];
                     } else {
                         if (stage == 4) {
-                            const double uo = y[i], vo = y[n + i];
+                            const double uo = yv[e][0], vo = yv[e][1];
                             const double un = zn[0], vn = zn[1];
                             const double dth = atan2(uo * vn - vo * un, uo * un + vo * vn);
                             d.mv[i] = (g == d.mv_start ? 0.0 : d.mv[i]) + dth;
@@ -312,8 +267,6 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                     }
                 }
             }
-            run0 += dl[e][0];
-            run1 += dl[e][1];
         }
         block_sum<BS, 4>(nx, lds);
         if (tid == 0) {
@@ -377,7 +330,14 @@ template <int MODEL, class KT, int BS, int EPT>
 static RingLaunch ring_entry() {
     RingLaunch r;
     r.prologue = k_ring_prologue<MODEL, KT, BS, EPT>;
-    r.stage = k_ring_stage<MODEL, KT, BS, EPT>;
+    r.stage[0] = k_ring_stage<MODEL, KT, BS, EPT, 1, false>;
+    r.stage[1] = k_ring_stage<MODEL, KT, BS, EPT, 2, false>;
+    r.stage[2] = k_ring_stage<MODEL, KT, BS, EPT, 3, false>;
+    r.stage[3] = k_ring_stage<MODEL, KT, BS, EPT, 4, false>;
+    r.stage_mv[0] = k_ring_stage<MODEL, KT, BS, EPT, 1, true>;
+    r.stage_mv[1] = k_ring_stage<MODEL, KT, BS, EPT, 2, true>;
+    r.stage_mv[2] = k_ring_stage<MODEL, KT, BS, EPT, 3, true>;
+    r.stage_mv[3] = k_ring_stage<MODEL, KT, BS, EPT, 4, true>;
     r.epilogue = k_ring_epilogue<MODEL, KT, BS, EPT>;
     r.bs = BS;
     r.tile = BS * EPT;
@@ -391,6 +351,7 @@ static bool ring_pick(int tile, RingLaunch* out) {
         case 2048: *out = ring_entry<MODEL, KT, 256, 8>(); return true;
         case 4096: *out = ring_entry<MODEL, KT, 512, 8>(); return true;
         case 512: *out = ring_entry<MODEL, KT, 128, 4>(); return true;
+        case 256: *out = ring_entry<MODEL, KT, 64, 4>(); return true;
         default: return false;
     }
 }
@@ -409,8 +370,9 @@ hipError_t ring_launch_prologue(const RingLaunch& L, int grid, hipStream_t s, Ne
     return hipGetLastError();
 }
 hipError_t ring_launch_stage(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
-                             const int* nwork, int stage, int j) {
-    hipLaunchKernelGGL(L.stage, dim3(grid), dim3(L.bs), 0, s, D, work, nwork, stage, j);
+                             const int* nwork, int stage, int j, bool mv) {
+    hipLaunchKernelGGL(mv ? L.stage_mv[stage - 1] : L.stage[stage - 1], dim3(grid), dim3(L.bs), 0, s, D, work,
+                       nwork, j);
     return hipGetLastError();
 }
 hipError_t ring_launch_epilogue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,

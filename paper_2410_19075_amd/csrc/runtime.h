@@ -17,6 +17,7 @@ nd_status hip_fail(hipError_t e, const char* what);
 int nvars_of(int model);
 nd_status validate_problem(const nd_problem* p);
 nd_kernel_config default_config(const nd_problem* p);
+int ring_block(int tile);
 int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c);
 
 // A network handle (nd_handle).
@@ -39,6 +40,7 @@ struct Net {
     ~Net();
     nd_status alloc(void** ptr, size_t bytes);
     nd_status create(const nd_problem* p);
+    nd_status apply_config(const nd_kernel_config& c);
     int64_t work_items() const;
     void append_work(int desc_index, std::vector<int2>& wk) const;
     nd_status prepare_observe(int64_t steps, const nd_observe* obs);
@@ -48,6 +50,8 @@ struct Net {
 // Networks of one kernel class launched together.
 struct Group {
     int model, topo, prec, tile;
+    int tile_y, h;  // cube: y tile extent and half-width (kernel shape)
+    bool mv;        // some network records the mean phase velocity
     int ndesc;
     int grid;
     NetDesc* desc;  // device
@@ -62,7 +66,8 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
 // ring kernels (ring.hip)
 struct RingLaunch {
     void (*prologue)(const NetDesc*, const int2*, const int*);
-    void (*stage)(const NetDesc*, const int2*, const int*, int, int);
+    void (*stage[4])(const NetDesc*, const int2*, const int*, int);
+    void (*stage_mv[4])(const NetDesc*, const int2*, const int*, int);  // with mean-velocity recording
     void (*epilogue)(const NetDesc*, const int2*, const int*, int);
     int bs, tile;
 };
@@ -70,8 +75,34 @@ bool ring_select(int model, int prec, int tile, RingLaunch* out);
 hipError_t ring_launch_prologue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                 const int* nwork);
 hipError_t ring_launch_stage(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
-                             const int* nwork, int stage, int j);
+                             const int* nwork, int stage, int j, bool mv);
 hipError_t ring_launch_epilogue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                 const int* nwork, int chunk);
+
+// cube kernels (cube.hip)
+struct CubeLaunch {
+    void (*stage[4])(const NetDesc*, const int2*, const int*, int);
+    void (*stage_mv[4])(const NetDesc*, const int2*, const int*, int);
+    void (*final_partials)(const NetDesc*, const int2*, const int*, int);
+    void (*final_R)(const NetDesc*, const int2*, const int*, int);
+};
+bool cube_select(int prec, int h, CubeLaunch* out);
+size_t cube_smem_bytes(int h, int cx, int cy);
+int cube_block(int h, int cx, int cy);
+hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,
+                             const int2* work, const int* nwork, int stage, int j, bool mv);
+hipError_t cube_launch_final(const CubeLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                             const int* nwork, int chunk);
+
+// CSR kernels (csr.hip): work items of 256 target rows
+struct CsrLaunch {
+    void (*stage[4])(const NetDesc*, const int2*, const int*, int);
+    void (*prologue)(const NetDesc*, const int2*, const int*);
+};
+bool csr_select(int prec, int lanes, CsrLaunch* out);
+hipError_t csr_launch_prologue(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                               const int* nwork);
+hipError_t csr_launch_stage(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                            const int* nwork, int stage, int j);
 
 }  // namespace nd

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -105,17 +106,29 @@ nd_kernel_config default_config(const nd_problem* p) {
     c.grid = 0;
     c.chunk = 64;
     if (p->topo == ND_RING) {
-        c.tile = p->n <= (int64_t(1) << 16) ? 1024 : (p->n <= (int64_t(1) << 20) ? 2048 : 4096);
-        c.block = c.tile == 4096 ? 512 : (c.tile == 512 ? 128 : 256);
+        c.tile = p->n <= (int64_t(1) << 16) ? 512 : (p->n <= (int64_t(1) << 20) ? 1024 : 2048);
+        c.block = ring_block(c.tile);
     } else if (p->topo == ND_CUBE3D) {
-        c.tile = 16;
-        c.block = 256;
+        // 20 x 20 outputs per plane (28 x 28 halo columns at h = 4) and 40-plane
+        // z runs: ~500 work items on a 200^3 lattice
+        const int h = (int)p->radius;
+        int cx = (int)std::min<int64_t>(20, p->n1), cy = (int)std::min<int64_t>(20, p->n2);
+        while ((cx + 2 * h) * (cy + 2 * h) > 1024) {
+            if (cx >= cy) --cx; else --cy;
+        }
+        c.tile = cx;
+        c.tile_y = cy;
+        c.tile_z = (int)std::min<int64_t>(40, p->n3);
+        c.block = cube_block(h, cx, cy);
     } else {
-        c.tile = 16;
+        c.tile = 256;    // target rows per work item
+        c.tile_y = 16;   // lanes per row
         c.block = 256;
     }
     return c;
 }
+
+int ring_block(int tile) { return tile == 4096 ? 512 : (tile == 512 ? 128 : (tile == 256 ? 64 : 256)); }
 
 static int64_t bulk_bytes(int prec) { return prec == ND_FP64 ? 8 : 4; }
 
@@ -125,6 +138,9 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
     const int64_t V = nvars_of(p->model), n = p->n, kb = bulk_bytes(p->precision);
     int64_t b = 3 * V * n * 8 + 3 * V * n * kb;  // y[2], acc, k[3]
     if (p->topo == ND_RING) b += 3 * 2 * ring_tiles(n, c.tile) * 8;
+    if (p->topo == ND_CUBE3D)
+        b += 3 * 2 * 8 * ((p->n1 + c.tile - 1) / c.tile) * ((p->n2 + c.tile_y - 1) / c.tile_y) *
+             ((p->n3 + c.tile_z - 1) / c.tile_z);
     if (p->topo == ND_CSR) b += (n + 1) * 8 + p->nnz * (4 + kb) + n * 8 + 2 * n * kb;
     b += sizeof(NetDesc) + 64;
     return b;
@@ -189,13 +205,6 @@ nd_status Net::create(const nd_problem* pr) {
     if ((s = alloc((void**)&d.acc, V * n * 8))) return s;
     for (int b = 0; b < 3; ++b)
         if ((s = alloc(&d.k[b], V * n * kb))) return s;
-    if (pr->topo == ND_RING) {
-        d.tile = cfg.tile;
-        d.G = (int32_t)ring_tiles(n, cfg.tile);
-        for (int b = 0; b < 2; ++b)
-            if ((s = alloc((void**)&d.tsum[b], 2 * d.G * 8))) return s;
-        if ((s = alloc((void**)&d.rsum, 2 * d.G * 8))) return s;
-    }
     if (pr->topo == ND_CSR) {
         if ((s = alloc((void**)&d.row_ptr, (n + 1) * 8))) return s;
         if ((s = alloc((void**)&d.col, std::max<int64_t>(pr->nnz, 1) * 4))) return s;
@@ -216,23 +225,63 @@ nd_status Net::create(const nd_problem* pr) {
         }
         HIPC(hipMemcpy((void*)d.iapp, pr->per_elem, n * 8, hipMemcpyHostToDevice));
     }
-    // single-network launch arrays (descriptor, work map, counts)
-    const int64_t nwork = work_items();
     if ((s = alloc((void**)&solo_desc, sizeof(NetDesc)))) return s;
-    if ((s = alloc((void**)&solo_work, nwork * sizeof(int2)))) return s;
     if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
+    return apply_config(cfg);
+}
+
+// (Re)build everything that depends on the kernel configuration: the work
+// decomposition, the per-work-item sum buffers and the single-network work map.
+nd_status Net::apply_config(const nd_kernel_config& c) {
+    (void)hipDeviceSynchronize();
+    auto release = [&](void*& q) {
+        if (!q) return;
+        (void)hipFree(q);
+        allocs.erase(std::find(allocs.begin(), allocs.end(), q));
+        q = nullptr;
+    };
+    release((void*&)tmpl.tsum[0]);
+    release((void*&)tmpl.tsum[1]);
+    release((void*&)tmpl.rsum);
+    release((void*&)solo_work);
+    cfg = c;
+    const int64_t n = prob.n;
+    if (prob.topo == ND_RING) {
+        cfg.block = ring_block(cfg.tile);
+        tmpl.tile = cfg.tile;
+        tmpl.G = (int32_t)ring_tiles(n, cfg.tile);
+    } else if (prob.topo == ND_CUBE3D) {
+        const int h = (int)prob.radius;
+        cfg.block = cube_block(h, cfg.tile, cfg.tile_y);
+        tmpl.cx = cfg.tile;
+        tmpl.cy = cfg.tile_y;
+        tmpl.cz = cfg.tile_z;
+        tmpl.gx = (int32_t)((prob.n1 + cfg.tile - 1) / cfg.tile);
+        tmpl.gy = (int32_t)((prob.n2 + cfg.tile_y - 1) / cfg.tile_y);
+        const int32_t gz = (int32_t)((prob.n3 + cfg.tile_z - 1) / cfg.tile_z);
+        tmpl.G = tmpl.gx * tmpl.gy * gz;
+    } else {
+        cfg.block = 256;
+        cfg.tile = 256;  // rows per work item (fixed by the kernel)
+        tmpl.tile = 256;
+        tmpl.G = (int32_t)((n + 255) / 256);
+    }
+    nd_status s;
+    if (prob.topo != ND_CSR) {
+        for (int b = 0; b < 2; ++b)
+            if ((s = alloc((void**)&tmpl.tsum[b], 2 * (int64_t)tmpl.G * 8))) return s;
+        if ((s = alloc((void**)&tmpl.rsum, 2 * (int64_t)tmpl.G * 8))) return s;
+    }
     std::vector<int2> wk;
     append_work(0, wk);
+    if ((s = alloc((void**)&solo_work, wk.size() * sizeof(int2)))) return s;
     HIPC(hipMemcpy(solo_work, wk.data(), wk.size() * sizeof(int2), hipMemcpyHostToDevice));
     int cnt[2] = {(int)wk.size(), 1};
     HIPC(hipMemcpy(solo_count, cnt, sizeof cnt, hipMemcpyHostToDevice));
     return ND_OK;
 }
 
-int64_t Net::work_items() const {
-    if (prob.topo == ND_RING) return tmpl.G;
-    return 1;
-}
+int64_t Net::work_items() const { return tmpl.G; }
 
 void Net::append_work(int desc_index, std::vector<int2>& wk) const {
     const int64_t m = work_items();
@@ -312,15 +361,64 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
         if ((e = ring_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess) return hip_fail(e, "ring prologue");
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
-                if ((e = ring_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j)) != hipSuccess)
+                if ((e = ring_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
                     return hip_fail(e, "ring stage");
         if ((e = ring_launch_epilogue(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "ring epilogue");
+    } else if (g.topo == ND_CUBE3D) {
+        CubeLaunch L;
+        if (!cube_select(g.prec, g.h, &L)) return fail(ND_ERR_UNSUPPORTED, "no cube kernel for h = %d", g.h);
+        const int block = cube_block(g.h, g.tile, g.tile_y);
+        const size_t smem = cube_smem_bytes(g.h, g.tile, g.tile_y);
+        for (int j = 0; j < chunk; ++j)
+            for (int s = 1; s <= 4; ++s)
+                if ((e = cube_launch_stage(L, grid, block, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
+                    return hip_fail(e, "cube stage");
+        if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
+            return hip_fail(e, "cube final");
     } else {
-        return fail(ND_ERR_UNSUPPORTED, "topology %d not supported yet", g.topo);
+        CsrLaunch L;
+        if (!csr_select(g.prec, g.tile_y, &L)) return fail(ND_ERR_UNSUPPORTED, "no CSR kernel for %d lanes", g.tile_y);
+        if ((e = csr_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess) return hip_fail(e, "csr prologue");
+        for (int j = 0; j < chunk; ++j)
+            for (int s = 1; s <= 4; ++s)
+                if ((e = csr_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j)) != hipSuccess)
+                    return hip_fail(e, "csr stage");
     }
     hipLaunchKernelGGL(k_advance, dim3((g.ndesc + 255) / 256), dim3(256), 0, st, g.desc, g.ndesc, chunk);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "advance");
+    return ND_OK;
+}
+
+bool graphs_enabled() {
+    static const bool on = [] {
+        const char* v = getenv("ND_GRAPHS");
+        return !(v && v[0] == '0');
+    }();
+    return on;
+}
+
+// Capture one chunk of K steps of group g into an executable graph.
+nd_status capture_chunk(const Group& g, int K, hipGraphExec_t* out) {
+    hipStream_t cap;
+    HIPC(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    nd_status s = enqueue_chunk(g, K, cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    if (s) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     return ND_OK;
 }
 
@@ -339,11 +437,13 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
     for (int i = 0; i < count; ++i)
         if ((s = nets[i]->prepare_observe(steps[i], obs ? &obs[i] : nullptr))) return s;
     // group by kernel class
-    std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const Net* n = nets[i];
-        groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile)].push_back(i);
+        const int h = n->prob.topo == ND_CUBE3D ? (int)n->prob.radius : 0;
+        groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h)]
+            .push_back(i);
     }
     for (auto& kv : groups) {
         const std::vector<int>& idx = kv.second;
@@ -352,13 +452,17 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         g.topo = std::get<1>(kv.first);
         g.prec = std::get<2>(kv.first);
         g.tile = std::get<3>(kv.first);
+        g.tile_y = std::get<4>(kv.first);
+        g.h = std::get<5>(kv.first);
         g.ndesc = (int)idx.size();
         int64_t maxsteps = 0;
         std::vector<NetDesc> descs;
         std::vector<int2> work;
+        g.mv = false;
         for (int q = 0; q < (int)idx.size(); ++q) {
             Net* n = nets[idx[q]];
             descs.push_back(n->run_desc(dt[idx[q]], steps[idx[q]]));
+            g.mv = g.mv || n->mv_start >= 0;
             n->append_work(q, work);
             maxsteps = std::max(maxsteps, steps[idx[q]]);
         }
@@ -380,10 +484,26 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
             HIPC(hipMemcpyAsync(g.nwork, &nw, sizeof nw, hipMemcpyHostToDevice, st));
         }
         HIPC(hipMemcpyAsync(g.desc, descs.data(), descs.size() * sizeof(NetDesc), hipMemcpyHostToDevice, st));
-        const int cfg_grid = nets[idx[0]]->cfg.grid;
+        const Net* n0 = nets[idx[0]];
+        const int cfg_grid = n0->cfg.grid;
         g.grid = cfg_grid > 0 ? std::min<int>(cfg_grid, (int)work.size()) : (int)work.size();
-        const int chunk = (int)std::min<int64_t>(maxsteps, 1 << 30);
-        if ((s = enqueue_chunk(g, chunk, st))) return s;
+        const int K = std::max(1, n0->cfg.chunk);
+        if (maxsteps <= K || !graphs_enabled()) {
+            // one eager chunk covering every network's steps
+            if ((s = enqueue_chunk(g, (int)std::min<int64_t>(maxsteps, 1 << 30), st))) return s;
+        } else {
+            // capture one K-step chunk and replay it; the descriptors advance on
+            // the device, so every replay continues where the last one stopped
+            hipGraphExec_t exec = nullptr;
+            if ((s = capture_chunk(g, K, &exec))) return s;
+            const int64_t reps = (maxsteps + K - 1) / K;
+            hipError_t e = hipSuccess;
+            for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, st);
+            hipError_t e2 = hipStreamSynchronize(st);
+            (void)hipGraphExecDestroy(exec);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+        }
         if (scratch) HIPC(hipFreeAsync(scratch, st));
         // pageable sources of the async copies above must stay alive until consumed
         HIPC(hipStreamSynchronize(st));
@@ -500,11 +620,27 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
     Net* n = as_net(h);
     if (!n || !cfg) return fail(ND_ERR_INVALID_ARG, "NULL argument");
     if (cfg->grid < 0 || cfg->chunk < 1) return fail(ND_ERR_INVALID_ARG, "grid must be >= 0 and chunk >= 1");
-    if (n->prob.topo == ND_RING && cfg->tile != n->cfg.tile)
-        return fail(ND_ERR_INVALID_ARG, "the ring tile is fixed at nd_create (tiles size the buffers)");
-    n->cfg.grid = cfg->grid;
-    n->cfg.chunk = cfg->chunk;
-    return ND_OK;
+    nd_kernel_config c = *cfg;
+    const nd_problem& p = n->prob;
+    if (p.topo == ND_RING) {
+        RingLaunch L;
+        if (!ring_select(p.model, p.precision, c.tile, &L))
+            return fail(ND_ERR_INVALID_ARG, "no ring kernel for tile %d", c.tile);
+    } else if (p.topo == ND_CUBE3D) {
+        const int h = (int)p.radius;
+        if (c.tile < 1 || c.tile_y < 1 || c.tile_z < 1)
+            return fail(ND_ERR_INVALID_ARG, "cube tile extents must be >= 1");
+        c.tile = (int32_t)std::min<int64_t>(c.tile, p.n1);
+        c.tile_y = (int32_t)std::min<int64_t>(c.tile_y, p.n2);
+        c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
+        if ((c.tile + 2 * h) * (c.tile_y + 2 * h) > 1024)
+            return fail(ND_ERR_INVALID_ARG, "cube tile: (tile+2h)*(tile_y+2h) must be <= 1024");
+    } else {
+        if (c.tile != 256) return fail(ND_ERR_INVALID_ARG, "CSR work items hold 256 rows (tile must be 256)");
+        if (c.tile_y < 4 || c.tile_y > 64 || (c.tile_y & (c.tile_y - 1)))
+            return fail(ND_ERR_INVALID_ARG, "CSR lanes per row must be a power of two in [4, 64]");
+    }
+    return n->apply_config(c);
 }
 
 const char* nd_status_str(nd_status s) {

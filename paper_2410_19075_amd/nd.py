@@ -38,7 +38,8 @@ class nd_observe(ctypes.Structure):
 
 
 class nd_kernel_config(ctypes.Structure):
-    _fields_ = [("tile", _c_i32), ("block", _c_i32), ("grid", _c_i32), ("chunk", _c_i32)]
+    _fields_ = [("tile", _c_i32), ("block", _c_i32), ("grid", _c_i32), ("chunk", _c_i32), ("tile_y", _c_i32),
+                ("tile_z", _c_i32)]
 
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnd.so")

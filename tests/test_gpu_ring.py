@@ -34,6 +34,30 @@ def ring_case(nd, model, n, P, params, prec, y0, dt, steps, record_every=0, mv=-
     return nd.simulate(p, y0, dt, steps, record_every=record_every, mv_start_step=mv)
 
 
+def run_with_config(nd, p, y0, dt, steps, tile=None, grid=None, chunk=None, record_every=0):
+    h = nd.nd_create(p)
+    try:
+        c = nd.nd_get_config(h)
+        if tile:
+            c.tile = tile
+        if grid is not None:
+            c.grid = grid
+        if chunk:
+            c.chunk = chunk
+        nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, dt, steps, nd.observe(record_every, -1))
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+        R = None
+        if record_every:
+            R = np.empty(steps // record_every + 1)
+            nd.nd_get_observables(h, R=R, on_device=0)
+        return y, R
+    finally:
+        nd.nd_destroy(h)
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_c1_kuramoto_ring_fp64_parity(nd, seed):
     """Kuramoto ring N=1024, P=256, alpha=1.46, dt=0.01, 200 steps, FP64: final
@@ -172,3 +196,18 @@ def test_batch_equals_solo_bitwise(nd):
     finally:
         for h in hs:
             nd.nd_destroy(h)
+
+
+@pytest.mark.parametrize("tile", [512, 1024, 2048, 4096])
+@pytest.mark.parametrize("grid,chunk", [(0, 64), (24, 16), (8, 5)])
+def test_tile_grid_and_chunk_configs(nd, tile, grid, chunk):
+    """Every tile size, persistent grids smaller than the work and graph chunks
+    that do not divide the step count give the oracle's result."""
+    n, P = 9001, 3150
+    y0 = inputs.fhn_circle(11, n)
+    print(f"case cfg tile={tile} grid={grid} chunk={chunk}", flush=True)
+    p = nd.problem(nd.ND_FHN, nd.ND_RING, n, FHN_PRM, radius=P)
+    y, R = run_with_config(nd, p, y0, 0.01, 37, tile=tile, grid=grid, chunk=chunk, record_every=4)
+    ref, Rref, _ = O.run(O.ring(O.FHN, n, P, FHN_PRM), y0, 0.01, 37, record_every=4)
+    assert normwise(y, ref, 2) < 1e-12
+    assert np.max(np.abs(R - Rref)) < 1e-12
