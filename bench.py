@@ -1,14 +1,24 @@
 """Throughput benchmark of the network-dynamics hot path on one MI355X.
 
-Default workload: FitzHugh-Nagumo rings of N = 65536 elements, coupling radius
-P = floor(0.35 N) = 22937, eps = 0.05, a = 0.5, sigma = 0.1, phi = pi/2 - 0.1,
-initial (u, v) on the circle of radius 2 at seeded random angles, classical RK4
-with dt = 0.01 over a horizon of 10^4 steps.  One benchmark step integrates a
-batch of B such rings (distinct seeds) over the full horizon with one batched
-launch sequence; `value` is the aggregate oscillator-steps per second in FP64,
-the FP32-bulk figure is reported beside it.  Inputs are synthetic and resident
-on the GPU before timing starts.
+Default workload (--workload fhn): FitzHugh-Nagumo rings of N = 65536 elements,
+coupling radius P = floor(0.35 N) = 22937, eps = 0.05, a = 0.5, sigma = 0.1,
+phi = pi/2 - 0.1, initial (u, v) on the circle of radius 2 at seeded random
+angles, classical RK4 with dt = 0.01 over a horizon of 10^4 steps.  One
+benchmark step integrates a batch of B such rings (distinct seeds) over the
+full horizon with one batched launch sequence; `value` is the aggregate
+oscillator-steps per second in FP64, the FP32-bulk figure is reported beside it.
 
+Other workloads (one JSON line each, same fields):
+  --workload cube      3D Kuramoto-Sakaguchi, 200^3 periodic lattice, cube
+                       half-width 4 (728 neighbours), alpha = 0.8, mu = 1,
+                       dt = 0.05, 2000 steps, uniform phases plus a planted
+                       coherent ball
+  --workload hh        Hodgkin-Huxley, 10^6 neurons, random directed graph with
+                       out-degree 100, weights U[0, 0.1], I_app U[8, 12],
+                       dt = 0.01 ms, 5000 steps
+  --workload kuramoto  Kuramoto rings N = 1024, P = 256, alpha = 1.46, 200 steps
+
+Inputs are synthetic (seeded) and resident on the GPU before timing starts.
 Prints one JSON line.
 """
 import argparse
@@ -25,6 +35,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 FHN_PRM = [0.05, 0.5, 0.1, math.pi / 2 - 0.1]
+HH_PRM = [1.0, 120.0, 36.0, 0.3, 50.0, -77.0, -54.387, 0.0, 0.0, 2.0]
+
+DEFAULTS = {  # workload: (batch, horizon, dt, n)
+    "fhn": (64, 10000, 0.01, 65536),
+    "kuramoto": (4096, 200, 0.01, 1024),
+    "cube": (1, 2000, 0.05, 200),
+    "hh": (1, 5000, 0.01, 1000000),
+}
 
 
 def parse():
@@ -32,45 +50,119 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed benchmark steps")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=64, help="rings per benchmark step")
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--horizon", type=int, default=10000, help="RK4 steps per benchmark step")
+    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="fhn")
+    ap.add_argument("--batch", type=int, default=0, help="networks per benchmark step (0 = workload default)")
+    ap.add_argument("--n", type=int, default=0, help="elements (cube: edge) per network (0 = default)")
+    ap.add_argument("--horizon", type=int, default=0, help="RK4 steps per benchmark step (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
-    ap.add_argument("--tile", type=int, default=0, help="ring tile override (0 = library default)")
-    ap.add_argument("--grid", type=int, default=0, help="persistent grid override (0 = one block per tile)")
+    ap.add_argument("--tile", type=int, default=0, help="tile override (0 = library default)")
+    ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--tile-z", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0, help="persistent grid override (0 = one block per work item)")
     ap.add_argument("--chunk", type=int, default=0, help="steps per captured graph chunk (0 = default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (for scaling HBM counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    b, hz, dt, n = DEFAULTS[a.workload]
+    a.batch = a.batch or b
+    a.horizon = a.horizon or hz
+    a.n = a.n or n
+    a.dt = dt
+    return a
 
 
-def bytes_alg_per_elem_step(nvars, prec):
-    """13 state-vector accesses per element and RK4 step (no window scratch):
-    y read 4x, acc written and read, y written (doubles) and k1..k3 written and
-    read once each (bulk type)."""
-    kb = 8 if prec == "fp64" else 4
-    return nvars * (7 * 8 + 6 * kb)
+# ----------------------------------------------------------------- workloads
+class Workload:
+    """Network descriptions, synthetic inputs and per-element algorithmic bytes."""
+
+    def __init__(self, args, nd):
+        self.a, self.nd = args, nd
+        w = args.workload
+        if w == "fhn":
+            self.n, self.P = args.n, int(0.35 * args.n)
+            self.nvars, self.links = 2, 2 * self.P
+            self.name = (f"FitzHugh-Nagumo ring N={self.n} P={self.P} (0.35N), eps=0.05 a=0.5 sigma=0.1 "
+                         f"phi=pi/2-0.1, RK4 dt=0.01, {args.horizon} steps per ring, {args.batch} rings "
+                         f"(seeds 1000..) per benchmark step")
+            self.kernel = "k_ring_stage<FHN>"
+        elif w == "kuramoto":
+            self.n, self.P = args.n, args.n // 4
+            self.nvars, self.links = 1, 2 * self.P
+            self.name = (f"Kuramoto-Sakaguchi ring N={self.n} P={self.P}, alpha=1.46 mu=1 omega=0, RK4 dt=0.01, "
+                         f"{args.horizon} steps, {args.batch} rings per benchmark step")
+            self.kernel = "k_ring_stage<Kuramoto>"
+        elif w == "cube":
+            self.n1 = args.n
+            self.n, self.P = args.n ** 3, 4
+            self.nvars, self.links = 1, 728
+            self.name = (f"Kuramoto-Sakaguchi 3D lattice {args.n}^3 periodic, cube half-width 4 (728 neighbours), "
+                         f"alpha=0.8 mu=1 omega=0, RK4 dt=0.05, {args.horizon} steps, planted coherent ball")
+            self.kernel = "k_cube_stage"
+        else:
+            self.n = args.n
+            self.nvars, self.links = 4, 100
+            self.name = (f"Hodgkin-Huxley N={self.n}, random directed graph out-degree 100 (nnz={self.n * 100}), "
+                         f"w U[0,0.1], I_app U[8,12], RK4 dt=0.01 ms, {args.horizon} steps")
+            self.kernel = "k_csr_stage"
+            from paper_2410_19075_amd import inputs
+            self.graph = inputs.random_out_graph(1, self.n, 100)
+            self.iapp = inputs.hh_iapp(1, self.n)
+
+    def problem(self, prec):
+        nd, w = self.nd, self.a.workload
+        if w == "fhn":
+            return nd.problem(nd.ND_FHN, nd.ND_RING, self.n, FHN_PRM, precision=prec, radius=self.P)
+        if w == "kuramoto":
+            return nd.problem(nd.ND_KURAMOTO, nd.ND_RING, self.n, [0.0, 1.0, 1.46], precision=prec, radius=self.P)
+        if w == "cube":
+            return nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, self.n, [0.0, 1.0, 0.8], precision=prec, radius=4,
+                              dims=(self.n1,) * 3)
+        rp, col, wt = self.graph
+        return nd.problem(nd.ND_HH, nd.ND_CSR, self.n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=wt,
+                          per_elem=self.iapp)
+
+    def state(self, b):
+        from paper_2410_19075_amd import inputs
+        w = self.a.workload
+        if w == "fhn":
+            return inputs.fhn_circle(1000 + b, self.n)
+        if w == "kuramoto":
+            return inputs.kuramoto_phases(1000 + b, self.n)
+        if w == "cube":
+            return inputs.cube_phases_with_patch(1000 + b, self.n1)
+        return inputs.hh_state(1000 + b, self.n)
+
+    def bytes_alg_per_elem_step(self, prec):
+        """13 state-vector accesses per element and RK4 step (no scratch): y read
+        4x, acc written and read, y written (doubles), k1..k3 written and read
+        once each (bulk type); the CSR path adds its edge stream (col + w) once
+        per stage."""
+        kb = 8 if prec == 0 else 4
+        b = self.nvars * (7 * 8 + 6 * kb)
+        if self.a.workload == "hh":
+            b += 4 * self.links * (4 + kb)
+        return b
 
 
-def run_fhn(nd, torch, args, prec_code, stream):
-    n, P = args.n, int(0.35 * args.n)
-    from paper_2410_19075_amd import inputs
+def run(nd, torch, wl, args, prec, stream):
     hs = []
     for b in range(args.batch):
-        h = nd.nd_create(nd.problem(nd.ND_FHN, nd.ND_RING, n, FHN_PRM, precision=prec_code, radius=P))
-        if args.tile or args.grid or args.chunk:
+        h = nd.nd_create(wl.problem(prec))
+        if args.tile or args.grid or args.chunk or args.tile_y or args.tile_z:
             c = nd.nd_get_config(h)
             c.tile = args.tile or c.tile
+            c.tile_y = args.tile_y or c.tile_y
+            c.tile_z = args.tile_z or c.tile_z
             c.grid = args.grid or c.grid
             c.chunk = args.chunk or c.chunk
             nd.nd_set_config(h, c)
-        y0 = torch.from_numpy(inputs.fhn_circle(1000 + b, n)).cuda()
+        y0 = torch.from_numpy(wl.state(b)).cuda()
         nd.nd_set_state(h, y0, stream=stream)
         hs.append(h)
     torch.cuda.synchronize()
-    dts = [0.01] * len(hs)
+    dts = [args.dt] * len(hs)
     steps = [args.horizon] * len(hs)
 
     def one():
@@ -94,29 +186,51 @@ def run_fhn(nd, torch, args, prec_code, stream):
         ev_total += ev0.elapsed_time(ev1) / 1e3
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    y = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    y = torch.empty(wl.nvars * wl.n, dtype=torch.float64, device="cuda")
     nd.nd_get_state(hs[0], y, stream=stream)
     torch.cuda.synchronize()
     finite = bool(torch.isfinite(y).all().item())
+    cfg = nd.nd_get_config(hs[0])
+    cfgd = {k: getattr(cfg, k) for k, _ in cfg._fields_}
     for h in hs:
         nd.nd_destroy(h)
-    return wall, times, ev_total, finite
+    return wall, times, ev_total, finite, cfgd
 
 
-def cpu_baseline(args):
+def cpu_baseline(wl, args):
+    """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
     from oracle import oracle as O
-    from paper_2410_19075_amd import inputs
-    n, P = args.n, int(0.35 * args.n)
-    y0 = inputs.fhn_circle(1000, n)
-    net = O.ring(O.FHN, n, P, FHN_PRM)
     O.lib()
+    y0 = wl.state(0)
+    w = args.workload
+    if w == "fhn":
+        net, steps, what = O.ring(O.FHN, wl.n, wl.P, FHN_PRM), args.cpu_sample_steps, f"one FHN ring N={wl.n} P={wl.P}"
+    elif w == "kuramoto":
+        net, steps, what = O.ring(O.KURAMOTO, wl.n, wl.P, [0.0, 1.0, 1.46]), 200, f"one Kuramoto ring N={wl.n}"
+    elif w == "cube":
+        net, steps, what = O.cube(wl.n1, 4, [0.0, 1.0, 0.8]), 1, f"the {wl.n1}^3 lattice, h=4"
+    else:
+        rp, col, wt = wl.graph
+        net, steps, what = O.csr(wl.n, rp, col, wt, HH_PRM, wl.iapp), args.cpu_sample_steps, f"HH N={wl.n} deg 100"
     t0 = time.perf_counter()
-    O.run(net, y0, 0.01, args.cpu_sample_steps)
+    O.run(net, y0, args.dt, steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n * args.cpu_sample_steps / dt, "unit": "oscillator-steps/s", "cores": cores,
-            "kind": "oracle", "sample": f"one FHN ring N={n} P={P}, {args.cpu_sample_steps} RK4 step(s), FP64, "
-                                        f"direct neighbour sums, {dt:.2f} s"}
+    return {"value": wl.n * steps / dt, "unit": "oscillator-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{what}, {steps} RK4 step(s), FP64, direct neighbour sums, {dt:.2f} s"}
+
+
+def roofline(wl, args, prec, ev_total):
+    """Algorithmic bytes of one stage launch over the measured average stage time
+    (HIP events on the launch stream; the chunk's few small bookkeeping kernels
+    are included, so the stage time is an upper bound)."""
+    n_stage = 4 * args.horizon * args.steps
+    stage_s = ev_total / n_stage
+    per_launch = args.batch * wl.n * wl.bytes_alg_per_elem_step(prec) / 4.0
+    achieved = per_launch / stage_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": wl.kernel,
+            "bytes_per_launch": per_launch, "avg_launch_us": stage_s * 1e6}
 
 
 def main():
@@ -135,21 +249,22 @@ def main():
         nbytes = args.copy_calibration
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
         for _ in range(3):
             dst.copy_(src)
+        ev1.record(stream)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}))
+        sec = ev0.elapsed_time(ev1) / 1e3 / 3
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 4, "copy_GBps": 2 * nbytes / sec / 1e9}))
         return
-    n, P = args.n, int(0.35 * args.n)
-    osc_per_step = args.batch * n * args.horizon
-
-    wall, times, ev_total, finite = run_fhn(nd, torch, args, nd.ND_FP64, stream)
+    wl = Workload(args, nd)
+    osc_per_step = args.batch * wl.n * args.horizon
+    wall, times, ev_total, finite, cfg = run(nd, torch, wl, args, nd.ND_FP64, stream)
     value = osc_per_step * args.steps / wall
-    n_stage = 4 * args.horizon * args.steps
-    stage_s = ev_total / n_stage
-    balg64 = bytes_alg_per_elem_step(2, "fp64")
-    per_launch = args.batch * n * balg64 / 4.0
-    achieved = per_launch / stage_s / 1e9
     out = {
         "metric": "oscillator-steps/s",
         "value": value,
@@ -163,31 +278,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FitzHugh-Nagumo ring N={n} P={P} (0.35N), eps=0.05 a=0.5 sigma=0.1 "
-                               f"phi=pi/2-0.1, RK4 dt=0.01, {args.horizon} steps per ring, {args.batch} rings "
-                               f"(seeds 1000..) per benchmark step",
-                   "global_batch": args.batch, "seq_len": args.horizon, "parallelism": "single-gpu"},
-        "coupling_terms_per_s": value * 2 * P * 4,
+        "config": {"workload": wl.name, "global_batch": args.batch, "seq_len": args.horizon,
+                   "parallelism": "single-gpu", "kernel_config": cfg},
+        "coupling_terms_per_s": value * wl.links * 4,
         "batch_latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
                              "p99": 1e3 * float(np.percentile(times, 99))},
         "state_finite": finite,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_ring_stage<FHN,double>", "bytes_per_launch": per_launch,
-                     "avg_launch_us": stage_s * 1e6},
+        "roofline": roofline(wl, args, 0, ev_total),
     }
     if not args.no_fp32:
-        wall32, times32, ev32, fin32 = run_fhn(nd, torch, args, nd.ND_FP32_BULK, stream)
+        wall32, times32, ev32, fin32, _ = run(nd, torch, wl, args, nd.ND_FP32_BULK, stream)
         v32 = osc_per_step * args.steps / wall32
-        s32 = ev32 / n_stage
-        pl32 = args.batch * n * bytes_alg_per_elem_step(2, "fp32") / 4.0
         out["fp32_bulk"] = {"value": v32, "unit": "oscillator-steps/s", "ms_per_step": 1e3 * wall32 / args.steps,
-                            "roofline": {"bound": "hbm", "achieved": pl32 / s32 / 1e9, "peak": HBM_PEAK_GBS,
-                                         "unit": "GB/s", "frac": pl32 / s32 / 1e9 / HBM_PEAK_GBS,
-                                         "avg_launch_us": s32 * 1e6},
-                            "state_finite": fin32}
+                            "coupling_terms_per_s": v32 * wl.links * 4,
+                            "roofline": roofline(wl, args, 1, ev32), "state_finite": fin32}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+        out["cpu_baseline"] = cpu_baseline(wl, args)
     print(json.dumps(out), flush=True)
 
 

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_csr_prologue(const NetDesc* __restrict_
         const NetDesc& d = D[wk.x];
         if (d.g0 != 0 || d.nsteps <= 0) continue;
         const int64_t i = (int64_t)wk.y * kCsrRows + threadIdx.x;
-        if (i < d.n) ((KT*)d.sx[0])[i] = (KT)synapse<KT>(d.p, d.y[d.ypar][i]);
+        if (i < d.n) gp((KT*)d.sx[0])[i] = (KT)synapse<KT>(d.p, gp(d.y[d.ypar])[i]);
     }
 }
 
@@ -90,13 +90,15 @@ __global__ __launch_bounds__(256) void k_csr_stage(const NetDesc* __restrict__ D
         const int64_t r0 = (int64_t)wk.y * kCsrRows;
         const int nrows = (int)min((int64_t)kCsrRows, n - r0);
         const int par = (d.ypar + j) & 1;
-        const double* __restrict__ y = d.y[par];
-        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage > 1 ? stage - 2 : 0];
-        const KT* __restrict__ sin_ = (const KT*)d.sx[(stage - 1) & 1];
-        KT* __restrict__ sout = (KT*)d.sx[stage & 1];
-        const int64_t* __restrict__ rp = d.row_ptr;
-        const int32_t* __restrict__ col = d.col;
-        const KT* __restrict__ wt = (const KT*)d.w;
+        const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
+        const ND_GLOBAL KT* __restrict__ kp =
+            stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
+        const ND_GLOBAL KT* __restrict__ sin_ = gp((const KT*)d.sx[(stage - 1) & 1]);
+        ND_GLOBAL KT* __restrict__ sout = gp((KT*)d.sx[stage & 1]);
+        const ND_GLOBAL int64_t* __restrict__ rp = gp(d.row_ptr);
+        const ND_GLOBAL int32_t* __restrict__ col = gp(d.col);
+        const ND_GLOBAL KT* __restrict__ wt = gp((const KT*)d.w);
+        const ND_GLOBAL double* __restrict__ accp = gp(d.acc);
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
 
@@ -133,27 +135,27 @@ __global__ __launch_bounds__(256) void k_csr_stage(const NetDesc* __restrict__ D
             }
             double k[4];
             if constexpr (sizeof(KT) == 8)
-                hh_rhs<double>(d.p, d.iapp[i], z, gsum[tid], k);
+                hh_rhs<double>(d.p, gp(d.iapp)[i], z, gsum[tid], k);
             else
-                hh_rhs<float>(d.p, d.iapp[i], z, gsum[tid], k);
+                hh_rhs<float>(d.p, gp(d.iapp)[i], z, gsum[tid], k);
             double zn[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t q = v * n + i;
                 const double kk = kq<KT>(k[v]);
                 if (stage == 1) {
-                    ((KT*)d.k[0])[q] = (KT)kk;
+                    gp((KT*)d.k[0])[q] = (KT)kk;
                     zn[v] = fma(0.5 * dt, kk, yv[v]);
                 } else if (stage == 2) {
-                    ((KT*)d.k[1])[q] = (KT)kk;
-                    d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[v], yv[v]));
+                    gp((KT*)d.k[1])[q] = (KT)kk;
+                    gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[v], yv[v]));
                     zn[v] = fma(0.5 * dt, kk, yv[v]);
                 } else if (stage == 3) {
-                    ((KT*)d.k[2])[q] = (KT)kk;
+                    gp((KT*)d.k[2])[q] = (KT)kk;
                     zn[v] = fma(dt, kk, yv[v]);
                 } else {
-                    const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[v], d.acc[q]));
-                    d.y[par ^ 1][q] = yo;
+                    const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[v], accp[q]));
+                    gp(d.y[par ^ 1])[q] = yo;
                     zn[v] = yo;
                 }
             }

@@ -78,21 +78,23 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         const int nz = min(cz, n3 - z0);
         const int64_t g = d.g0 + j;
         const int par = (d.ypar + j) & 1;
-        const double* __restrict__ y = d.y[par];
-        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage > 1 ? stage - 2 : 0];
-        const double* __restrict__ acc = d.acc;
+        const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
+        const ND_GLOBAL KT* __restrict__ kp =
+            stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
+        const ND_GLOBAL double* __restrict__ acc = gp(d.acc);
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
 
         // ---- order parameter R(g) from the stage-1 partial sums (stage 2, item 0)
         if (stage == 2 && t == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
             double s[2] = {0.0, 0.0};
+            const ND_GLOBAL double* ts = gp(d.tsum[0]);
             for (int u = tid; u < d.G; u += blockDim.x) {
-                s[0] += d.tsum[0][2 * u];
-                s[1] += d.tsum[0][2 * u + 1];
+                s[0] += ts[2 * u];
+                s[1] += ts[2 * u + 1];
             }
             block_sum_rt<2>(s, lds);
-            if (tid == 0) d.R[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
+            if (tid == 0) gp(d.R)[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
         }
 
         double2* S1 = smem;                  // [2][HY][HX] z-sums per halo column
@@ -189,17 +191,17 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         const int64_t q = obase + plane * zo;
                         const double kk = kq<KT>(k[0]);
                         if (stage == 1) {
-                            ((KT*)d.k[0])[q] = (KT)kk;
+                            gp((KT*)d.k[0])[q] = (KT)kk;
                             part[0] += xo.x;
                             part[1] += xo.y;
-                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) d.mv[q] = cry;
+                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) gp(d.mv)[q] = cry;
                         } else if (stage == 2) {
-                            ((KT*)d.k[1])[q] = (KT)kk;
-                            d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, crk, cry));
+                            gp((KT*)d.k[1])[q] = (KT)kk;
+                            gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, crk, cry));
                         } else if (stage == 3) {
-                            ((KT*)d.k[2])[q] = (KT)kk;
+                            gp((KT*)d.k[2])[q] = (KT)kk;
                         } else {
-                            d.y[par ^ 1][q] = fma(dt / 6.0, kk, fma(dt / 3.0, crk, cra));
+                            gp(d.y[par ^ 1])[q] = fma(dt / 6.0, kk, fma(dt / 3.0, crk, cra));
                         }
                     }
                 }
@@ -208,8 +210,8 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         if (stage == 1) {
             block_sum_rt<2>(part, lds);
             if (tid == 0) {
-                d.tsum[0][2 * t] = part[0];
-                d.tsum[0][2 * t + 1] = part[1];
+                gp(d.tsum[0])[2 * t] = part[0];
+                gp(d.tsum[0])[2 * t + 1] = part[1];
             }
         } else {
             __syncthreads();  // LDS reuse by the next work item

@@ -6,13 +6,6 @@
 
 namespace nd {
 
-// Barrier for exchanges through LDS only: waits for this wave's LDS traffic
-// but lets outstanding global loads stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // ------------------------------------------------------------------ models
 template <int MODEL, class KT>
@@ -96,9 +89,8 @@ __device__ __forceinline__ double kq(double k) {
 
 // Stage value z_v(idx) = y + c dt k_prev (stage 1: y).  Written once here so the
 // producer of the tile sums and every reader of the window ends agree bitwise.
-template <int V, class KT>
-__device__ __forceinline__ void stage_z(const double* __restrict__ y, const KT* __restrict__ kp, double cdt,
-                                        int64_t n, int64_t idx, double* z) {
+template <int V, class KT, class YP, class KP>
+__device__ __forceinline__ void stage_z(YP y, KP kp, double cdt, int64_t n, int64_t idx, double* z) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const double yy = y[v * n + idx];

@@ -47,6 +47,19 @@ struct NetDesc {
 
 enum : int32_t { OBS_R = 1, OBS_MV = 2 };
 
+// Buffers reached through the descriptor are generic pointers to the compiler;
+// casting them to the global address space gives global (not flat) memory
+// instructions, whose completion is tracked apart from LDS traffic.
+#define ND_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ ND_GLOBAL T* gp(T* p) {
+    return (ND_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const ND_GLOBAL T* gp(const T* p) {
+    return (const ND_GLOBAL T*)p;
+}
+
 __device__ __forceinline__ int64_t ring_wrap(int64_t i, int64_t n) {
     // valid for i in [-n, 2n)
     return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -62,6 +75,14 @@ __device__ __forceinline__ int xcd_work(int vb, int nwork) {
     const int q = nwork >> 3, r = nwork & 7;
     const int cnt = q + (x < r ? 1 : 0);
     return s < cnt ? x * q + min(x, r) + s : -1;
+}
+
+// Barrier for exchanges through LDS only: waits for this wave's LDS traffic
+// but lets outstanding global loads stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ---------------------------------------------------------------- wave/block
@@ -94,7 +115,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) lds[q * NW + wid] = v[q];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         double s = 0.0;
@@ -102,7 +123,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
         for (int w = 0; w < NW; ++w) s += lds[q * NW + w];
         v[q] = s;
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 // One pass over LDS that returns, in every thread, the block sums of NR values
@@ -129,7 +150,7 @@ __device__ __forceinline__ void block_sum_and_exscan(double (&r)[NR], double (&s
 #pragma unroll
         for (int q = 0; q < NS; ++q) lds[(NR + q) * NW + wid] = incl[q];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         double a = 0.0;
@@ -143,7 +164,7 @@ __device__ __forceinline__ void block_sum_and_exscan(double (&r)[NR], double (&s
         for (int w = 0; w < wid; ++w) a += lds[(NR + q) * NW + w];
         s[q] = a + excl[q];
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 }  // namespace nd

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(BS) void k_ring_prologue(const NetDesc* __restrict_
         if (d.g0 != 0 || d.nsteps <= 0) continue;
         const int64_t n = d.n, t0 = (int64_t)wk.y * T;
         const int cnt = (int)min((int64_t)T, n - t0);
-        const double* y = d.y[d.ypar];
+        const ND_GLOBAL double* y = gp(d.y[d.ypar]);
         double s[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(BS) void k_ring_prologue(const NetDesc* __restrict_
             const int m = e * BS + threadIdx.x;
             if (m < cnt) {
                 double z[V];
-                stage_z<V, KT>(y, (const KT*)nullptr, 0.0, n, t0 + m, z);
+                stage_z<V, KT>(y, (const ND_GLOBAL KT*)nullptr, 0.0, n, t0 + m, z);
                 const double2 x = M::map(z);
                 s[0] += x.x;
                 s[1] += x.y;
@@ -61,11 +61,11 @@ __global__ __launch_bounds__(BS) void k_ring_prologue(const NetDesc* __restrict_
         }
         block_sum<BS, 4>(s, lds);
         if (threadIdx.x == 0) {
-            d.tsum[0][2 * wk.y] = s[0];
-            d.tsum[0][2 * wk.y + 1] = s[1];
+            gp(d.tsum[0])[2 * wk.y] = s[0];
+            gp(d.tsum[0])[2 * wk.y + 1] = s[1];
             if constexpr (MODEL == ND_FHN) {
-                d.rsum[2 * wk.y] = s[2];
-                d.rsum[2 * wk.y + 1] = s[3];
+                gp(d.rsum)[2 * wk.y] = s[2];
+                gp(d.rsum)[2 * wk.y + 1] = s[3];
             }
         }
     }
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
     using M = RingModel<MODEL, KT>;
     constexpr int V = M::V, T = BS * EPT, NW = BS / kWave;
     __shared__ double2 sd[T];  // x_right - x_left, then the inclusive window sums
+    __shared__ double sy[V * T], sk[V * T];  // own y and k_prev, kept for the RK update
     __shared__ double lds[8 * NW];
     const int nwork = *nwork_p;
     const int tid = threadIdx.x;
@@ -96,22 +97,24 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         const int cnt = (int)min((int64_t)T, n - t0);
         const int64_t g = d.g0 + j;
         const int par = (d.ypar + j) & 1;
-        const double* __restrict__ y = d.y[par];
-        const KT* __restrict__ kp = stage == 1 ? nullptr : (const KT*)d.k[stage > 1 ? stage - 2 : 0];
+        const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
+        const ND_GLOBAL KT* __restrict__ kp =
+            stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
+        const ND_GLOBAL double* __restrict__ acc = gp(d.acc);
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
-        const double* __restrict__ tin = d.tsum[(stage - 1) & 1];
+        const ND_GLOBAL double* __restrict__ tin = gp(d.tsum[(stage - 1) & 1]);
 
         // ---- order parameter R(g) from the tile sums of map(y) (tile 0)
         if (stage == 1 && tile == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
-            const double* src = (MODEL == ND_FHN) ? d.rsum : tin;
+            const ND_GLOBAL double* src = (MODEL == ND_FHN) ? gp((const double*)d.rsum) : tin;
             double s[2] = {0.0, 0.0};
             for (int u = tid; u < G; u += BS) {
                 s[0] += src[2 * u];
                 s[1] += src[2 * u + 1];
             }
             block_sum<BS, 2>(s, lds);
-            if (tid == 0) d.R[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
+            if (tid == 0) gp(d.R)[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
         }
 
         // ---- geometry of the window ends [A, A+T) and [B, B+T)
@@ -145,7 +148,14 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 const int64_t io = m < cnt ? t0 + m : t0;
                 stage_z<V, KT>(y, kp, cdt, n, il, zl[e]);
                 stage_z<V, KT>(y, kp, cdt, n, ir, zr[e]);
-                stage_z<V, KT>(y, kp, cdt, n, io, zo[e]);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const double yy = y[v * n + io];
+                    const double kk = stage == 1 ? 0.0 : (double)kp[v * n + io];
+                    zo[e][v] = stage == 1 ? yy : fma(cdt, kk, yy);
+                    sy[v * T + m] = yy;
+                    sk[v * T + m] = kk;
+                }
             }
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -170,8 +180,17 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
             red[4] += tin[2 * uu];
             red[5] += tin[2 * uu + 1];
         }
-        __syncthreads();
+        lds_barrier();
 
+        // stage 4 needs the accumulator: issue its loads before the scan
+        double av[EPT][V];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int m = e * BS + tid;
+            const int64_t i = t0 + (m < cnt ? m : 0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) av[e][v] = stage == 4 ? acc[v * n + i] : 0.0;
+        }
         // ---- phase 2 (blocked, elements EPT*tid ..): exclusive scan of the
         // differences; LDS then holds the inclusive window sum of every element
         double2 dv[EPT];
@@ -194,22 +213,19 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 r1 += dv[e].y;
             }
         }
-        __syncthreads();
+        lds_barrier();
 
         // ---- phase 3 (coalesced): RHS, RK bookkeeping, next-stage tile sums
         // (loads from clamped indices issue together; only stores are masked)
         double nx[4] = {0.0, 0.0, 0.0, 0.0};
-        double yv[EPT][V], kv[EPT][V], av[EPT][V];
+        double yv[EPT][V], kv[EPT][V];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int m = e * BS + tid;
-            const int64_t i = t0 + (m < cnt ? m : 0);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int64_t q = v * n + i;
-                yv[e][v] = y[q];
-                kv[e][v] = (stage == 2 || stage == 4) ? (double)kp[q] : 0.0;
-                av[e][v] = stage == 4 ? d.acc[q] : 0.0;
+                yv[e][v] = sy[v * T + m];
+                kv[e][v] = sk[v * T + m];
             }
         }
 #pragma unroll
@@ -228,18 +244,18 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                     const double yy = yv[e][v];
                     const double kk = kq<KT>(k[v]);
                     if (stage == 1) {
-                        ((KT*)d.k[0])[q] = (KT)kk;
+                        gp((KT*)d.k[0])[q] = (KT)kk;
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 2) {
-                        ((KT*)d.k[1])[q] = (KT)kk;
-                        d.acc[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[e][v], yy));
+                        gp((KT*)d.k[1])[q] = (KT)kk;
+                        gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[e][v], yy));
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 3) {
-                        ((KT*)d.k[2])[q] = (KT)kk;
+                        gp((KT*)d.k[2])[q] = (KT)kk;
                         zn[v] = fma(dt, kk, yy);
                     } else {
                         const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[e][v], av[e][v]));
-                        d.y[par ^ 1][q] = yo;
+                        gp(d.y[par ^ 1])[q] = yo;
                         zn[v] = yo;
                     }
                 }
@@ -256,13 +272,13 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 // mean phase velocity (compiled only into the MV variants)
                 if (MV && (d.obs & OBS_MV) && g >= d.mv_start) {
                     if constexpr (MODEL == ND_KURAMOTO) {
-                        if (stage == 1 && g == d.mv_start) d.mv[i] = yv[e][0];
+                        if (stage == 1 && g == d.mv_start) gp(d.mv)[i] = yv[e][0];
                     } else {
                         if (stage == 4) {
                             const double uo = yv[e][0], vo = yv[e][1];
                             const double un = zn[0], vn = zn[1];
                             const double dth = atan2(uo * vn - vo * un, uo * un + vo * vn);
-                            d.mv[i] = (g == d.mv_start ? 0.0 : d.mv[i]) + dth;
+                            gp(d.mv)[i] = (g == d.mv_start ? 0.0 : gp(d.mv)[i]) + dth;
                         }
                     }
                 }
@@ -270,13 +286,13 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         }
         block_sum<BS, 4>(nx, lds);
         if (tid == 0) {
-            double* tout = d.tsum[stage & 1];
+            ND_GLOBAL double* tout = gp(d.tsum[stage & 1]);
             tout[2 * tile] = nx[0];
             tout[2 * tile + 1] = nx[1];
             if constexpr (MODEL == ND_FHN) {
                 if (stage == 4) {
-                    d.rsum[2 * tile] = nx[2];
-                    d.rsum[2 * tile + 1] = nx[3];
+                    gp(d.rsum)[2 * tile] = nx[2];
+                    gp(d.rsum)[2 * tile + 1] = nx[3];
                 }
             }
         }
@@ -349,7 +365,6 @@ static bool ring_pick(int tile, RingLaunch* out) {
     switch (tile) {
         case 1024: *out = ring_entry<MODEL, KT, 256, 4>(); return true;
         case 2048: *out = ring_entry<MODEL, KT, 256, 8>(); return true;
-        case 4096: *out = ring_entry<MODEL, KT, 512, 8>(); return true;
         case 512: *out = ring_entry<MODEL, KT, 128, 4>(); return true;
         case 256: *out = ring_entry<MODEL, KT, 64, 4>(); return true;
         default: return false;

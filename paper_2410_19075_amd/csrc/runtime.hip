@@ -106,7 +106,7 @@ nd_kernel_config default_config(const nd_problem* p) {
     c.grid = 0;
     c.chunk = 64;
     if (p->topo == ND_RING) {
-        c.tile = p->n <= (int64_t(1) << 16) ? 512 : (p->n <= (int64_t(1) << 20) ? 1024 : 2048);
+        c.tile = p->n <= (int64_t(1) << 18) ? 256 : (p->n <= (int64_t(1) << 20) ? 512 : 1024);
         c.block = ring_block(c.tile);
     } else if (p->topo == ND_CUBE3D) {
         // 20 x 20 outputs per plane (28 x 28 halo columns at h = 4) and 40-plane
@@ -128,7 +128,7 @@ nd_kernel_config default_config(const nd_problem* p) {
     return c;
 }
 
-int ring_block(int tile) { return tile == 4096 ? 512 : (tile == 512 ? 128 : (tile == 256 ? 64 : 256)); }
+int ring_block(int tile) { return tile == 512 ? 128 : (tile == 256 ? 64 : 256); }
 
 static int64_t bulk_bytes(int prec) { return prec == ND_FP64 ? 8 : 4; }
 

@@ -132,10 +132,12 @@ def random_out_graph(seed, n, out_degree, wmax=0.1):
         tgt[bad] = (bad[:, None] + 1 + (draw * (n - 1)).astype(np.int64)) % n
         rows = bad
     w = wmax * uniform(seed, TAG_WEIGHT, n * d)
-    src = src.ravel()
-    tgt = tgt.ravel()
-    order = np.lexsort((src, tgt))  # by target, then source ascending
-    col = src[order].astype(np.int32)
+    tgt = tgt.ravel().astype(np.int32)
+    del src
+    # edges are generated source-major, so a stable sort by target leaves the
+    # sources of every row ascending
+    order = np.argsort(tgt, kind="stable")
+    col = (order // d).astype(np.int32)
     w = w[order]
     counts = np.bincount(tgt, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
