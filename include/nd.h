@@ -168,6 +168,73 @@ typedef struct nd_kernel_config {
 nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
 nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of many independent simulations on one GPU.  The paper
+ * runs many small unconnected sub-networks in one run for throughput (Sec.
+ * III.C) and computes thousands of trajectories in batch mode (Sec. II, Sec.
+ * IV); the server does this online: requests arrive at any time, wait in a
+ * FIFO queue, are admitted while their device footprint fits the HBM budget and
+ * a slot is free, and then advance together, a chunk of RK4 steps at a time, in
+ * one persistent batched launch per kernel class (a captured graph replayed
+ * every chunk).  New requests join and finished ones leave at chunk
+ * boundaries.  Every request's arithmetic is the same as nd_run's for the same
+ * problem, whatever else shares the GPU with it.
+ */
+typedef struct nd_server* nd_server_h;
+typedef int64_t nd_req;
+
+#define ND_REQ_QUEUED 0
+#define ND_REQ_RUNNING 1
+#define ND_REQ_DONE 2
+#define ND_REQ_FAILED 3
+#define ND_REQ_CANCELLED 4
+
+typedef struct nd_server_config {
+    int64_t hbm_budget_bytes; /* device bytes that admitted requests may hold (nd_footprint) */
+    int32_t max_slots;        /* requests running at once (<= 4096) */
+    int32_t chunk_steps;      /* RK4 steps per chunk (>= 1) */
+    int32_t grid;             /* persistent workgroups per kernel class (multiple of 8; 0 = 2048) */
+    int32_t reserved;         /* must be 0 */
+} nd_server_config;
+
+typedef struct nd_request_info {
+    int32_t state;        /* ND_REQ_* */
+    nd_status status;     /* failure reason when state == ND_REQ_FAILED */
+    int64_t steps_done;
+    double arrival;       /* seconds on the server clock */
+    double admitted;      /* -1 until admitted */
+    double finished;      /* -1 until done / failed / cancelled */
+} nd_request_info;
+
+typedef struct nd_server_counters {
+    int64_t submitted, completed, failed, cancelled, queued, running;
+    int64_t bytes_in_use;  /* footprint of the running requests */
+    int64_t chunks;        /* chunks launched */
+    double gpu_seconds;    /* time spent waiting for chunks */
+    int64_t osc_steps;     /* element-steps completed */
+} nd_server_counters;
+
+nd_status nd_server_create(const nd_server_config* cfg, nd_server_h* out);
+/* Seconds since the server was created (the clock of arrival/admitted/finished). */
+nd_status nd_server_now(nd_server_h s, double* seconds);
+/* Queue a simulation: problem p (host data copied), initial state y0 (host, nvars*n doubles,
+ * copied), dt, steps >= 1, observables (may be NULL).  arrival < 0 means now.  Returns
+ * ND_ERR_INVALID_ARG for a bad problem or a footprint above the budget and ND_ERR_NUMERIC for a
+ * non-finite y0; the request then does not exist.  Never touches the GPU. */
+nd_status nd_server_submit(nd_server_h s, const nd_problem* p, const double* y0, int64_t len, double dt,
+                           int64_t steps, const nd_observe* obs, double arrival, nd_req* id);
+/* One scheduling cycle on `stream`: admit from the queue, run one chunk of every admitted request,
+ * wait for it, retire finished requests (results copied to host memory).  *pending receives the
+ * number of queued + running requests afterwards. */
+nd_status nd_server_pump(nd_server_h s, void* stream, int64_t* pending);
+nd_status nd_server_info(nd_server_h s, nd_req id, nd_request_info* info);
+/* Final state (len = nvars*n) and R (r_len = steps/record_every + 1, or NULL / 0) of a done request. */
+nd_status nd_server_result(nd_server_h s, nd_req id, double* y, int64_t len, double* R, int64_t r_len);
+/* Cancel a queued or running request; a running one leaves at the next chunk boundary. */
+nd_status nd_server_cancel(nd_server_h s, nd_req id);
+nd_status nd_server_stats(nd_server_h s, nd_server_counters* st);
+nd_status nd_server_destroy(nd_server_h s);
+
 const char* nd_status_str(nd_status s);
 const char* nd_last_error(void);
 

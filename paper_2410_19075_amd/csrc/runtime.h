@@ -45,6 +45,12 @@ struct Net {
     void append_work(int desc_index, std::vector<int2>& wk) const;
     nd_status prepare_observe(int64_t steps, const nd_observe* obs);
     NetDesc run_desc(double dt, int64_t steps) const;
+    // chunked runs (serving): the run's step counter lives on the host and each
+    // chunk's descriptor starts where the previous chunk stopped
+    double run_dt = 0.0;
+    int64_t run_total = 0, run_done = 0;
+    nd_status begin_run(double dt, int64_t steps, const nd_observe* obs);
+    NetDesc chunk_desc() const;
 };
 
 // Networks of one kernel class launched together.
@@ -60,6 +66,8 @@ struct Group {
 };
 
 nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st);
+nd_status capture_chunk(const Group& g, int K, hipGraphExec_t* out);
+bool graphs_enabled();
 nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t* steps, const nd_observe* obs,
                    hipStream_t st);
 

@@ -336,6 +336,24 @@ NetDesc Net::run_desc(double dt, int64_t steps) const {
     return d;
 }
 
+nd_status Net::begin_run(double dt, int64_t steps, const nd_observe* obs) {
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ND_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (steps < 1) return fail(ND_ERR_INVALID_ARG, "steps must be >= 1");
+    nd_status s = prepare_observe(steps, obs);
+    if (s) return s;
+    run_dt = dt;
+    run_total = steps;
+    run_done = 0;
+    return ND_OK;
+}
+
+NetDesc Net::chunk_desc() const {
+    NetDesc d = run_desc(run_dt, run_total);
+    d.g0 = run_done;
+    d.nsteps = run_total - run_done;
+    return d;
+}
+
 // ----------------------------------------------------------- launch groups
 __global__ void k_advance(NetDesc* D, int ndesc, int chunk) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;

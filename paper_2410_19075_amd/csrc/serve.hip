@@ -1,0 +1,474 @@
+// Continuous-batching server (nd_server_* in include/nd.h).
+//
+// Requests are queued FIFO with their arrival time.  Each pump admits queued
+// requests while their device footprint fits the HBM budget and a slot is free,
+// advances every admitted request by one chunk of RK4 steps, waits for the
+// chunk and retires the requests that finished.  Admitted requests are grouped
+// by kernel class (model, topology, precision, tile shape); every class owns a
+// fixed-capacity descriptor table and work map in device memory and one chunk
+// graph captured once with a persistent grid.  Between chunks only the table
+// contents change (pinned host staging, async copies on the pump's stream), so
+// the same graph is replayed whatever the mix of requests.  A request's kernels
+// and tile decomposition depend on its own problem only, so its arithmetic is
+// identical alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "runtime.h"
+
+namespace nd {
+
+#define HIPC(expr)                                        \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+using ClassKey = std::tuple<int, int, int, int, int, int>;
+
+static ClassKey class_key(const Net* n) {
+    const int h = n->prob.topo == ND_CUBE3D ? (int)n->prob.radius : 0;
+    return ClassKey(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h);
+}
+
+struct Request {
+    nd_req id = 0;
+    nd_problem prob{};
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<double> weight, per_elem, y0, y, R;
+    double dt = 0.0;
+    int64_t steps = 0;
+    nd_observe obs{0, -1};
+    int64_t footprint = 0;
+    int32_t state = ND_REQ_QUEUED;
+    nd_status status = ND_OK;
+    double arrival = 0.0, admitted = -1.0, finished = -1.0;
+    Net* net = nullptr;
+    int cls = -1, slot = -1;
+    bool cancel = false;
+};
+
+struct ClassTable {
+    ClassKey key;
+    Group g{};
+    int cap_desc = 0, cap_work = 0;
+    void* dev = nullptr;  // desc | work | nwork
+    NetDesc* h_desc = nullptr;
+    int2* h_work = nullptr;
+    int* h_nwork = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};  // without / with mean-velocity kernels
+    std::vector<Request*> slots;
+
+    ~ClassTable() {
+        for (auto& e : exec)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (dev) (void)hipFree(dev);
+        if (h_desc) (void)hipHostFree(h_desc);
+        if (h_work) (void)hipHostFree(h_work);
+        if (h_nwork) (void)hipHostFree(h_nwork);
+    }
+    int active() const {
+        int c = 0;
+        for (auto* r : slots) c += r != nullptr;
+        return c;
+    }
+};
+
+struct Server {
+    nd_server_config cfg{};
+    std::chrono::steady_clock::time_point t0;
+    std::mutex mu;
+    std::map<nd_req, std::unique_ptr<Request>> reqs;
+    std::deque<Request*> queue;
+    std::vector<Request*> running;
+    std::vector<std::unique_ptr<ClassTable>> classes;
+    int64_t next_id = 1;
+    nd_server_counters st{};
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    nd_status table_for(Request* r, ClassTable** out);
+    nd_status grow_work(ClassTable* t, int need);
+    nd_status admit(Request* r);
+    void release(Request* r, int32_t state, nd_status why);
+    nd_status pump(hipStream_t st, int64_t* pending);
+};
+
+static void set_empty(NetDesc& d) {
+    std::memset(&d, 0, sizeof d);
+    d.r_every = 1;
+}
+
+nd_status Server::grow_work(ClassTable* t, int need) {
+    if (need <= t->cap_work && t->dev) return ND_OK;
+    int cap = std::max(need, std::max(1024, 2 * t->cap_work));
+    for (auto& e : t->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    if (t->dev) (void)hipFree(t->dev);
+    if (t->h_work) (void)hipHostFree(t->h_work);
+    t->dev = nullptr;
+    t->h_work = nullptr;
+    const size_t bd = (size_t)t->cap_desc * sizeof(NetDesc), bw = (size_t)cap * sizeof(int2);
+    HIPC(hipMalloc(&t->dev, bd + bw + 64));
+    HIPC(hipHostMalloc((void**)&t->h_work, bw));
+    t->cap_work = cap;
+    t->g.desc = (NetDesc*)t->dev;
+    t->g.work = (int2*)((char*)t->dev + bd);
+    t->g.nwork = (int*)((char*)t->dev + bd + bw);
+    return ND_OK;
+}
+
+nd_status Server::table_for(Request* r, ClassTable** out) {
+    const ClassKey key = class_key(r->net);
+    for (auto& t : classes)
+        if (t->key == key) {
+            *out = t.get();
+            return ND_OK;
+        }
+    auto t = std::make_unique<ClassTable>();
+    t->key = key;
+    t->cap_desc = cfg.max_slots;
+    t->slots.assign(cfg.max_slots, nullptr);
+    Group& g = t->g;
+    g.model = std::get<0>(key);
+    g.topo = std::get<1>(key);
+    g.prec = std::get<2>(key);
+    g.tile = std::get<3>(key);
+    g.tile_y = std::get<4>(key);
+    g.h = std::get<5>(key);
+    g.ndesc = t->cap_desc;
+    g.grid = cfg.grid;
+    HIPC(hipHostMalloc((void**)&t->h_desc, (size_t)t->cap_desc * sizeof(NetDesc)));
+    HIPC(hipHostMalloc((void**)&t->h_nwork, 64));
+    nd_status s = grow_work(t.get(), 1024);
+    if (s) return s;
+    *out = t.get();
+    classes.push_back(std::move(t));
+    return ND_OK;
+}
+
+nd_status Server::admit(Request* r) {
+    Net* n = new (std::nothrow) Net();
+    if (!n) return fail(ND_ERR_OUT_OF_MEMORY, "host allocation failed");
+    nd_status s = n->create(&r->prob);
+    if (!s) s = n->begin_run(r->dt, r->steps, &r->obs);
+    if (!s) {
+        hipError_t e = hipMemcpy(n->tmpl.y[n->ypar], r->y0.data(), r->y0.size() * 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) s = hip_fail(e, "state upload");
+    }
+    if (s) {
+        delete n;
+        return s;
+    }
+    r->net = n;
+    ClassTable* t = nullptr;
+    if ((s = table_for(r, &t))) {
+        delete n;
+        r->net = nullptr;
+        return s;
+    }
+    const int slot = (int)(std::find(t->slots.begin(), t->slots.end(), nullptr) - t->slots.begin());
+    t->slots[slot] = r;
+    r->cls = (int)(std::find_if(classes.begin(), classes.end(), [&](auto& c) { return c.get() == t; }) -
+                   classes.begin());
+    r->slot = slot;
+    r->state = ND_REQ_RUNNING;
+    r->admitted = now();
+    r->y0.clear();
+    r->y0.shrink_to_fit();
+    st.bytes_in_use += r->footprint;
+    running.push_back(r);
+    return ND_OK;
+}
+
+void Server::release(Request* r, int32_t state, nd_status why) {
+    if (r->slot >= 0) classes[r->cls]->slots[r->slot] = nullptr;
+    r->slot = -1;
+    if (r->net) {
+        delete r->net;
+        r->net = nullptr;
+        st.bytes_in_use -= r->footprint;
+    }
+    r->state = state;
+    r->status = why;
+    r->finished = now();
+    if (state == ND_REQ_DONE) ++st.completed;
+    if (state == ND_REQ_FAILED) ++st.failed;
+    if (state == ND_REQ_CANCELLED) ++st.cancelled;
+}
+
+nd_status Server::pump(hipStream_t strm, int64_t* pending) {
+    // ---- admission: FIFO while the head fits the budget and a slot is free
+    while (!queue.empty()) {
+        Request* r = queue.front();
+        if (r->cancel) {
+            queue.pop_front();
+            release(r, ND_REQ_CANCELLED, ND_OK);
+            continue;
+        }
+        if ((int)running.size() >= cfg.max_slots) break;
+        if (st.bytes_in_use + r->footprint > cfg.hbm_budget_bytes) break;
+        queue.pop_front();
+        nd_status s = admit(r);
+        if (s) release(r, ND_REQ_FAILED, s);
+    }
+    // ---- one chunk for every kernel class with admitted requests
+    const int K = cfg.chunk_steps;
+    bool launched = false;
+    for (auto& tp : classes) {
+        ClassTable* t = tp.get();
+        if (!t->active()) continue;
+        int nw = 0;
+        bool mv = false;
+        for (int s = 0; s < t->cap_desc; ++s) {
+            Request* r = t->slots[s];
+            if (r && !r->cancel) {
+                nw += (int)r->net->work_items();
+                mv = mv || r->net->mv_start >= 0;
+            }
+        }
+        nd_status s = grow_work(t, nw);
+        if (s) return s;
+        int w = 0;
+        for (int sl = 0; sl < t->cap_desc; ++sl) {
+            Request* r = t->slots[sl];
+            if (r && !r->cancel) {
+                t->h_desc[sl] = r->net->chunk_desc();
+                const int64_t m = r->net->work_items();
+                for (int64_t q = 0; q < m; ++q) t->h_work[w++] = make_int2(sl, (int)q);
+            } else {
+                set_empty(t->h_desc[sl]);
+            }
+        }
+        *t->h_nwork = w;
+        HIPC(hipMemcpyAsync(t->g.desc, t->h_desc, (size_t)t->cap_desc * sizeof(NetDesc), hipMemcpyHostToDevice,
+                            strm));
+        HIPC(hipMemcpyAsync(t->g.work, t->h_work, (size_t)std::max(w, 1) * sizeof(int2), hipMemcpyHostToDevice,
+                            strm));
+        HIPC(hipMemcpyAsync(t->g.nwork, t->h_nwork, sizeof(int), hipMemcpyHostToDevice, strm));
+        t->g.mv = mv;
+        if (graphs_enabled()) {
+            hipGraphExec_t& ex = t->exec[mv ? 1 : 0];
+            if (!ex && (s = capture_chunk(t->g, K, &ex))) return s;
+            HIPC(hipGraphLaunch(ex, strm));
+        } else if ((s = enqueue_chunk(t->g, K, strm))) {
+            return s;
+        }
+        launched = true;
+    }
+    if (launched) {
+        const double a = now();
+        HIPC(hipStreamSynchronize(strm));
+        st.gpu_seconds += now() - a;
+        ++st.chunks;
+    }
+    // ---- advance host-side progress, retire finished and cancelled requests
+    std::vector<Request*> still;
+    for (Request* r : running) {
+        Net* n = r->net;
+        if (!r->cancel) {
+            const int64_t done = std::min<int64_t>(K, n->run_total - n->run_done);
+            n->run_done += done;
+            n->ypar ^= (int)(done & 1);
+            st.osc_steps += done * n->prob.n;
+        }
+        if (r->cancel) {
+            release(r, ND_REQ_CANCELLED, ND_OK);
+        } else if (n->run_done >= n->run_total) {
+            r->y.resize((size_t)nvars_of(r->prob.model) * r->prob.n);
+            hipError_t e = hipMemcpy(r->y.data(), n->tmpl.y[n->ypar], r->y.size() * 8, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && n->r_every > 0) {
+                r->R.resize(n->run_total / n->r_every + 1);
+                e = hipMemcpy(r->R.data(), n->R_dev, r->R.size() * 8, hipMemcpyDeviceToHost);
+            }
+            if (e != hipSuccess) {
+                release(r, ND_REQ_FAILED, hip_fail(e, "result download"));
+            } else {
+                bool finite = true;
+                for (double v : r->y) finite = finite && std::isfinite(v);
+                release(r, finite ? ND_REQ_DONE : ND_REQ_FAILED, finite ? ND_OK : ND_ERR_NUMERIC);
+            }
+        } else {
+            still.push_back(r);
+        }
+    }
+    running.swap(still);
+    if (pending) *pending = (int64_t)(queue.size() + running.size());
+    return ND_OK;
+}
+
+}  // namespace nd
+
+using namespace nd;
+
+extern "C" {
+
+nd_status nd_server_create(const nd_server_config* cfg, nd_server_h* out) {
+    if (!cfg || !out) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (cfg->reserved != 0) return fail(ND_ERR_INVALID_ARG, "reserved must be 0");
+    if (cfg->hbm_budget_bytes <= 0) return fail(ND_ERR_INVALID_ARG, "hbm_budget_bytes must be > 0");
+    if (cfg->max_slots < 1 || cfg->max_slots > 4096) return fail(ND_ERR_INVALID_ARG, "max_slots in [1, 4096]");
+    if (cfg->chunk_steps < 1) return fail(ND_ERR_INVALID_ARG, "chunk_steps must be >= 1");
+    if (cfg->grid < 0 || (cfg->grid % 8) != 0) return fail(ND_ERR_INVALID_ARG, "grid must be a multiple of 8");
+    Server* s = new (std::nothrow) Server();
+    if (!s) return fail(ND_ERR_OUT_OF_MEMORY, "host allocation failed");
+    s->cfg = *cfg;
+    if (s->cfg.grid == 0) s->cfg.grid = 2048;
+    s->t0 = std::chrono::steady_clock::now();
+    *out = reinterpret_cast<nd_server_h>(s);
+    return ND_OK;
+}
+
+static Server* as_server(nd_server_h h) { return reinterpret_cast<Server*>(h); }
+
+nd_status nd_server_now(nd_server_h h, double* seconds) {
+    Server* s = as_server(h);
+    if (!s || !seconds) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    *seconds = s->now();
+    return ND_OK;
+}
+
+nd_status nd_server_submit(nd_server_h h, const nd_problem* p, const double* y0, int64_t len, double dt,
+                           int64_t steps, const nd_observe* obs, double arrival, nd_req* id) {
+    Server* s = as_server(h);
+    if (!s || !id || !y0) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    nd_status st = validate_problem(p);
+    if (st) return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ND_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (steps < 1) return fail(ND_ERR_INVALID_ARG, "steps must be >= 1");
+    const int64_t want = nvars_of(p->model) * p->n;
+    if (len != want) return fail(ND_ERR_INVALID_ARG, "state length %lld, expected %lld", (long long)len,
+                                 (long long)want);
+    if (obs) {
+        if (obs->record_every < 0 || obs->mv_start_step < -1 || obs->mv_start_step >= steps)
+            return fail(ND_ERR_INVALID_ARG, "bad observation settings");
+        if ((obs->record_every > 0 || obs->mv_start_step >= 0) && p->model == ND_HH)
+            return fail(ND_ERR_INVALID_ARG, "R and mean phase velocity are not defined for HH");
+    }
+    for (int64_t i = 0; i < len; ++i)
+        if (!std::isfinite(y0[i])) return fail(ND_ERR_NUMERIC, "initial state holds a non-finite value at %lld",
+                                               (long long)i);
+    auto r = std::make_unique<Request>();
+    r->prob = *p;
+    if (p->topo == ND_CSR) {
+        r->row_ptr.assign(p->row_ptr, p->row_ptr + p->n + 1);
+        r->col.assign(p->col, p->col + p->nnz);
+        r->weight.assign(p->weight, p->weight + p->nnz);
+        r->prob.row_ptr = r->row_ptr.data();
+        r->prob.col = r->col.data();
+        r->prob.weight = r->weight.data();
+    }
+    if (p->per_elem) {
+        r->per_elem.assign(p->per_elem, p->per_elem + p->n);
+        r->prob.per_elem = r->per_elem.data();
+    }
+    r->y0.assign(y0, y0 + len);
+    r->dt = dt;
+    r->steps = steps;
+    if (obs) r->obs = *obs;
+    r->footprint = footprint_bytes(p, default_config(p));
+    if (r->obs.record_every > 0) r->footprint += (steps / r->obs.record_every + 1) * 8;
+    if (r->obs.mv_start_step >= 0) r->footprint += p->n * 8;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (r->footprint > s->cfg.hbm_budget_bytes)
+        return fail(ND_ERR_INVALID_ARG, "request footprint %lld exceeds the HBM budget %lld",
+                    (long long)r->footprint, (long long)s->cfg.hbm_budget_bytes);
+    r->id = s->next_id++;
+    r->arrival = arrival >= 0.0 ? arrival : s->now();
+    *id = r->id;
+    s->queue.push_back(r.get());
+    s->reqs[r->id] = std::move(r);
+    ++s->st.submitted;
+    return ND_OK;
+}
+
+nd_status nd_server_pump(nd_server_h h, void* stream, int64_t* pending) {
+    Server* s = as_server(h);
+    if (!s) return fail(ND_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->pump((hipStream_t)stream, pending);
+}
+
+nd_status nd_server_info(nd_server_h h, nd_req id, nd_request_info* info) {
+    Server* s = as_server(h);
+    if (!s || !info) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(ND_ERR_INVALID_ARG, "unknown request %lld", (long long)id);
+    const Request* r = it->second.get();
+    info->state = r->state;
+    info->status = r->status;
+    info->steps_done = r->net ? r->net->run_done : (r->state == ND_REQ_DONE ? r->steps : 0);
+    info->arrival = r->arrival;
+    info->admitted = r->admitted;
+    info->finished = r->finished;
+    return ND_OK;
+}
+
+nd_status nd_server_result(nd_server_h h, nd_req id, double* y, int64_t len, double* R, int64_t r_len) {
+    Server* s = as_server(h);
+    if (!s) return fail(ND_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(ND_ERR_INVALID_ARG, "unknown request %lld", (long long)id);
+    const Request* r = it->second.get();
+    if (r->state != ND_REQ_DONE) return fail(ND_ERR_NOT_READY, "request %lld is not done", (long long)id);
+    if (y) {
+        if (len != (int64_t)r->y.size()) return fail(ND_ERR_INVALID_ARG, "state length mismatch");
+        std::memcpy(y, r->y.data(), len * 8);
+    }
+    if (R) {
+        if (r_len != (int64_t)r->R.size()) return fail(ND_ERR_INVALID_ARG, "R length mismatch");
+        std::memcpy(R, r->R.data(), r_len * 8);
+    }
+    return ND_OK;
+}
+
+nd_status nd_server_cancel(nd_server_h h, nd_req id) {
+    Server* s = as_server(h);
+    if (!s) return fail(ND_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(ND_ERR_INVALID_ARG, "unknown request %lld", (long long)id);
+    Request* r = it->second.get();
+    if (r->state == ND_REQ_QUEUED || r->state == ND_REQ_RUNNING) r->cancel = true;
+    return ND_OK;
+}
+
+nd_status nd_server_stats(nd_server_h h, nd_server_counters* out) {
+    Server* s = as_server(h);
+    if (!s || !out) return fail(ND_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->queued = (int64_t)s->queue.size();
+    out->running = (int64_t)s->running.size();
+    return ND_OK;
+}
+
+nd_status nd_server_destroy(nd_server_h h) {
+    Server* s = as_server(h);
+    if (!s) return fail(ND_ERR_INVALID_ARG, "NULL server");
+    (void)hipDeviceSynchronize();
+    for (Request* r : s->running)
+        if (r->net) delete r->net;
+    delete s;
+    return ND_OK;
+}
+
+}  // extern "C"

@@ -42,6 +42,24 @@ class nd_kernel_config(ctypes.Structure):
                 ("tile_z", _c_i32)]
 
 
+class nd_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _c_i64), ("max_slots", _c_i32), ("chunk_steps", _c_i32), ("grid", _c_i32),
+                ("reserved", _c_i32)]
+
+
+class nd_request_info(ctypes.Structure):
+    _fields_ = [("state", _c_i32), ("status", _c_i32), ("steps_done", _c_i64), ("arrival", _c_dbl),
+                ("admitted", _c_dbl), ("finished", _c_dbl)]
+
+
+class nd_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("failed", _c_i64), ("cancelled", _c_i64),
+                ("queued", _c_i64), ("running", _c_i64), ("bytes_in_use", _c_i64), ("chunks", _c_i64),
+                ("gpu_seconds", _c_dbl), ("osc_steps", _c_i64)]
+
+
+ND_REQ_QUEUED, ND_REQ_RUNNING, ND_REQ_DONE, ND_REQ_FAILED, ND_REQ_CANCELLED = range(5)
+
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnd.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libnd.so is not built ({LIB_PATH}); run python -m paper_2410_19075_amd.build")
@@ -59,6 +77,16 @@ _sig = {
     "nd_destroy": [_c_vp],
     "nd_get_config": [_c_vp, _P(nd_kernel_config)],
     "nd_set_config": [_c_vp, _P(nd_kernel_config)],
+    "nd_server_create": [_P(nd_server_config), _P(_c_vp)],
+    "nd_server_now": [_c_vp, _P(_c_dbl)],
+    "nd_server_submit": [_c_vp, _P(nd_problem), _c_vp, _c_i64, _c_dbl, _c_i64, _P(nd_observe), _c_dbl,
+                         _P(_c_i64)],
+    "nd_server_pump": [_c_vp, _c_vp, _P(_c_i64)],
+    "nd_server_info": [_c_vp, _c_i64, _P(nd_request_info)],
+    "nd_server_result": [_c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64],
+    "nd_server_cancel": [_c_vp, _c_i64],
+    "nd_server_stats": [_c_vp, _P(nd_server_counters)],
+    "nd_server_destroy": [_c_vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -191,6 +219,59 @@ def nd_get_config(h):
 
 def nd_set_config(h, c):
     _check(_lib.nd_set_config(h, ctypes.byref(c)), "nd_set_config")
+
+
+def nd_server_create(hbm_budget_bytes, max_slots=256, chunk_steps=64, grid=0):
+    cfg = nd_server_config(int(hbm_budget_bytes), int(max_slots), int(chunk_steps), int(grid), 0)
+    h = _c_vp()
+    _check(_lib.nd_server_create(ctypes.byref(cfg), ctypes.byref(h)), "nd_server_create")
+    return h.value
+
+
+def nd_server_now(s):
+    t = _c_dbl()
+    _check(_lib.nd_server_now(s, ctypes.byref(t)), "nd_server_now")
+    return t.value
+
+
+def nd_server_submit(s, p, y0, dt, steps, obs=None, arrival=-1.0):
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    rid = _c_i64()
+    _check(_lib.nd_server_submit(s, ctypes.byref(p), y0.ctypes.data, y0.size, float(dt), int(steps),
+                                 ctypes.byref(obs) if obs is not None else None, float(arrival), ctypes.byref(rid)),
+           "nd_server_submit")
+    return rid.value
+
+
+def nd_server_pump(s, stream=None):
+    pending = _c_i64()
+    _check(_lib.nd_server_pump(s, _stream(stream), ctypes.byref(pending)), "nd_server_pump")
+    return pending.value
+
+
+def nd_server_info(s, rid):
+    info = nd_request_info()
+    _check(_lib.nd_server_info(s, int(rid), ctypes.byref(info)), "nd_server_info")
+    return info
+
+
+def nd_server_result(s, rid, y, R=None):
+    _check(_lib.nd_server_result(s, int(rid), _ptr(y), y.size, _ptr(R), 0 if R is None else R.size),
+           "nd_server_result")
+
+
+def nd_server_cancel(s, rid):
+    _check(_lib.nd_server_cancel(s, int(rid)), "nd_server_cancel")
+
+
+def nd_server_stats(s):
+    st = nd_server_counters()
+    _check(_lib.nd_server_stats(s, ctypes.byref(st)), "nd_server_stats")
+    return st
+
+
+def nd_server_destroy(s):
+    _check(_lib.nd_server_destroy(s), "nd_server_destroy")
 
 
 def nd_status_str(s):

@@ -1,0 +1,60 @@
+"""Host-side behaviour of the serving API (no GPU work is started)."""
+import numpy as np
+import pytest
+
+from paper_2410_19075_amd import inputs
+
+nd = pytest.importorskip("paper_2410_19075_amd.nd")
+
+
+def kur(n=1024, P=256):
+    return nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, [0.0, 1.0, 1.46], radius=P)
+
+
+def test_config_validation():
+    with pytest.raises(nd.NDError):
+        nd.nd_server_create(0)
+    with pytest.raises(nd.NDError):
+        nd.nd_server_create(1 << 30, max_slots=0)
+    with pytest.raises(nd.NDError):
+        nd.nd_server_create(1 << 30, grid=12)
+    s = nd.nd_server_create(1 << 30)
+    nd.nd_server_destroy(s)
+
+
+def test_submit_rejections_fail_alone():
+    s = nd.nd_server_create(1 << 20, max_slots=4)
+    try:
+        good = nd.nd_server_submit(s, kur(), inputs.kuramoto_phases(1, 1024), 0.01, 10)
+        y = inputs.kuramoto_phases(2, 1024)
+        y[17] = np.nan
+        with pytest.raises(nd.NDError) as ei:
+            nd.nd_server_submit(s, kur(), y, 0.01, 10)
+        assert ei.value.status == nd.ND_ERR_NUMERIC
+        with pytest.raises(nd.NDError) as ei:  # footprint above the budget
+            nd.nd_server_submit(s, kur(1 << 20, 1000), inputs.kuramoto_phases(3, 1 << 20), 0.01, 10)
+        assert ei.value.status == nd.ND_ERR_INVALID_ARG and "budget" in str(ei.value)
+        with pytest.raises(nd.NDError):
+            nd.nd_server_submit(s, kur(), inputs.kuramoto_phases(1, 1000), 0.01, 10)  # wrong length
+        with pytest.raises(nd.NDError):
+            nd.nd_server_submit(s, kur(), inputs.kuramoto_phases(1, 1024), 0.0, 10)
+        st = nd.nd_server_stats(s)
+        assert st.submitted == 1 and st.queued == 1
+        info = nd.nd_server_info(s, good)
+        assert info.state == nd.ND_REQ_QUEUED and info.admitted == -1.0
+    finally:
+        nd.nd_server_destroy(s)
+
+
+def test_cancel_queued_request_without_gpu_work():
+    s = nd.nd_server_create(1 << 30)
+    try:
+        r = nd.nd_server_submit(s, kur(), inputs.kuramoto_phases(1, 1024), 0.01, 10, arrival=0.0)
+        nd.nd_server_cancel(s, r)
+        assert nd.nd_server_pump(s) == 0  # only the cancelled head: nothing is launched
+        assert nd.nd_server_info(s, r).state == nd.ND_REQ_CANCELLED
+        with pytest.raises(nd.NDError) as ei:
+            nd.nd_server_result(s, r, np.empty(1024))
+        assert ei.value.status == nd.ND_ERR_NOT_READY
+    finally:
+        nd.nd_server_destroy(s)
