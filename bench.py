@@ -17,6 +17,13 @@ Other workloads (one JSON line each, same fields):
                        out-degree 100, weights U[0, 0.1], I_app U[8, 12],
                        dt = 0.01 ms, 5000 steps
   --workload kuramoto  Kuramoto rings N = 1024, P = 256, alpha = 1.46, 200 steps
+  --workload serve     continuous-batching server fed by seeded Poisson arrivals of
+                       Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
+                       [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
+                       [1.3, 1.55], horizons log-uniform in [--hmin, --hmax] RK4 steps,
+                       arrival rate = rho x measured capacity; reports p50/p99 request
+                       and chunk latency, aggregate oscillator-steps/s, and the FP32-bulk
+                       results' error against the FP64 run of the same requests
 
 Inputs are synthetic (seeded) and resident on the GPU before timing starts.
 Prints one JSON line.
@@ -42,6 +49,7 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "kuramoto": (4096, 200, 0.01, 1024),
     "cube": (1, 2000, 0.05, 200),
     "hh": (1, 5000, 0.01, 1000000),
+    "serve": (24, 0, 0.01, 0),
 }
 
 
@@ -62,6 +70,10 @@ def parse():
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="persistent grid override (0 = one block per work item)")
     ap.add_argument("--chunk", type=int, default=0, help="steps per captured graph chunk (0 = default)")
+    ap.add_argument("--hmin", type=float, default=1e3, help="serve: shortest horizon (RK4 steps)")
+    ap.add_argument("--hmax", type=float, default=1e4, help="serve: longest horizon (RK4 steps)")
+    ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load / capacity")
+    ap.add_argument("--budget-gb", type=float, default=8.0, help="serve: HBM budget of the server")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (for scaling HBM counters)")
     a = ap.parse_args()
@@ -233,6 +245,116 @@ def roofline(wl, args, prec, ev_total):
             "bytes_per_launch": per_launch, "avg_launch_us": stage_s * 1e6}
 
 
+# ------------------------------------------------------------------- serving
+def serve_requests(args):
+    """The request stream: model, N, P, alpha, horizon, seed and arrival gap per request."""
+    from paper_2410_19075_amd import inputs
+    m = args.batch
+    u = inputs.uniform(77, inputs.TAG_MISC, 6 * m).reshape(6, m)
+    reqs = []
+    for i in range(m):
+        model = "kur" if u[0, i] < 0.5 else "fhn"
+        n = int(2 ** (10 + 12 * u[1, i]))
+        P = max(1, int(n * (0.05 + 0.35 * u[2, i])))
+        P = min(P, (n - 1) // 2)
+        alpha = 1.3 + 0.25 * u[3, i]
+        steps = int(10 ** (math.log10(args.hmin) + (math.log10(args.hmax) - math.log10(args.hmin)) * u[4, i]))
+        reqs.append(dict(model=model, n=n, P=P, alpha=alpha, steps=steps, seed=5000 + i, gap=-math.log(1 - u[5, i])))
+    return reqs
+
+
+def serve_run(nd, torch, args, reqs, states, prec, rate, stream):
+    """Feed the requests at their arrival times (rate = requests per second) and pump
+    the server until all are done; returns per-request latencies, chunk times,
+    makespan and the results."""
+    s = nd.nd_server_create(int(args.budget_gb * 2 ** 30), max_slots=256, chunk_steps=64)
+    try:
+        arrivals, t = [], 0.0
+        for r in reqs:
+            t += r["gap"] / rate
+            arrivals.append(t)
+        ids = [None] * len(reqs)
+        chunk_ms = []
+        i = 0
+        t0 = nd.nd_server_now(s)
+        pending = 0
+        while i < len(reqs) or pending:
+            now = nd.nd_server_now(s) - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                r = reqs[i]
+                if r["model"] == "kur":
+                    p = nd.problem(nd.ND_KURAMOTO, nd.ND_RING, r["n"], [0.0, 1.0, r["alpha"]], precision=prec,
+                                   radius=r["P"])
+                else:
+                    p = nd.problem(nd.ND_FHN, nd.ND_RING, r["n"], FHN_PRM, precision=prec, radius=r["P"])
+                ids[i] = nd.nd_server_submit(s, p, states[i], 0.01, r["steps"], arrival=t0 + arrivals[i])
+                i += 1
+            if pending == 0 and i < len(reqs) and nd.nd_server_stats(s).queued == 0:
+                time.sleep(max(0.0, min(0.05, arrivals[i] - now)))
+            a = time.perf_counter()
+            pending = nd.nd_server_pump(s, stream)
+            if nd.nd_server_stats(s).running or pending:
+                chunk_ms.append(1e3 * (time.perf_counter() - a))
+        makespan = nd.nd_server_now(s) - t0
+        lat, results = [], []
+        for rid, r, st in zip(ids, reqs, states):
+            info = nd.nd_server_info(s, rid)
+            assert info.state == nd.ND_REQ_DONE, (r, info.state, info.status)
+            lat.append(info.finished - info.arrival)
+            y = np.empty_like(st)
+            nd.nd_server_result(s, rid, y)
+            results.append(y)
+        stats = nd.nd_server_stats(s)
+        return dict(lat=lat, chunk_ms=chunk_ms, makespan=makespan, results=results, osc=stats.osc_steps,
+                    gpu_s=stats.gpu_seconds)
+    finally:
+        nd.nd_server_destroy(s)
+
+
+def main_serve(nd, torch, args, stream):
+    from paper_2410_19075_amd import inputs
+    reqs = serve_requests(args)
+    states = [inputs.kuramoto_phases(r["seed"], r["n"]) if r["model"] == "kur" else inputs.fhn_circle(r["seed"], r["n"])
+              for r in reqs]
+    work = sum(r["n"] * r["steps"] for r in reqs)
+    # capacity probe: the whole stream submitted at once (closed loop), FP64
+    probe = serve_run(nd, torch, args, reqs, states, nd.ND_FP64, 1e9, stream)
+    capacity = work / probe["makespan"]
+    rate = args.rho * capacity / (work / len(reqs))
+    out = {"metric": "oscillator-steps/s", "unit": "oscillator-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"serving: {len(reqs)} Poisson requests (50/50 Kuramoto/FHN rings, N log-uniform "
+                                  f"2^10..2^22, P/N U[0.05,0.4], alpha U[1.3,1.55], horizons log-uniform "
+                                  f"[{args.hmin:g}, {args.hmax:g}] RK4 steps, dt=0.01), offered load "
+                                  f"rho={args.rho} of the measured capacity, HBM budget {args.budget_gb} GB, "
+                                  f"chunks of 64 steps"},
+           "capacity_osc_steps_per_s": capacity}
+    ref = None
+    for prec, key in ((nd.ND_FP64, "fp64"), (nd.ND_FP32_BULK, "fp32_bulk")):
+        r = serve_run(nd, torch, args, reqs, states, prec, rate, stream)
+        lat = np.array(r["lat"]) * 1e3
+        rec = {"value": work / r["makespan"], "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                                           "p99": float(np.percentile(lat, 99))},
+               "chunk_ms": {"p50": float(np.percentile(r["chunk_ms"], 50)),
+                            "p99": float(np.percentile(r["chunk_ms"], 99))},
+               "makespan_s": r["makespan"], "gpu_busy_frac": r["gpu_s"] / r["makespan"]}
+        if key == "fp64":
+            ref = r["results"]
+            out["value"] = rec["value"]
+            out["ms_per_step"] = 1e3 * r["makespan"]
+            out.update({"latency_ms": rec["latency_ms"], "batch_latency_ms": rec["chunk_ms"],
+                        "makespan_s": rec["makespan_s"], "gpu_busy_frac": rec["gpu_busy_frac"]})
+        else:
+            errs = []
+            for y, yr, q in zip(r["results"], ref, reqs):
+                nv = 1 if q["model"] == "kur" else 2
+                a, b = y.reshape(nv, -1), yr.reshape(nv, -1)
+                errs.append(max(float(np.max(np.abs(a[v] - b[v])) / np.max(np.abs(b[v]))) for v in range(nv)))
+            rec["max_normwise_error_vs_fp64"] = max(errs)
+            out["fp32_bulk"] = rec
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -260,6 +382,9 @@ def main():
         torch.cuda.synchronize()
         sec = ev0.elapsed_time(ev1) / 1e3 / 3
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 4, "copy_GBps": 2 * nbytes / sec / 1e9}))
+        return
+    if args.workload == "serve":
+        main_serve(nd, torch, args, stream)
         return
     wl = Workload(args, nd)
     osc_per_step = args.batch * wl.n * args.horizon

@@ -168,6 +168,20 @@ typedef struct nd_kernel_config {
 nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
 nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);
 
+/* Autotuner.  Times every candidate kernel configuration for problem p (ring: tile sizes;
+ * cube: x/y/z tile extents; CSR: lanes per row) on `steps` RK4 steps of size dt from state y0
+ * (host, nvars*n doubles), keeps the fastest in a process-wide cache keyed by (device
+ * architecture, model, topology, precision, log2 n, coupling-width bucket, half-width), and
+ * returns it.  nd_create uses a cached entry for every later problem of the same key.  The
+ * paper tunes its own knobs (CUDA streams per GPU, MPI partitions) by hand (Sec. III.E-F).
+ * best_ms (may be NULL) receives the best time per step in milliseconds. */
+nd_status nd_tune(const nd_problem* p, const double* y0, int64_t len, double dt, int32_t steps, void* stream,
+                  nd_kernel_config* best, double* best_ms);
+/* Read / write the cache as text, one entry per line (an existing file is replaced). */
+nd_status nd_tune_load(const char* path);
+nd_status nd_tune_save(const char* path);
+nd_status nd_tune_clear(void);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of many independent simulations on one GPU.  The paper
  * runs many small unconnected sub-networks in one run for throughput (Sec.

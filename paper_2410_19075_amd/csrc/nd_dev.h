@@ -88,21 +88,42 @@ __device__ __forceinline__ void lds_barrier() {
 // ---------------------------------------------------------------- wave/block
 // All reductions below use a fixed combination tree, so every lane and every
 // launch produces bitwise identical sums for identical inputs.
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;  // identical in all lanes: IEEE addition is commutative
+// Cross-lane moves of a double through DPP (data-parallel primitives): each half
+// is moved with the same control; lanes whose source is outside the pattern,
+// or whose row / bank is masked off, receive 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, BANK_MASK, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Inclusive scan over the 64 lanes: shifts of 1, 2, 4, 8 inside each row of 16
+// lanes, then the row totals are carried by the row broadcasts of lanes 15 and
+// 31.  A fixed combination tree, so the result is deterministic.
 __device__ __forceinline__ double wave_incl_scan(double x) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        double t = __shfl_up(x, d, kWave);
-        if (lane >= d) x += t;
-    }
+    x += dpp_move<0x111>(x);          // row_shr:1
+    x += dpp_move<0x112>(x);          // row_shr:2
+    x += dpp_move<0x114>(x);          // row_shr:4
+    x += dpp_move<0x118>(x);          // row_shr:8
+    x += dpp_move<0x142, 0xa>(x);     // row_bcast:15 into rows 1 and 3
+    x += dpp_move<0x143, 0xc>(x);     // row_bcast:31 into rows 2 and 3
     return x;
 }
+
+// Exclusive value of an inclusive scan: the previous lane's value (lane 0: 0).
+__device__ __forceinline__ double wave_shift_up1(double x) { return dpp_move<0x138>(x); }  // wave_shr:1
+
+__device__ __forceinline__ double wave_bcast(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave, identical in every lane (the scan's last lane, broadcast).
+__device__ __forceinline__ double wave_sum(double x) { return wave_bcast(wave_incl_scan(x), kWave - 1); }
 
 // Sum NV values over the block (result in every thread). lds: NV * (BS/64) doubles.
 template <int BS, int NV>
@@ -139,8 +160,7 @@ __device__ __forceinline__ void block_sum_and_exscan(double (&r)[NR], double (&s
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         incl[q] = wave_incl_scan(s[q]);
-        double t = __shfl_up(incl[q], 1, kWave);
-        excl[q] = lane == 0 ? 0.0 : t;
+        excl[q] = wave_shift_up1(incl[q]);
     }
     if (lane == 0) {
 #pragma unroll

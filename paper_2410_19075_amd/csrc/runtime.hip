@@ -188,6 +188,8 @@ nd_status Net::create(const nd_problem* pr) {
     prob.weight = nullptr;
     prob.per_elem = nullptr;
     cfg = default_config(pr);
+    nd_kernel_config tuned;
+    if (tuned_config(pr, &tuned)) cfg = tuned;
     const int64_t V = nvars_of(pr->model), n = pr->n, kb = bulk_bytes(pr->precision);
     std::memset(&tmpl, 0, sizeof tmpl);
     NetDesc& d = tmpl;

@@ -87,6 +87,10 @@ _sig = {
     "nd_server_cancel": [_c_vp, _c_i64],
     "nd_server_stats": [_c_vp, _P(nd_server_counters)],
     "nd_server_destroy": [_c_vp],
+    "nd_tune": [_P(nd_problem), _c_vp, _c_i64, _c_dbl, _c_i32, _c_vp, _P(nd_kernel_config), _P(_c_dbl)],
+    "nd_tune_load": [ctypes.c_char_p],
+    "nd_tune_save": [ctypes.c_char_p],
+    "nd_tune_clear": [],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -272,6 +276,28 @@ def nd_server_stats(s):
 
 def nd_server_destroy(s):
     _check(_lib.nd_server_destroy(s), "nd_server_destroy")
+
+
+def nd_tune(p, y0, dt, steps, stream=None):
+    """Returns (best nd_kernel_config, ms per step)."""
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    best = nd_kernel_config()
+    ms = _c_dbl()
+    _check(_lib.nd_tune(ctypes.byref(p), y0.ctypes.data, y0.size, float(dt), int(steps), _stream(stream),
+                        ctypes.byref(best), ctypes.byref(ms)), "nd_tune")
+    return best, ms.value
+
+
+def nd_tune_load(path):
+    _check(_lib.nd_tune_load(os.fsencode(path)), "nd_tune_load")
+
+
+def nd_tune_save(path):
+    _check(_lib.nd_tune_save(os.fsencode(path)), "nd_tune_save")
+
+
+def nd_tune_clear():
+    _check(_lib.nd_tune_clear(), "nd_tune_clear")
 
 
 def nd_status_str(s):

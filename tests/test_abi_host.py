@@ -127,3 +127,11 @@ def test_patch_is_planted():
     big = counts.max()
     # a ball of radius 4 holds 257 lattice points
     assert big == 257
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -58,3 +58,21 @@ def test_cancel_queued_request_without_gpu_work():
         assert ei.value.status == nd.ND_ERR_NOT_READY
     finally:
         nd.nd_server_destroy(s)
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    f = tmp_path / "tune.txt"
+    f.write_text("# arch model topo precision log2n width h tile block grid chunk tile_y tile_z\n"
+                 "gfx950 1 0 0 16 2 0 512 128 0 64 0 0\n"
+                 "gfx950 0 1 1 23 0 4 24 832 0 32 24 100\n")
+    nd.nd_tune_clear()
+    nd.nd_tune_load(str(f))
+    out = tmp_path / "out.txt"
+    nd.nd_tune_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert sorted(lines) == sorted(["gfx950 0 1 1 23 0 4 24 832 0 32 24 100", "gfx950 1 0 0 16 2 0 512 128 0 64 0 0"])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 1 0\n")
+    with pytest.raises(nd.NDError):
+        nd.nd_tune_load(str(bad))
+    nd.nd_tune_clear()
