@@ -299,6 +299,168 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
     }
 }
 
+// ---------------------------------------------------------------- resident
+// Rings small enough for one workgroup (n <= BS*EPT): the state stays in
+// registers for a whole chunk of steps.  Per stage the mapped values are
+// prefix-summed in LDS (double) and every window sum is a difference of two
+// prefix values (wrapping through the ring total); no global memory traffic
+// between stages.  Each thread owns EPT consecutive elements.
+template <int MODEL, class KT, int BS, int EPT, bool MV>
+__global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                      const int* __restrict__ nwork_p, int chunk) {
+    using M = RingModel<MODEL, KT>;
+    constexpr int V = M::V, T = BS * EPT, NW = BS / kWave;
+    extern __shared__ double pf[];  // [2][T]: inclusive prefix sums of the two map components
+    __shared__ double lds[8 * NW];
+    const int nwork = *nwork_p;
+    const int tid = threadIdx.x;
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (d.nsteps <= 0) continue;
+        const int steps = (int)min((int64_t)chunk, d.nsteps);
+        const int n = (int)d.n, P = (int)d.P;
+        const double dt = d.dt;
+        const ND_GLOBAL double* yin = gp(d.y[d.ypar]);
+        double y[EPT][V], acc[EPT][V], kp[EPT][V], dth[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid * EPT + e;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                y[e][v] = i < n ? yin[(int64_t)v * n + i] : 0.0;
+                acc[e][v] = 0.0;
+                kp[e][v] = 0.0;
+            }
+            dth[e] = 0.0;
+        }
+        for (int j = 0; j < steps; ++j) {
+            const int64_t g = d.g0 + j;
+#pragma unroll
+            for (int s = 1; s <= 4; ++s) {
+                const double cdt = s == 4 ? dt : 0.5 * dt;
+                double z[EPT][V];
+                double2 x[EPT];
+                double tot[2] = {0.0, 0.0};
+                double ru[2] = {0.0, 0.0};  // FHN: unit phase vectors for R
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = tid * EPT + e;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) z[e][v] = s == 1 ? y[e][v] : fma(cdt, kp[e][v], y[e][v]);
+                    x[e] = M::map(z[e]);
+                    if (i >= n) x[e] = make_double2(0.0, 0.0);
+                    tot[0] += x[e].x;
+                    tot[1] += x[e].y;
+                    // thread-local inclusive prefix, completed below with the
+                    // block-exclusive offset of this thread
+                    pf[tid * EPT + e] = tot[0];
+                    pf[T + tid * EPT + e] = tot[1];
+                    if constexpr (MODEL == ND_FHN) {
+                        if (s == 1 && i < n) {
+                            const double r = sqrt(z[e][0] * z[e][0] + z[e][1] * z[e][1]);
+                            ru[0] += z[e][0] / r;
+                            ru[1] += z[e][1] / r;
+                        }
+                    }
+                }
+                block_sum_and_exscan<BS, 2, 2>(ru, tot, lds);
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    pf[tid * EPT + e] = tot[0] + pf[tid * EPT + e];
+                    pf[T + tid * EPT + e] = tot[1] + pf[T + tid * EPT + e];
+                }
+                lds_barrier();
+                const double t0 = pf[n - 1], t1 = pf[T + n - 1];
+                if (s == 1 && tid == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
+                    const double c = MODEL == ND_FHN ? ru[0] : t0, sn = MODEL == ND_FHN ? ru[1] : t1;
+                    gp(d.R)[g / d.r_every] = sqrt(c * c + sn * sn) / (double)n;
+                }
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = tid * EPT + e;
+                    if (i < n) {
+                        // prefix(k) = sum_{j<k} x_j; window [i-P, i+P] through the ring total
+                        const int lo = i - P, hi = i + P + 1;
+                        auto pre = [&](int k, int c) { return k == 0 ? 0.0 : pf[c * T + k - 1]; };
+                        double w0, w1;
+                        if (lo < 0) {
+                            w0 = pre(hi, 0) + (t0 - pre(lo + n, 0));
+                            w1 = pre(hi, 1) + (t1 - pre(lo + n, 1));
+                        } else if (hi > n) {
+                            w0 = (t0 - pre(lo, 0)) + pre(hi - n, 0);
+                            w1 = (t1 - pre(lo, 1)) + pre(hi - n, 1);
+                        } else {
+                            w0 = pre(hi, 0) - pre(lo, 0);
+                            w1 = pre(hi, 1) - pre(lo, 1);
+                        }
+                        const double2 W = make_double2(w0 - x[e].x, w1 - x[e].y);
+                        double k[V];
+                        M::rhs(d, z[e], x[e], W, k);
+                        if (MV && (d.obs & OBS_MV) && g == d.mv_start && s == 1 && MODEL == ND_KURAMOTO)
+                            gp(d.mv)[i] = y[e][0];
+                        double yo[V];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const double kk = kq<KT>(k[v]);
+                            if (s == 2) acc[e][v] = fma(dt / 3.0, kk, fma(dt / 6.0, kp[e][v], y[e][v]));
+                            yo[v] = s == 4 ? fma(dt / 6.0, kk, fma(dt / 3.0, kp[e][v], acc[e][v])) : y[e][v];
+                            kp[e][v] = kk;
+                        }
+                        if constexpr (MODEL == ND_FHN) {
+                            if (MV && s == 4 && (d.obs & OBS_MV) && g >= d.mv_start) {
+                                const double uo = y[e][0], vo = y[e][1], un = yo[0], vn = yo[1];
+                                dth[e] += atan2(uo * vn - vo * un, uo * un + vo * vn);
+                            }
+                        }
+#pragma unroll
+                        for (int v = 0; v < V; ++v) y[e][v] = yo[v];
+                    }
+                }
+                lds_barrier();
+            }
+        }
+        if constexpr (MODEL == ND_FHN) {
+            // unwrapped-phase increments of this chunk's steps at or after mv_start
+            if (MV && (d.obs & OBS_MV) && d.mv_start < d.g0 + steps) {
+                const bool first = d.mv_start >= d.g0;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = tid * EPT + e;
+                    if (i < n) gp(d.mv)[i] = (first ? 0.0 : gp(d.mv)[i]) + dth[e];
+                }
+            }
+        }
+        // write the state back into the buffer the chunk ends on, plus the map
+        // sums the epilogue turns into the final R
+        ND_GLOBAL double* yout = gp(d.y[(d.ypar + steps) & 1]);
+        double sums[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid * EPT + e;
+            if (i < n) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) yout[(int64_t)v * n + i] = y[e][v];
+                const double2 xm = M::map(y[e]);
+                sums[0] += xm.x;
+                sums[1] += xm.y;
+                if constexpr (MODEL == ND_FHN) {
+                    const double r = sqrt(y[e][0] * y[e][0] + y[e][1] * y[e][1]);
+                    sums[2] += y[e][0] / r;
+                    sums[3] += y[e][1] / r;
+                }
+            }
+        }
+        block_sum<BS, 4>(sums, lds);
+        if (tid == 0) {
+            gp(d.tsum[0])[0] = sums[0];
+            gp(d.tsum[0])[1] = sums[1];
+            gp(d.rsum)[0] = sums[2];
+            gp(d.rsum)[1] = sums[3];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- epilogue
 // After the last step of a run: R at the final step and the mean phase velocity.
 // `chunk` is the number of steps of the chunk that just ran.
@@ -326,7 +488,8 @@ __global__ __launch_bounds__(BS) void k_ring_epilogue(const NetDesc* __restrict_
         }
         if (d.obs & OBS_MV) {
             const int64_t t0 = (int64_t)wk.y * T;
-            const int cnt = (int)min((int64_t)T, n - t0);
+            // a ring held by one work item (resident kernel) is finalised whole
+            const int cnt = d.G == 1 ? (int)n : (int)min((int64_t)T, n - t0);
             const double* y = d.y[par];
             for (int m = threadIdx.x; m < cnt; m += BS) {
                 const int64_t i = t0 + m;
@@ -357,12 +520,29 @@ static RingLaunch ring_entry() {
     r.epilogue = k_ring_epilogue<MODEL, KT, BS, EPT>;
     r.bs = BS;
     r.tile = BS * EPT;
+    r.resident = nullptr;
+    r.resident_mv = nullptr;
+    r.smem = 0;
+    return r;
+}
+
+template <int MODEL, class KT, int BS, int EPT>
+static RingLaunch resident_entry() {
+    RingLaunch r = ring_entry<MODEL, KT, 64, 4>();  // prologue / epilogue (G = 1)
+    r.resident = k_ring_resident<MODEL, KT, BS, EPT, false>;
+    r.resident_mv = k_ring_resident<MODEL, KT, BS, EPT, true>;
+    r.bs = BS;
+    r.tile = -BS * EPT;
+    r.smem = 2 * BS * EPT * sizeof(double);
     return r;
 }
 
 template <int MODEL, class KT>
 static bool ring_pick(int tile, RingLaunch* out) {
     switch (tile) {
+        case -1024: *out = resident_entry<MODEL, KT, 256, 4>(); return true;
+        case -2048: *out = resident_entry<MODEL, KT, 256, 8>(); return true;
+        case -4096: *out = resident_entry<MODEL, KT, 512, 8>(); return true;
         case 1024: *out = ring_entry<MODEL, KT, 256, 4>(); return true;
         case 2048: *out = ring_entry<MODEL, KT, 256, 8>(); return true;
         case 512: *out = ring_entry<MODEL, KT, 128, 4>(); return true;
@@ -390,6 +570,17 @@ hipError_t ring_launch_stage(const RingLaunch& L, int grid, hipStream_t s, NetDe
                        nwork, j);
     return hipGetLastError();
 }
+hipError_t ring_launch_resident(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                                const int* nwork, int chunk, bool mv) {
+    auto f = mv ? L.resident_mv : L.resident;
+    if (L.smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.smem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(f, dim3(grid), dim3(L.bs), L.smem, s, D, work, nwork, chunk);
+    return hipGetLastError();
+}
+
 hipError_t ring_launch_epilogue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                 const int* nwork, int chunk) {
     hipLaunchKernelGGL(L.epilogue, dim3(grid), dim3(L.bs), 0, s, D, work, nwork, chunk);

@@ -78,13 +78,18 @@ struct RingLaunch {
     void (*stage[4])(const NetDesc*, const int2*, const int*, int);
     void (*stage_mv[4])(const NetDesc*, const int2*, const int*, int);  // with mean-velocity recording
     void (*epilogue)(const NetDesc*, const int2*, const int*, int);
+    void (*resident)(const NetDesc*, const int2*, const int*, int);  // whole ring per workgroup
+    void (*resident_mv)(const NetDesc*, const int2*, const int*, int);
     int bs, tile;
+    size_t smem;
 };
 bool ring_select(int model, int prec, int tile, RingLaunch* out);
 hipError_t ring_launch_prologue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                 const int* nwork);
 hipError_t ring_launch_stage(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                              const int* nwork, int stage, int j, bool mv);
+hipError_t ring_launch_resident(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                                const int* nwork, int chunk, bool mv);
 hipError_t ring_launch_epilogue(const RingLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                 const int* nwork, int chunk);
 

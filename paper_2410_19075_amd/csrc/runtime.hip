@@ -106,7 +106,12 @@ nd_kernel_config default_config(const nd_problem* p) {
     c.grid = 0;
     c.chunk = 64;
     if (p->topo == ND_RING) {
-        c.tile = p->n <= (int64_t(1) << 18) ? 256 : (p->n <= (int64_t(1) << 20) ? 512 : 1024);
+        // rings up to 4096 elements stay resident in one workgroup (negative tile =
+        // resident capacity); larger rings use the per-stage tiled kernel
+        if (p->n <= 1024) c.tile = -1024;
+        else if (p->n <= 2048) c.tile = -2048;
+        else if (p->n <= 4096) c.tile = -4096;
+        else c.tile = p->n <= (int64_t(1) << 18) ? 256 : (p->n <= (int64_t(1) << 20) ? 512 : 1024);
         c.block = ring_block(c.tile);
     } else if (p->topo == ND_CUBE3D) {
         // 20 x 20 outputs per plane (28 x 28 halo columns at h = 4) and 40-plane
@@ -128,11 +133,14 @@ nd_kernel_config default_config(const nd_problem* p) {
     return c;
 }
 
-int ring_block(int tile) { return tile == 512 ? 128 : (tile == 256 ? 64 : 256); }
+int ring_block(int tile) {
+    if (tile < 0) return tile == -4096 ? 512 : 256;
+    return tile == 512 ? 128 : (tile == 256 ? 64 : 256);
+}
 
 static int64_t bulk_bytes(int prec) { return prec == ND_FP64 ? 8 : 4; }
 
-static int64_t ring_tiles(int64_t n, int tile) { return (n + tile - 1) / tile; }
+static int64_t ring_tiles(int64_t n, int tile) { return tile < 0 ? 1 : (n + tile - 1) / tile; }
 
 int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
     const int64_t V = nvars_of(p->model), n = p->n, kb = bulk_bytes(p->precision);
@@ -378,11 +386,17 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
     if (g.topo == ND_RING) {
         RingLaunch L;
         if (!ring_select(g.model, g.prec, g.tile, &L)) return fail(ND_ERR_UNSUPPORTED, "no ring kernel for tile %d", g.tile);
-        if ((e = ring_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess) return hip_fail(e, "ring prologue");
-        for (int j = 0; j < chunk; ++j)
-            for (int s = 1; s <= 4; ++s)
-                if ((e = ring_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
-                    return hip_fail(e, "ring stage");
+        if (g.tile < 0) {
+            if ((e = ring_launch_resident(L, grid, st, g.desc, g.work, g.nwork, chunk, g.mv)) != hipSuccess)
+                return hip_fail(e, "ring resident");
+        } else {
+            if ((e = ring_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess)
+                return hip_fail(e, "ring prologue");
+            for (int j = 0; j < chunk; ++j)
+                for (int s = 1; s <= 4; ++s)
+                    if ((e = ring_launch_stage(L, grid, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
+                        return hip_fail(e, "ring stage");
+        }
         if ((e = ring_launch_epilogue(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "ring epilogue");
     } else if (g.topo == ND_CUBE3D) {
@@ -646,6 +660,8 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         RingLaunch L;
         if (!ring_select(p.model, p.precision, c.tile, &L))
             return fail(ND_ERR_INVALID_ARG, "no ring kernel for tile %d", c.tile);
+        if (c.tile < 0 && -c.tile < p.n)
+            return fail(ND_ERR_INVALID_ARG, "a resident ring needs n <= %d", -c.tile);
     } else if (p.topo == ND_CUBE3D) {
         const int h = (int)p.radius;
         if (c.tile < 1 || c.tile_y < 1 || c.tile_z < 1)

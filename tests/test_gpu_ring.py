@@ -72,16 +72,23 @@ def test_c1_kuramoto_ring_fp64_parity(nd, seed):
 
 
 @pytest.mark.parametrize("n,P", [(1500, 1), (1500, 749), (3000, 600), (5000, 77), (4097, 2048), (2049, 1000),
-                                 (1024, 511), (333, 100)])
+                                 (1024, 511), (333, 100), (4096, 1), (7, 3)])
 @pytest.mark.parametrize("model", ["kur", "fhn"])
-def test_ring_tiles_and_ragged_tails_fp64(nd, n, P, model):
-    """Several tiles, a ragged last tile, windows from P = 1 to (n-1)/2."""
-    print(f"case tiles model={model} n={n} P={P}", flush=True)
+@pytest.mark.parametrize("path", ["default", "tiled256"])
+def test_ring_tiles_and_ragged_tails_fp64(nd, n, P, model, path):
+    """Several tiles, a ragged last tile, windows from P = 1 to (n-1)/2; small
+    rings run resident in one workgroup by default, 'tiled256' forces the
+    per-stage tiled kernel."""
+    print(f"case tiles model={model} n={n} P={P} path={path}", flush=True)
     if model == "kur":
         m, om, prm, y0 = nd.ND_KURAMOTO, O.KURAMOTO, [0.3, 1.0, 1.2], inputs.kuramoto_phases(n + P, n)
     else:
         m, om, prm, y0 = nd.ND_FHN, O.FHN, FHN_PRM, inputs.fhn_circle(n + P, n)
-    y, R, _ = ring_case(nd, m, n, P, prm, nd.ND_FP64, y0, 0.01, 30, record_every=3)
+    if path == "default":
+        y, R, _ = ring_case(nd, m, n, P, prm, nd.ND_FP64, y0, 0.01, 30, record_every=3)
+    else:
+        y, R = run_with_config(nd, nd.problem(m, nd.ND_RING, n, prm, radius=P), y0, 0.01, 30, tile=256,
+                               record_every=3)
     ref, Rref, _ = O.run(O.ring(om, n, P, prm), y0, 0.01, 30, record_every=3)
     assert normwise(y, ref, O.NVARS[om]) < 1e-12
     assert np.max(np.abs(R - Rref)) < 1e-12
@@ -198,12 +205,12 @@ def test_batch_equals_solo_bitwise(nd):
             nd.nd_destroy(h)
 
 
-@pytest.mark.parametrize("tile", [256, 512, 1024, 2048])
+@pytest.mark.parametrize("tile", [256, 512, 1024, 2048, -4096])
 @pytest.mark.parametrize("grid,chunk", [(0, 64), (24, 16), (8, 5)])
 def test_tile_grid_and_chunk_configs(nd, tile, grid, chunk):
     """Every tile size, persistent grids smaller than the work and graph chunks
     that do not divide the step count give the oracle's result."""
-    n, P = 9001, 3150
+    n, P = (9001, 3150) if tile > 0 else (4000, 1400)
     y0 = inputs.fhn_circle(11, n)
     print(f"case cfg tile={tile} grid={grid} chunk={chunk}", flush=True)
     p = nd.problem(nd.ND_FHN, nd.ND_RING, n, FHN_PRM, radius=P)
