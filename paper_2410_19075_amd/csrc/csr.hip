@@ -105,17 +105,24 @@ __global__ __launch_bounds__(256) void k_csr_stage(const NetDesc* __restrict__ D
         // ---- phase A: synaptic sums, L lanes per row
         for (int r = grp; r < nrows; r += NG) {
             const int64_t b = rp[r0 + r], e = rp[r0 + r + 1];
-            double a0 = 0.0, a1 = 0.0;
-            int64_t q = b + lane;
-            // two independent gathers in flight per lane
-            for (; q + L < e; q += 2 * L) {
-                const int c0 = col[q], c1 = col[q + L];
-                const double w0 = (double)wt[q], w1 = (double)wt[q + L];
-                a0 += w0 * (double)sin_[c0];
-                a1 += w1 * (double)sin_[c1];
+            double a = 0.0;
+            // four independent gathers in flight per lane: the column and weight
+            // loads of a group of 4L edges are issued first (clamped indices,
+            // zero weight past the row end), then the activations they select
+            for (int64_t q0 = b + lane; q0 < e; q0 += 4 * L) {
+                int c[4];
+                double wv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = q0 + u * L;
+                    const bool ok = q < e;
+                    const int64_t qq = ok ? q : q0;
+                    c[u] = col[qq];
+                    wv[u] = ok ? (double)wt[qq] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a += wv[u] * (double)sin_[c[u]];
             }
-            if (q < e) a0 += (double)wt[q] * (double)sin_[col[q]];
-            double a = a0 + a1;
 #pragma unroll
             for (int o = L / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
             if (lane == 0) gsum[r] = a;

@@ -528,7 +528,13 @@ static RingLaunch ring_entry() {
 
 template <int MODEL, class KT, int BS, int EPT>
 static RingLaunch resident_entry() {
-    RingLaunch r = ring_entry<MODEL, KT, 64, 4>();  // prologue / epilogue (G = 1)
+    // every kernel of this entry is launched with BS threads, so each one is
+    // instantiated for BS (launch bounds and LDS sizing follow the block size)
+    RingLaunch r;
+    r.prologue = k_ring_prologue<MODEL, KT, BS, EPT>;
+    for (auto& f : r.stage) f = nullptr;
+    for (auto& f : r.stage_mv) f = nullptr;
+    r.epilogue = k_ring_epilogue<MODEL, KT, BS, EPT>;
     r.resident = k_ring_resident<MODEL, KT, BS, EPT, false>;
     r.resident_mv = k_ring_resident<MODEL, KT, BS, EPT, true>;
     r.bs = BS;

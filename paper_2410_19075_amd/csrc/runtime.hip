@@ -387,6 +387,7 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
         RingLaunch L;
         if (!ring_select(g.model, g.prec, g.tile, &L)) return fail(ND_ERR_UNSUPPORTED, "no ring kernel for tile %d", g.tile);
         if (g.tile < 0) {
+            if (!L.resident || L.bs * 4 > -g.tile) return fail(ND_ERR_UNSUPPORTED, "bad resident ring entry");
             if ((e = ring_launch_resident(L, grid, st, g.desc, g.work, g.nwork, chunk, g.mv)) != hipSuccess)
                 return hip_fail(e, "ring resident");
         } else {

@@ -61,6 +61,14 @@ class nd_server_counters(ctypes.Structure):
 ND_REQ_QUEUED, ND_REQ_RUNNING, ND_REQ_DONE, ND_REQ_FAILED, ND_REQ_CANCELLED = range(5)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnd.so")
+# One HIP runtime per process: PyTorch ships its own libamdhip64 / HSA runtime and
+# references them under names that differ from libnd.so's, so if libnd.so were
+# loaded first the process would hold two runtimes and the second could not open
+# the device.  Loading torch first makes libnd.so bind to torch's runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is part of the supported stack
+    pass
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libnd.so is not built ({LIB_PATH}); run python -m paper_2410_19075_amd.build")
 _lib = ctypes.CDLL(LIB_PATH)
