@@ -162,7 +162,8 @@ typedef struct nd_kernel_config {
     int32_t grid;   /* persistent grid size in workgroups; 0 = one workgroup per work item */
     int32_t chunk;  /* steps per captured graph chunk */
     int32_t tile_y; /* cube: output tile extent along y ((tile+2h)*(tile_y+2h) <= 1024);
-                       CSR: lanes per row (4..64, power of two) */
+                       CSR: edges each thread streams per chunk (2, 4, 8 or 16; results
+                       do not depend on it) */
     int32_t tile_z; /* cube: planes per work item */
 } nd_kernel_config;
 
@@ -170,7 +171,7 @@ nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
 nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);
 
 /* Autotuner.  Times every candidate kernel configuration for problem p (ring: tile sizes;
- * cube: x/y/z tile extents; CSR: lanes per row) on `steps` RK4 steps of size dt from state y0
+ * cube: x/y/z tile extents; CSR: edges per thread) on `steps` RK4 steps of size dt from state y0
  * (host, nvars*n doubles), keeps the fastest in a process-wide cache keyed by (device
  * architecture, model, topology, precision, log2 n, coupling-width bucket, half-width), and
  * returns it.  nd_create uses a cached entry for every later problem of the same key.  The

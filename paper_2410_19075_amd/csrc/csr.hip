@@ -11,17 +11,20 @@
 // Per stage the activations s_j = S(V_j) of the stage values are computed
 // once per neuron by the previous stage (the exchanged quantity), and each
 // work item (256 target rows) does:
-//   phase A: groups of L lanes walk the in-edges of one row each, accumulate
-//            w_e s_src(e) in double, reduce within the group (fixed tree),
-//            row sums to LDS;
-//   phase B: one thread per neuron evaluates the HH right-hand side, does the
-//            13-access RK bookkeeping and writes S of its next stage value.
+//   phase A: the in-edges are split into 8 source blocks (one per XCD); per
+//            (row tile, block) the tile's edges are streamed coalesced, the
+//            products w_e s_src(e) are formed in double and every row's
+//            products are added in edge order, giving one partial per block;
+//   phase B: one thread per neuron adds the 8 partials in block order,
+//            evaluates the HH right-hand side, does the 13-access RK
+//            bookkeeping and writes S of its next stage value.
 #include "models.h"
 #include "runtime.h"
 
 namespace nd {
 
 constexpr int kCsrRows = 256;
+constexpr int kSrcBlocks = kCsrSourceBlocks;  // source blocks, one per XCD
 
 // x / (1 - exp(-x)) with the removable singularity at 0 taken by its series
 template <class T>
@@ -60,153 +63,179 @@ template <class KT>
 __global__ __launch_bounds__(256) void k_csr_prologue(const NetDesc* __restrict__ D, const int2* __restrict__ work,
                                                      const int* __restrict__ nwork_p) {
     const int nwork = *nwork_p;
-    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const int2 wk = work[w];
+    // one row tile per workgroup: the tile's work items are 8 consecutive
+    // entries starting at a multiple of 8; spreading the tiles over the
+    // workgroups (rather than taking every 8th workgroup) keeps all XCDs busy
+    for (int v = blockIdx.x; v < nwork / kSrcBlocks; v += gridDim.x) {
+        const int2 wk = work[v * kSrcBlocks];
         const NetDesc& d = D[wk.x];
         if (d.g0 != 0 || d.nsteps <= 0) continue;
-        const int64_t i = (int64_t)wk.y * kCsrRows + threadIdx.x;
+        const int64_t i = (int64_t)(wk.y / kSrcBlocks) * kCsrRows + threadIdx.x;
         if (i < d.n) gp((KT*)d.sx[0])[i] = (KT)synapse<KT>(d.p, gp(d.y[d.ypar])[i]);
     }
 }
 
-template <class KT, int STAGE, int L>
-__global__ __launch_bounds__(256) void k_csr_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
-                                                  const int* __restrict__ nwork_p, int j) {
-    constexpr int stage = STAGE;
-    constexpr int BS = 256;
-    __shared__ double gsum[kCsrRows];
+// Phase A: synaptic partial sums of one source block for 256 target rows.
+// Work item (row tile t, block x) is entry 8t + x; with the work map aligned
+// to multiples of 8 and the grid a multiple of 8, block x always lands on XCD x
+// (workgroups go to the XCDs round-robin), whose L2 then holds that block's
+// slice of the activations.
+// The tile's in-edges of block x are one contiguous range of the block-major
+// edge arrays.  It is streamed in chunks of 256*U edges: every thread loads U
+// edges (coalesced col and w, then the U gathers, all in flight together) and
+// leaves the products in LDS; then the owner thread of each row adds its
+// row's products in ascending edge order.  The sum of a row therefore does not
+// depend on U or on the chunking.
+template <class KT, int U>
+__global__ __launch_bounds__(256) void k_csr_gather(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                   const int* __restrict__ nwork_p, int stage, int j) {
+    constexpr int BS = 256, CH = BS * U;
+    __shared__ double prod[CH];
+    __shared__ int64_t rb[kCsrRows + 1];
     const int nwork = *nwork_p;
-    const int nvb = ((nwork + 7) >> 3) << 3;
     const int tid = threadIdx.x;
-    const int lane = tid & (L - 1), grp = tid / L;
-    constexpr int NG = BS / L;
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int wi = xcd_work(vb, nwork);
-        if (wi < 0) continue;
-        const int2 wk = work[wi];
+    for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (j >= d.nsteps) continue;  // uniform over the block
+        const int64_t n = d.n;
+        const int x = wk.y % kSrcBlocks;
+        const int64_t r0 = (int64_t)(wk.y / kSrcBlocks) * kCsrRows;
+        const int nrows = (int)min((int64_t)kCsrRows, n - r0);
+        const ND_GLOBAL int64_t* __restrict__ bp = gp(d.row_ptr) + (int64_t)x * (n + 1) + r0;
+        const ND_GLOBAL int32_t* __restrict__ col = gp(d.col);
+        const ND_GLOBAL KT* __restrict__ wt = gp((const KT*)d.w);
+        const ND_GLOBAL KT* __restrict__ sin_ = gp((const KT*)d.sx[(stage - 1) & 1]);
+        if (tid <= nrows) rb[tid] = bp[tid];
+        if (tid == 0 && nrows == BS) rb[BS] = bp[BS];
+        __syncthreads();
+        const int64_t E0 = rb[0], E1 = rb[nrows];
+        const int64_t mb = tid < nrows ? rb[tid] : E1, me = tid < nrows ? rb[tid + 1] : E1;
+        double a = 0.0;
+        for (int64_t c0 = E0; c0 < E1; c0 += CH) {
+            int c[U];
+            double wv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = c0 + u * BS + tid;
+                const bool ok = q < E1;
+                c[u] = col[ok ? q : E0];
+                wv[u] = ok ? (double)wt[q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) prod[u * BS + tid] = wv[u] * (double)sin_[c[u]];
+            __syncthreads();
+            const int64_t lo = max(mb, c0), hi = min(me, c0 + CH);
+            for (int64_t q = lo; q < hi; ++q) a += prod[q - c0];
+            __syncthreads();
+        }
+        if (tid < nrows) gp(d.acc_part)[(int64_t)x * n + r0 + tid] = a;
+    }
+}
+
+// Phase B: one thread per neuron sums the source-block partials (fixed order),
+// evaluates the HH right-hand side, does the 13-access RK bookkeeping and
+// writes S of its next stage value.
+template <class KT, int STAGE>
+__global__ __launch_bounds__(256) void k_csr_update(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                   const int* __restrict__ nwork_p, int j) {
+    constexpr int stage = STAGE;
+    const int nwork = *nwork_p;
+    const int tid = threadIdx.x;
+    for (int v = blockIdx.x; v < nwork / kSrcBlocks; v += gridDim.x) {  // one row tile per workgroup
+        const int2 wk = work[v * kSrcBlocks];
         const NetDesc& d = D[wk.x];
         if (j >= d.nsteps) continue;
         const int64_t n = d.n;
-        const int64_t r0 = (int64_t)wk.y * kCsrRows;
-        const int nrows = (int)min((int64_t)kCsrRows, n - r0);
+        const int64_t i = (int64_t)(wk.y / kSrcBlocks) * kCsrRows + tid;
+        if (i >= n) continue;
         const int par = (d.ypar + j) & 1;
         const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
         const ND_GLOBAL KT* __restrict__ kp =
             stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
-        const ND_GLOBAL KT* __restrict__ sin_ = gp((const KT*)d.sx[(stage - 1) & 1]);
-        ND_GLOBAL KT* __restrict__ sout = gp((KT*)d.sx[stage & 1]);
-        const ND_GLOBAL int64_t* __restrict__ rp = gp(d.row_ptr);
-        const ND_GLOBAL int32_t* __restrict__ col = gp(d.col);
-        const ND_GLOBAL KT* __restrict__ wt = gp((const KT*)d.w);
-        const ND_GLOBAL double* __restrict__ accp = gp(d.acc);
+        const ND_GLOBAL double* __restrict__ part = gp(d.acc_part);
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
-
-        // ---- phase A: synaptic sums, L lanes per row
-        for (int r = grp; r < nrows; r += NG) {
-            const int64_t b = rp[r0 + r], e = rp[r0 + r + 1];
-            double a = 0.0;
-            // four independent gathers in flight per lane: the column and weight
-            // loads of a group of 4L edges are issued first (clamped indices,
-            // zero weight past the row end), then the activations they select
-            for (int64_t q0 = b + lane; q0 < e; q0 += 4 * L) {
-                int c[4];
-                double wv[4];
+        double G = 0.0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t q = q0 + u * L;
-                    const bool ok = q < e;
-                    const int64_t qq = ok ? q : q0;
-                    c[u] = col[qq];
-                    wv[u] = ok ? (double)wt[qq] : 0.0;
-                }
+        for (int x = 0; x < kSrcBlocks; ++x) G += part[(int64_t)x * n + i];
+        double z[4], yv[4], kv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a += wv[u] * (double)sin_[c[u]];
-            }
-#pragma unroll
-            for (int o = L / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, kWave);
-            if (lane == 0) gsum[r] = a;
+        for (int v = 0; v < 4; ++v) {
+            const int64_t q = v * n + i;
+            yv[v] = y[q];
+            if (stage != 1) kv[v] = (double)kp[q];
+            z[v] = stage == 1 ? yv[v] : fma(cdt, kv[v], yv[v]);
         }
-        __syncthreads();
-
-        // ---- phase B: one neuron per thread
-        if (tid < nrows) {
-            const int64_t i = r0 + tid;
-            double z[4], yv[4], kv[4] = {0.0, 0.0, 0.0, 0.0};
+        double k[4];
+        if constexpr (sizeof(KT) == 8)
+            hh_rhs<double>(d.p, gp(d.iapp)[i], z, G, k);
+        else
+            hh_rhs<float>(d.p, gp(d.iapp)[i], z, G, k);
+        double zn[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t q = v * n + i;
-                yv[v] = y[q];
-                if (stage != 1) kv[v] = (double)kp[q];
-                z[v] = stage == 1 ? yv[v] : fma(cdt, kv[v], yv[v]);
+        for (int v = 0; v < 4; ++v) {
+            const int64_t q = v * n + i;
+            const double kk = kq<KT>(k[v]);
+            if (stage == 1) {
+                gp((KT*)d.k[0])[q] = (KT)kk;
+                zn[v] = fma(0.5 * dt, kk, yv[v]);
+            } else if (stage == 2) {
+                gp((KT*)d.k[1])[q] = (KT)kk;
+                gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[v], yv[v]));
+                zn[v] = fma(0.5 * dt, kk, yv[v]);
+            } else if (stage == 3) {
+                gp((KT*)d.k[2])[q] = (KT)kk;
+                zn[v] = fma(dt, kk, yv[v]);
+            } else {
+                const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[v], gp(d.acc)[q]));
+                gp(d.y[par ^ 1])[q] = yo;
+                zn[v] = yo;
             }
-            double k[4];
-            if constexpr (sizeof(KT) == 8)
-                hh_rhs<double>(d.p, gp(d.iapp)[i], z, gsum[tid], k);
-            else
-                hh_rhs<float>(d.p, gp(d.iapp)[i], z, gsum[tid], k);
-            double zn[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t q = v * n + i;
-                const double kk = kq<KT>(k[v]);
-                if (stage == 1) {
-                    gp((KT*)d.k[0])[q] = (KT)kk;
-                    zn[v] = fma(0.5 * dt, kk, yv[v]);
-                } else if (stage == 2) {
-                    gp((KT*)d.k[1])[q] = (KT)kk;
-                    gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[v], yv[v]));
-                    zn[v] = fma(0.5 * dt, kk, yv[v]);
-                } else if (stage == 3) {
-                    gp((KT*)d.k[2])[q] = (KT)kk;
-                    zn[v] = fma(dt, kk, yv[v]);
-                } else {
-                    const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[v], accp[q]));
-                    gp(d.y[par ^ 1])[q] = yo;
-                    zn[v] = yo;
-                }
-            }
-            sout[i] = (KT)synapse<KT>(d.p, zn[0]);
         }
-        __syncthreads();
+        gp((KT*)d.sx[stage & 1])[i] = (KT)synapse<KT>(d.p, zn[0]);
     }
 }
 
 // ------------------------------------------------------------------ launch
-template <class KT, int L>
+template <class KT, int U>
 static void csr_entry_l(CsrLaunch* r) {
-    r->stage[0] = k_csr_stage<KT, 1, L>;
-    r->stage[1] = k_csr_stage<KT, 2, L>;
-    r->stage[2] = k_csr_stage<KT, 3, L>;
-    r->stage[3] = k_csr_stage<KT, 4, L>;
+    r->gather = k_csr_gather<KT, U>;
+    r->update[0] = k_csr_update<KT, 1>;
+    r->update[1] = k_csr_update<KT, 2>;
+    r->update[2] = k_csr_update<KT, 3>;
+    r->update[3] = k_csr_update<KT, 4>;
     r->prologue = k_csr_prologue<KT>;
 }
 
 template <class KT>
-static bool csr_entry(int lanes, CsrLaunch* r) {
-    switch (lanes) {
+static bool csr_entry(int ept, CsrLaunch* r) {
+    switch (ept) {
+        case 2: csr_entry_l<KT, 2>(r); return true;
         case 4: csr_entry_l<KT, 4>(r); return true;
         case 8: csr_entry_l<KT, 8>(r); return true;
         case 16: csr_entry_l<KT, 16>(r); return true;
-        case 32: csr_entry_l<KT, 32>(r); return true;
-        case 64: csr_entry_l<KT, 64>(r); return true;
         default: return false;
     }
 }
 
-bool csr_select(int prec, int lanes, CsrLaunch* out) {
-    return prec == ND_FP64 ? csr_entry<double>(lanes, out) : csr_entry<float>(lanes, out);
+bool csr_select(int prec, int ept, CsrLaunch* out) {
+    return prec == ND_FP64 ? csr_entry<double>(ept, out) : csr_entry<float>(ept, out);
 }
 
 hipError_t csr_launch_prologue(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                const int* nwork) {
-    hipLaunchKernelGGL(L.prologue, dim3(grid), dim3(256), 0, s, D, work, nwork);
+    hipLaunchKernelGGL(L.prologue, dim3((grid + kSrcBlocks - 1) / kSrcBlocks), dim3(256), 0, s, D, work, nwork);
     return hipGetLastError();
 }
 
 hipError_t csr_launch_stage(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                             const int* nwork, int stage, int j) {
-    hipLaunchKernelGGL(L.stage[stage - 1], dim3(grid), dim3(256), 0, s, D, work, nwork, j);
+    hipLaunchKernelGGL(L.gather, dim3(grid), dim3(256), 0, s, D, work, nwork, stage, j);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(L.update[stage - 1], dim3((grid + kSrcBlocks - 1) / kSrcBlocks), dim3(256), 0, s, D, work, nwork,
+                       j);
     return hipGetLastError();
 }
 

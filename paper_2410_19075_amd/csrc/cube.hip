@@ -18,6 +18,8 @@
 // The next plane's column values and RK operands are prefetched one plane
 // ahead, and the plane loop synchronises through LDS-only barriers so those
 // loads stay in flight.  All sums are double and every sum has a fixed order.
+#include <type_traits>
+
 #include "models.h"
 #include "runtime.h"
 
@@ -111,55 +113,73 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
         const int64_t obase = (int64_t)(x0 + ox) + (int64_t)n1 * (y0 + oy);
 
-        double2 rb[S];
+        // the last 2H+1 mapped planes of this column; in the bulk type, which is
+        // exact (FP32-bulk maps are computed in float)
+        using RB = typename std::conditional<sizeof(KT) == 8, double2, float2>::type;
+        auto to_rb = [](double2 v) {
+            RB r;
+            r.x = v.x;
+            r.y = v.y;
+            return r;
+        };
+        RB rb[S];
 #pragma unroll
         for (int u = 0; u < 2 * H; ++u) {
             double z[1];
             stage_z<1, KT>(y, kp, cdt, n, colbase + plane * wrapm(z0 - H + u, n3), z);
-            rb[u] = M::map(z);
+            rb[u] = to_rb(M::map(z));
         }
-        rb[2 * H] = make_double2(0.0, 0.0);
-        // prefetched operands: the next new column plane and the RK operands
-        double cyv, ckv = 0.0, ry, rk = 0.0, ra = 0.0;
-        {
-            const int64_t ci = colbase + plane * wrapm(z0 + H, n3);
-            cyv = y[ci];
-            if (stage != 1) ckv = (double)kp[ci];
-            const int64_t oi = obase + plane * z0;
-            ry = y[oi];
-            if (stage == 2 || stage == 4) rk = (double)kp[oi];
-            if (stage == 4) ra = acc[oi];
-        }
+        rb[2 * H] = to_rb(make_double2(0.0, 0.0));
+        // prefetched operands, PF planes ahead (a shift queue with static
+        // indices): the column values of the plane entering the z window and
+        // the RK operands of the output plane
+        constexpr int PF = 2;
+        double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
+        auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
+            // operands of output plane z0 + ahead (clamped inside this work item)
+            const int zo_ = z0 + min(ahead, nz - 1);
+            const int64_t ci = colbase + plane * wrapm(zo_ + H, n3);
+            cy_ = y[ci];
+            ck_ = stage != 1 ? (double)kp[ci] : 0.0;
+            const int64_t oi = obase + plane * zo_;
+            ry_ = y[oi];
+            rk_ = (stage == 2 || stage == 4) ? (double)kp[oi] : 0.0;
+            ra_ = stage == 4 ? acc[oi] : 0.0;
+        };
+#pragma unroll
+        for (int f = 0; f < PF; ++f) fetch(f, qy[f], qk[f], qry[f], qrk[f], qra[f]);
         double part[2] = {0.0, 0.0};  // stage 1: sums of map(y) for R
         for (int zb = 0; zb < nz; zb += S) {
 #pragma unroll
             for (int u = 0; u < S; ++u) {
                 if (zb + u < nz) {
                     const int zo = z0 + zb + u;
-                    const double zc = stage == 1 ? cyv : fma(cdt, ckv, cyv);
-                    const double cry = ry, crk = rk, cra = ra;
-                    if (zb + u + 1 < nz) {
-                        const int64_t ci = colbase + plane * wrapm(zo + 1 + H, n3);
-                        cyv = y[ci];
-                        if (stage != 1) ckv = (double)kp[ci];
-                        const int64_t oi = obase + plane * (zo + 1);
-                        ry = y[oi];
-                        if (stage == 2 || stage == 4) rk = (double)kp[oi];
-                        if (stage == 4) ra = acc[oi];
+                    const double zc = stage == 1 ? qy[0] : fma(cdt, qk[0], qy[0]);
+                    const double cry = qry[0], crk = qrk[0], cra = qra[0];
+#pragma unroll
+                    for (int f = 0; f + 1 < PF; ++f) {
+                        qy[f] = qy[f + 1];
+                        qk[f] = qk[f + 1];
+                        qry[f] = qry[f + 1];
+                        qrk[f] = qrk[f + 1];
+                        qra[f] = qra[f + 1];
                     }
+                    fetch(zb + u + PF, qy[PF - 1], qk[PF - 1], qry[PF - 1], qrk[PF - 1], qra[PF - 1]);
                     {
                         double z[1] = {zc};
-                        rb[(u + 2 * H) % S] = M::map(z);
+                        rb[(u + 2 * H) % S] = to_rb(M::map(z));
                     }
                     double2 sz = make_double2(0.0, 0.0);
 #pragma unroll
                     for (int dz = -H; dz <= H; ++dz) {
-                        sz.x += rb[(u + dz + H) % S].x;
-                        sz.y += rb[(u + dz + H) % S].y;
+                        sz.x += (double)rb[(u + dz + H) % S].x;
+                        sz.y += (double)rb[(u + dz + H) % S].y;
                     }
                     const int buf = (zb + u) & 1;
                     if (col) S1[buf * HX * HY + tid] = sz;
-                    if (inner) S0[buf * cx * cy + (hy - H) * cx + (hx - H)] = rb[(u + H) % S];
+                    if (inner)
+                        S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
+                            make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
                     lds_barrier();
                     // x-pass over the HY rows
                     for (int q = tid; q < HY * cx; q += blockDim.x) {

@@ -10,6 +10,7 @@
 namespace nd {
 
 constexpr int kWave = 64;
+constexpr int kCsrSourceBlocks = 8;  // CSR in-edges split by source range, one block per XCD
 
 // Per-network descriptor, one per network of a batch, resident in device memory.
 // The chunk-position fields (g0, nsteps, ypar) advance on the device at the end
@@ -30,9 +31,10 @@ struct NetDesc {
     double* tsum[2];    // ring: per-tile sums of the mapped stage values, 2 comps
     double* rsum;       // FHN: per-tile sums of the unit phase vectors (u, v)/|(u, v)|
     void* sx[2];        // HH: exchanged synaptic activations S(V) per stage
-    const int64_t* row_ptr;
-    const int32_t* col;
-    const void* w;
+    const int64_t* row_ptr;  // CSR: per source block b, row offsets at [b*(n+1), (b+1)*(n+1))
+    const int32_t* col;      // CSR: sources, block-major, ascending within each row and block
+    const void* w;           // CSR: weights in the bulk type, same order
+    double* acc_part;        // CSR: per source block synaptic partial sums [blocks][n]
     const double* iapp;
     double* R;          // order parameter per recorded step
     int64_t r_every;

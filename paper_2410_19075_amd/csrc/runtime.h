@@ -110,10 +110,11 @@ hipError_t cube_launch_final(const CubeLaunch& L, int grid, hipStream_t s, NetDe
 
 // CSR kernels (csr.hip): work items of 256 target rows
 struct CsrLaunch {
-    void (*stage[4])(const NetDesc*, const int2*, const int*, int);
+    void (*gather)(const NetDesc*, const int2*, const int*, int, int);
+    void (*update[4])(const NetDesc*, const int2*, const int*, int);
     void (*prologue)(const NetDesc*, const int2*, const int*);
 };
-bool csr_select(int prec, int lanes, CsrLaunch* out);
+bool csr_select(int prec, int ept, CsrLaunch* out);
 hipError_t csr_launch_prologue(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                                const int* nwork);
 hipError_t csr_launch_stage(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,

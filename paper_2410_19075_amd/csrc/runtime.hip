@@ -127,7 +127,7 @@ nd_kernel_config default_config(const nd_problem* p) {
         c.block = cube_block(h, cx, cy);
     } else {
         c.tile = 256;    // target rows per work item
-        c.tile_y = 16;   // lanes per row
+        c.tile_y = 8;    // edges per thread per chunk
         c.block = 256;
     }
     return c;
@@ -149,7 +149,8 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
     if (p->topo == ND_CUBE3D)
         b += 3 * 2 * 8 * ((p->n1 + c.tile - 1) / c.tile) * ((p->n2 + c.tile_y - 1) / c.tile_y) *
              ((p->n3 + c.tile_z - 1) / c.tile_z);
-    if (p->topo == ND_CSR) b += (n + 1) * 8 + p->nnz * (4 + kb) + n * 8 + 2 * n * kb;
+    if (p->topo == ND_CSR)
+        b += kCsrSourceBlocks * (n + 1) * 8 + p->nnz * (4 + kb) + n * 8 + 2 * n * kb + kCsrSourceBlocks * n * 8;
     b += sizeof(NetDesc) + 64;
     return b;
 }
@@ -216,21 +217,47 @@ nd_status Net::create(const nd_problem* pr) {
     for (int b = 0; b < 3; ++b)
         if ((s = alloc(&d.k[b], V * n * kb))) return s;
     if (pr->topo == ND_CSR) {
-        if ((s = alloc((void**)&d.row_ptr, (n + 1) * 8))) return s;
-        if ((s = alloc((void**)&d.col, std::max<int64_t>(pr->nnz, 1) * 4))) return s;
-        if ((s = alloc((void**)&d.w, std::max<int64_t>(pr->nnz, 1) * kb))) return s;
+        // split every row's in-edges by source block (sources ascending, so each
+        // block keeps its order) and lay the blocks out one after the other
+        const int B = kCsrSourceBlocks;
+        const int64_t nnz = pr->nnz;
+        std::vector<int64_t> bptr((size_t)B * (n + 1), 0);
+        auto block_of = [&](int64_t src) { return (int)std::min<int64_t>(B - 1, src * B / n); };
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = pr->row_ptr[i]; e < pr->row_ptr[i + 1]; ++e) ++bptr[(size_t)block_of(pr->col[e]) * (n + 1) + i + 1];
+        int64_t base = 0;
+        for (int b = 0; b < B; ++b) {
+            int64_t* p = bptr.data() + (size_t)b * (n + 1);
+            p[0] = base;
+            for (int64_t i = 0; i < n; ++i) p[i + 1] += p[i];
+            base = p[n];
+        }
+        std::vector<int64_t> pos(bptr);
+        std::vector<int32_t> col2((size_t)std::max<int64_t>(nnz, 1));
+        std::vector<double> w2((size_t)std::max<int64_t>(nnz, 1));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = pr->row_ptr[i]; e < pr->row_ptr[i + 1]; ++e) {
+                const int b = block_of(pr->col[e]);
+                const int64_t dst = pos[(size_t)b * (n + 1) + i]++;
+                col2[dst] = pr->col[e];
+                w2[dst] = pr->weight[e];
+            }
+        if ((s = alloc((void**)&d.row_ptr, (size_t)B * (n + 1) * 8))) return s;
+        if ((s = alloc((void**)&d.col, std::max<int64_t>(nnz, 1) * 4))) return s;
+        if ((s = alloc((void**)&d.w, std::max<int64_t>(nnz, 1) * kb))) return s;
+        if ((s = alloc((void**)&d.acc_part, (size_t)B * n * 8))) return s;
         if ((s = alloc((void**)&d.iapp, n * 8))) return s;
         for (int b = 0; b < 2; ++b)
             if ((s = alloc(&d.sx[b], n * kb))) return s;
-        HIPC(hipMemcpy((void*)d.row_ptr, pr->row_ptr, (n + 1) * 8, hipMemcpyHostToDevice));
-        if (pr->nnz > 0) {
-            HIPC(hipMemcpy((void*)d.col, pr->col, pr->nnz * 4, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy((void*)d.row_ptr, bptr.data(), bptr.size() * 8, hipMemcpyHostToDevice));
+        if (nnz > 0) {
+            HIPC(hipMemcpy((void*)d.col, col2.data(), nnz * 4, hipMemcpyHostToDevice));
             if (kb == 8) {
-                HIPC(hipMemcpy((void*)d.w, pr->weight, pr->nnz * 8, hipMemcpyHostToDevice));
+                HIPC(hipMemcpy((void*)d.w, w2.data(), nnz * 8, hipMemcpyHostToDevice));
             } else {
-                std::vector<float> wf(pr->nnz);
-                for (int64_t e = 0; e < pr->nnz; ++e) wf[e] = (float)pr->weight[e];
-                HIPC(hipMemcpy((void*)d.w, wf.data(), pr->nnz * 4, hipMemcpyHostToDevice));
+                std::vector<float> wf(nnz);
+                for (int64_t e = 0; e < nnz; ++e) wf[e] = (float)w2[e];
+                HIPC(hipMemcpy((void*)d.w, wf.data(), nnz * 4, hipMemcpyHostToDevice));
             }
         }
         HIPC(hipMemcpy((void*)d.iapp, pr->per_elem, n * 8, hipMemcpyHostToDevice));
@@ -274,7 +301,7 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         cfg.block = 256;
         cfg.tile = 256;  // rows per work item (fixed by the kernel)
         tmpl.tile = 256;
-        tmpl.G = (int32_t)((n + 255) / 256);
+        tmpl.G = (int32_t)(kCsrSourceBlocks * ((n + 255) / 256));  // (row tile, source block)
     }
     nd_status s;
     if (prob.topo != ND_CSR) {
@@ -413,7 +440,7 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
             return hip_fail(e, "cube final");
     } else {
         CsrLaunch L;
-        if (!csr_select(g.prec, g.tile_y, &L)) return fail(ND_ERR_UNSUPPORTED, "no CSR kernel for %d lanes", g.tile_y);
+        if (!csr_select(g.prec, g.tile_y, &L)) return fail(ND_ERR_UNSUPPORTED, "no CSR kernel for %d edges per thread", g.tile_y);
         if ((e = csr_launch_prologue(L, grid, st, g.desc, g.work, g.nwork)) != hipSuccess) return hip_fail(e, "csr prologue");
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
@@ -674,8 +701,8 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
             return fail(ND_ERR_INVALID_ARG, "cube tile: (tile+2h)*(tile_y+2h) must be <= 1024");
     } else {
         if (c.tile != 256) return fail(ND_ERR_INVALID_ARG, "CSR work items hold 256 rows (tile must be 256)");
-        if (c.tile_y < 4 || c.tile_y > 64 || (c.tile_y & (c.tile_y - 1)))
-            return fail(ND_ERR_INVALID_ARG, "CSR lanes per row must be a power of two in [4, 64]");
+        if (c.tile_y < 2 || c.tile_y > 16 || (c.tile_y & (c.tile_y - 1)))
+            return fail(ND_ERR_INVALID_ARG, "CSR edges per thread must be 2, 4, 8 or 16");
     }
     return n->apply_config(c);
 }

@@ -85,7 +85,7 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
             }
         }
     } else {
-        for (int l : {8, 16, 32, 64}) {
+        for (int l : {4, 8, 16}) {
             nd_kernel_config c = base;
             c.tile_y = l;
             v.push_back(c);

@@ -55,10 +55,63 @@ def test_hh_fp64_parity(nd, n, deg, steps):
     assert normwise(y, ref) < 1e-12
 
 
-@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
-def test_hh_lane_groups(nd, lanes):
-    print(f"case hh lanes={lanes}", flush=True)
-    y, ref = hh_case(nd, 3000, 100, 5, 20, cfg=dict(tile_y=lanes))
+@pytest.mark.parametrize("ept", [2, 4, 8, 16])
+def test_hh_edges_per_thread(nd, ept):
+    print(f"case hh ept={ept}", flush=True)
+    y, ref = hh_case(nd, 3000, 100, 5, 20, cfg=dict(tile_y=ept))
+    assert normwise(y, ref) < 1e-12
+
+
+def test_hh_edges_per_thread_bitwise(nd):
+    """Every row's products are added in edge order whatever the chunking, so the
+    result does not depend on the edges-per-thread setting at all."""
+    ys = [hh_case(nd, 2500, 60, 9, 10, cfg=dict(tile_y=e))[0] for e in (2, 4, 8, 16)]
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])
+
+
+def hub_graph(n, deg, hub, empty, seed):
+    """Random out-degree `deg` graph plus every node feeding `hub`, with the rows
+    in `empty` stripped of all in-edges; CSR by target, sources ascending."""
+    rng = np.random.default_rng(seed)
+    src = np.repeat(np.arange(n), deg)
+    dst = rng.integers(0, n, size=src.size)
+    keep = dst != src
+    src, dst = src[keep], dst[keep]
+    src = np.concatenate([src, np.delete(np.arange(n), hub)])
+    dst = np.concatenate([dst, np.full(n - 1, hub)])
+    keep = ~np.isin(dst, empty)
+    src, dst = src[keep], dst[keep]
+    order = np.lexsort((src, dst))
+    src, dst = src[order], dst[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(np.bincount(dst, minlength=n))
+    w = rng.uniform(0.0, 0.1, size=src.size)
+    return rp, src.astype(np.int32), w
+
+
+@pytest.mark.parametrize("ept", [2, 16])
+def test_hh_hub_row_spans_chunks(nd, ept):
+    """A row whose in-edges of one source block exceed a whole chunk (hub with
+    in-degree n-1, ~5000 edges per block), and rows with no in-edges at all."""
+    n = 40000
+    rp, col, w = hub_graph(n, 3, 7, np.arange(100, 300), 11)
+    assert np.diff(rp)[100:300].max() == 0 and np.diff(rp)[7] >= n - 1
+    iapp = inputs.hh_iapp(11, n)
+    y0 = inputs.hh_state(11, n)
+    p = nd.problem(nd.ND_HH, nd.ND_CSR, n, HH_PRM, row_ptr=rp, col=col, weight=w, per_elem=iapp)
+    h = nd.nd_create(p)
+    try:
+        c = nd.nd_get_config(h)
+        c.tile_y = ept
+        nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, 0.01, 5)
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    ref, _, _ = O.run(O.csr(n, rp, col, w, HH_PRM, iapp), y0, 0.01, 5)
     assert normwise(y, ref) < 1e-12
 
 
