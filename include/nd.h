@@ -155,7 +155,7 @@ nd_status nd_destroy(nd_handle h);
 
 /* Kernel configuration (chosen by the autotuner; callers normally leave it alone). */
 typedef struct nd_kernel_config {
-    int32_t tile;   /* ring: elements per tile (256, 512, 1024 or 2048), or -1024 / -2048 / -4096:
+    int32_t tile;   /* ring: elements per tile (128, 256, 512, 1024 or 2048), or -1024 / -2048 / -4096:
                        the whole ring (n <= that capacity) resident in one workgroup;
                        cube: output tile extent along x; CSR: rows per workgroup */
     int32_t block;  /* threads per workgroup (derived; ignored by nd_set_config) */

@@ -182,13 +182,13 @@ __global__ __launch_bounds__(256) void k_csr_update(const NetDesc* __restrict__ 
                 zn[v] = fma(0.5 * dt, kk, yv[v]);
             } else if (stage == 2) {
                 gp((KT*)d.k[1])[q] = (KT)kk;
-                gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[v], yv[v]));
+                gp(d.acc)[q] = fma(d.dt3, kk, fma(d.dt6, kv[v], yv[v]));
                 zn[v] = fma(0.5 * dt, kk, yv[v]);
             } else if (stage == 3) {
                 gp((KT*)d.k[2])[q] = (KT)kk;
                 zn[v] = fma(dt, kk, yv[v]);
             } else {
-                const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[v], gp(d.acc)[q]));
+                const double yo = fma(d.dt6, kk, fma(d.dt3, kv[v], gp(d.acc)[q]));
                 gp(d.y[par ^ 1])[q] = yo;
                 zn[v] = yo;
             }

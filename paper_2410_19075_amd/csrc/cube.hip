@@ -217,11 +217,11 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                             if (MV && (d.obs & OBS_MV) && g == d.mv_start) gp(d.mv)[q] = cry;
                         } else if (stage == 2) {
                             gp((KT*)d.k[1])[q] = (KT)kk;
-                            gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, crk, cry));
+                            gp(d.acc)[q] = fma(d.dt3, kk, fma(d.dt6, crk, cry));
                         } else if (stage == 3) {
                             gp((KT*)d.k[2])[q] = (KT)kk;
                         } else {
-                            gp(d.y[par ^ 1])[q] = fma(dt / 6.0, kk, fma(dt / 3.0, crk, cra));
+                            gp(d.y[par ^ 1])[q] = fma(d.dt6, kk, fma(d.dt3, crk, cra));
                         }
                     }
                 }

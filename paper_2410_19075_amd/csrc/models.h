@@ -55,7 +55,9 @@ struct RingModel<ND_KURAMOTO, KT> {
 //   eps du = u - u^3/3 - v + kappa ( cos phi Du + sin phi Dv)
 //       dv = u + a         + kappa (-sin phi Du + cos phi Dv)
 // Du = sum_j u_j - 2P u_i, Dv likewise (double, before any rounding to float).
-// p = {eps, a, kappa, cos phi, sin phi, 2P}
+// The divisions by 3 and eps are multiplications by the rounded reciprocals
+// (a last-bit difference from the division; no division sequence per element).
+// p = {eps, a, kappa, cos phi, sin phi, 2P, 1/eps}
 template <class KT>
 struct RingModel<ND_FHN, KT> {
     static constexpr int V = 2;
@@ -69,14 +71,14 @@ struct RingModel<ND_FHN, KT> {
         if constexpr (sizeof(KT) == 8) {
             const double cu = d.p[2] * (d.p[3] * Du + d.p[4] * Dv);
             const double cv = d.p[2] * (d.p[3] * Dv - d.p[4] * Du);
-            k[0] = (u - u * u * u / 3.0 - v + cu) / d.p[0];
+            k[0] = (u - u * u * u * (1.0 / 3.0) - v + cu) * d.p[6];
             k[1] = u + d.p[1] + cv;
         } else {
             const float uf = (float)u, vf = (float)v, duf = (float)Du, dvf = (float)Dv;
             const float kap = (float)d.p[2], cph = (float)d.p[3], sph = (float)d.p[4];
             const float cu = kap * (cph * duf + sph * dvf);
             const float cv = kap * (cph * dvf - sph * duf);
-            k[0] = (double)((uf - uf * uf * uf / 3.0f - vf + cu) / (float)d.p[0]);
+            k[0] = (double)((uf - uf * uf * uf * (1.0f / 3.0f) - vf + cu) * (float)d.p[6]);
             k[1] = (double)(uf + (float)d.p[1] + cv);
         }
     }

@@ -24,6 +24,7 @@ struct NetDesc {
     int32_t cx, cy, cz; // cube: output tile extents per work item (x, y, z)
     int32_t gx, gy;     // cube: tiles along x and y
     double dt;
+    double dt3, dt6;    // dt/3 and dt/6 (rounded once, on the host)
     double p[12];       // derived model constants (layout per model, see runtime)
     double* y[2];       // state, double-buffered across steps
     double* acc;        // RK accumulator y + dt/6 k1 + dt/3 k2

@@ -79,7 +79,9 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
     using M = RingModel<MODEL, KT>;
     constexpr int V = M::V, T = BS * EPT, NW = BS / kWave;
     __shared__ double2 sd[T];  // x_right - x_left, then the inclusive window sums
-    __shared__ double sy[V * T], sk[V * T];  // own y and k_prev, kept for the RK update
+    // own y and k_prev, kept for the RK update, only where the stage uses them
+    constexpr bool kNeedY = STAGE != 4 || MV, kNeedK = STAGE == 2 || STAGE == 4;
+    __shared__ double sy[kNeedY ? V * T : 1], sk[kNeedK ? V * T : 1];
     __shared__ double lds[8 * NW];
     const int nwork = *nwork_p;
     const int tid = threadIdx.x;
@@ -133,7 +135,8 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
 
         // ---- phase 1 (coalesced, element m = e*BS + tid): own stage values,
         // window-end differences into LDS, head / tail-remainder partial sums
-        double red[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // head(2), tail remainder(2), tiles(2)
+        // per lane: head partial + whole tiles - tail remainder (both components)
+        double red[2] = {0.0, 0.0};
         double zo[EPT][V];
         double2 xo[EPT];
         {
@@ -153,8 +156,8 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                     const double yy = y[v * n + io];
                     const double kk = stage == 1 ? 0.0 : (double)kp[v * n + io];
                     zo[e][v] = stage == 1 ? yy : fma(cdt, kk, yy);
-                    sy[v * T + m] = yy;
-                    sk[v * T + m] = kk;
+                    if constexpr (kNeedY) sy[v * T + m] = yy;
+                    if constexpr (kNeedK) sk[v * T + m] = kk;
                 }
             }
 #pragma unroll
@@ -169,16 +172,21 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                     red[1] += xl.y;
                 }
                 if (m < tlen) {
-                    red[2] += xr.x;
-                    red[3] += xr.y;
+                    red[0] -= xr.x;
+                    red[1] -= xr.y;
                 }
                 sd[m] = make_double2(xr.x - xl.x, xr.y - xl.y);
             }
         }
+        // whole tiles inside the window (several per lane for long windows;
+        // unrolled so their loads are in flight together, order unchanged)
+#pragma unroll 4
         for (int u = ua + 1 + tid; u <= ub; u += BS) {
             const int uu = u < 0 ? u + G : (u >= G ? u - G : u);
-            red[4] += tin[2 * uu];
-            red[5] += tin[2 * uu + 1];
+            typedef double d2v __attribute__((ext_vector_type(2)));
+            const d2v ts = *(const ND_GLOBAL d2v*)(tin + 2 * uu);
+            red[0] += ts.x;
+            red[1] += ts.y;
         }
         lds_barrier();
 
@@ -201,10 +209,9 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
             tot[0] += dv[e].x;
             tot[1] += dv[e].y;
         }
-        block_sum_and_exscan<BS, 6, 2>(red, tot, lds);
+        block_sum_and_exscan<BS, 2, 2>(red, tot, lds);
         {
-            const double w0x = (red[0] + red[4]) - red[2];
-            const double w0y = (red[1] + red[5]) - red[3];
+            const double w0x = red[0], w0y = red[1];
             double r0 = tot[0], r1 = tot[1];
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -224,8 +231,8 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
             const int m = e * BS + tid;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                yv[e][v] = sy[v * T + m];
-                kv[e][v] = sk[v * T + m];
+                yv[e][v] = kNeedY ? sy[v * T + m] : 0.0;
+                kv[e][v] = kNeedK ? sk[v * T + m] : 0.0;
             }
         }
 #pragma unroll
@@ -248,13 +255,13 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 2) {
                         gp((KT*)d.k[1])[q] = (KT)kk;
-                        gp(d.acc)[q] = fma(dt / 3.0, kk, fma(dt / 6.0, kv[e][v], yy));
+                        gp(d.acc)[q] = fma(d.dt3, kk, fma(d.dt6, kv[e][v], yy));
                         zn[v] = fma(0.5 * dt, kk, yy);
                     } else if (stage == 3) {
                         gp((KT*)d.k[2])[q] = (KT)kk;
                         zn[v] = fma(dt, kk, yy);
                     } else {
-                        const double yo = fma(dt / 6.0, kk, fma(dt / 3.0, kv[e][v], av[e][v]));
+                        const double yo = fma(d.dt6, kk, fma(d.dt3, kv[e][v], av[e][v]));
                         gp(d.y[par ^ 1])[q] = yo;
                         zn[v] = yo;
                     }
@@ -284,7 +291,9 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 }
             }
         }
-        block_sum<BS, 4>(nx, lds);
+        // FHN's stage 4 also sums the unit vectors for R; otherwise two sums
+        block_sum<BS, (MODEL == ND_FHN && STAGE == 4) ? 4 : 2>(
+            *reinterpret_cast<double(*)[(MODEL == ND_FHN && STAGE == 4) ? 4 : 2]>(nx), lds);
         if (tid == 0) {
             ND_GLOBAL double* tout = gp(d.tsum[stage & 1]);
             tout[2 * tile] = nx[0];
@@ -403,8 +412,8 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
 #pragma unroll
                         for (int v = 0; v < V; ++v) {
                             const double kk = kq<KT>(k[v]);
-                            if (s == 2) acc[e][v] = fma(dt / 3.0, kk, fma(dt / 6.0, kp[e][v], y[e][v]));
-                            yo[v] = s == 4 ? fma(dt / 6.0, kk, fma(dt / 3.0, kp[e][v], acc[e][v])) : y[e][v];
+                            if (s == 2) acc[e][v] = fma(d.dt3, kk, fma(d.dt6, kp[e][v], y[e][v]));
+                            yo[v] = s == 4 ? fma(d.dt6, kk, fma(d.dt3, kp[e][v], acc[e][v])) : y[e][v];
                             kp[e][v] = kk;
                         }
                         if constexpr (MODEL == ND_FHN) {
@@ -549,10 +558,11 @@ static bool ring_pick(int tile, RingLaunch* out) {
         case -1024: *out = resident_entry<MODEL, KT, 256, 4>(); return true;
         case -2048: *out = resident_entry<MODEL, KT, 256, 8>(); return true;
         case -4096: *out = resident_entry<MODEL, KT, 512, 8>(); return true;
-        case 1024: *out = ring_entry<MODEL, KT, 256, 4>(); return true;
         case 2048: *out = ring_entry<MODEL, KT, 256, 8>(); return true;
-        case 512: *out = ring_entry<MODEL, KT, 128, 4>(); return true;
-        case 256: *out = ring_entry<MODEL, KT, 64, 4>(); return true;
+        case 1024: *out = ring_entry<MODEL, KT, 256, 4>(); return true;
+        case 512: *out = ring_entry<MODEL, KT, 256, 2>(); return true;
+        case 256: *out = ring_entry<MODEL, KT, 128, 2>(); return true;
+        case 128: *out = ring_entry<MODEL, KT, 64, 2>(); return true;
         default: return false;
     }
 }

@@ -135,7 +135,7 @@ nd_kernel_config default_config(const nd_problem* p) {
 
 int ring_block(int tile) {
     if (tile < 0) return tile == -4096 ? 512 : 256;
-    return tile == 512 ? 128 : (tile == 256 ? 64 : 256);
+    return tile == 128 ? 64 : (tile == 256 ? 128 : 256);  // two elements per thread up to 512
 }
 
 static int64_t bulk_bytes(int prec) { return prec == ND_FP64 ? 8 : 4; }
@@ -185,6 +185,7 @@ static void derive_params(const nd_problem* p, NetDesc& d) {
         d.p[3] = std::cos(p->params[3]);
         d.p[4] = std::sin(p->params[3]);
         d.p[5] = 2.0 * (double)p->radius;
+        d.p[6] = 1.0 / p->params[0];
     } else {
         for (int i = 0; i < 10; ++i) d.p[i] = p->params[i];
     }
@@ -360,6 +361,8 @@ nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs) {
 NetDesc Net::run_desc(double dt, int64_t steps) const {
     NetDesc d = tmpl;
     d.dt = dt;
+    d.dt3 = dt / 3.0;
+    d.dt6 = dt / 6.0;
     d.obs = (r_every > 0 ? OBS_R : 0) | (mv_start >= 0 ? OBS_MV : 0);
     d.R = R_dev;
     d.r_every = r_every > 0 ? r_every : 1;

@@ -66,7 +66,7 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
     std::vector<nd_kernel_config> v;
     nd_kernel_config base = default_config(p);
     if (p->topo == ND_RING) {
-        for (int t : {256, 512, 1024, 2048}) {
+        for (int t : {128, 256, 512, 1024, 2048}) {
             nd_kernel_config c = base;
             c.tile = t;
             v.push_back(c);

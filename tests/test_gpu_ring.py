@@ -205,7 +205,7 @@ def test_batch_equals_solo_bitwise(nd):
             nd.nd_destroy(h)
 
 
-@pytest.mark.parametrize("tile", [256, 512, 1024, 2048, -4096])
+@pytest.mark.parametrize("tile", [128, 256, 512, 1024, 2048, -4096])
 @pytest.mark.parametrize("grid,chunk", [(0, 64), (24, 16), (8, 5)])
 def test_tile_grid_and_chunk_configs(nd, tile, grid, chunk):
     """Every tile size, persistent grids smaller than the work and graph chunks
