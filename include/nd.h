@@ -29,7 +29,8 @@
  *                ND_CSR only.
  *
  * Topologies (Sec. IV; Sec. III.C for general coupling matrices):
- *   ND_RING      element i couples to i +- 1 .. i +- P (periodic), requires 1 <= P, 2P+1 <= n.
+ *   ND_RING      element i couples to i +- 1 .. i +- P (periodic), requires 1 <= P, 2P+1 <= n
+ *                and n < 2^29.
  *   ND_CUBE3D    periodic n1 x n2 x n3 lattice, index x + n1*y + n1*n2*z (the paper's 3D index
  *                map), neighbours = the (2h+1)^3 cube minus the element itself; n1,n2,n3 >= 2h+1.
  *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,

@@ -63,6 +63,23 @@ __device__ __forceinline__ const ND_GLOBAL T* gp(const T* p) {
     return (const ND_GLOBAL T*)p;
 }
 
+__device__ __forceinline__ int ring_wrap32(int i, int n) {
+    // valid for i in [-n, 2n)
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Element access through a uniform base and a 32-bit byte offset (arrays
+// below 4 GiB), which maps onto the scalar-base + lane-offset global memory
+// forms instead of a 64-bit address per lane.
+template <class T>
+__device__ __forceinline__ T ld32(const ND_GLOBAL T* base, uint32_t i) {
+    return *(const ND_GLOBAL T*)((const ND_GLOBAL char*)base + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st32(ND_GLOBAL T* base, uint32_t i, T v) {
+    *(ND_GLOBAL T*)((ND_GLOBAL char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ int64_t ring_wrap(int64_t i, int64_t n) {
     // valid for i in [-n, 2n)
     return i < 0 ? i + n : (i >= n ? i - n : i);

@@ -93,16 +93,24 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         const int2 wk = work[w];
         const NetDesc& d = D[wk.x];
         if (j >= d.nsteps) continue;  // uniform over the block
-        const int64_t n = d.n, P = d.P;
+        // element indices and the per-variable offsets below are 32-bit (rings
+        // hold fewer than 2^29 elements, so every byte offset fits 32 bits):
+        // loads and stores then take a uniform 64-bit base plus a lane offset
+        const int n = (int)d.n, P = (int)d.P;
         const int G = d.G, tile = wk.y;
-        const int64_t t0 = (int64_t)tile * T;
-        const int cnt = (int)min((int64_t)T, n - t0);
+        const int t0 = tile * T;
+        const int cnt = min(T, n - t0);
         const int64_t g = d.g0 + j;
         const int par = (d.ypar + j) & 1;
-        const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
-        const ND_GLOBAL KT* __restrict__ kp =
-            stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
-        const ND_GLOBAL double* __restrict__ acc = gp(d.acc);
+        const ND_GLOBAL double* yb[V];
+        const ND_GLOBAL KT* kb[V];
+        const ND_GLOBAL double* ab[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            yb[v] = gp(d.y[par]) + (int64_t)v * n;
+            kb[v] = stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]) + (int64_t)v * n;
+            ab[v] = gp(d.acc) + (int64_t)v * n;
+        }
         const double dt = d.dt;
         const double cdt = stage == 4 ? dt : 0.5 * dt;
         const ND_GLOBAL double* __restrict__ tin = gp(d.tsum[(stage - 1) & 1]);
@@ -120,12 +128,12 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         }
 
         // ---- geometry of the window ends [A, A+T) and [B, B+T)
-        const int64_t A = t0 - P, B = t0 + P + 1;
-        const int64_t a = A < 0 ? A + n : A;
-        const int64_t b = B >= n ? B - n : B;
-        const int ta = (int)(a / T), tb = (int)(b / T);
-        const int hlen = (int)(min((int64_t)ta * T + T, n) - a);
-        const int tlen = (int)(min((int64_t)tb * T + T, n) - b);
+        const int A = t0 - P, B = t0 + P + 1;
+        const int a = A < 0 ? A + n : A;
+        const int b = B >= n ? B - n : B;
+        const int ta = a / T, tb = b / T;
+        const int hlen = min(ta * T + T, n) - a;
+        const int tlen = min(tb * T + T, n) - b;
         const int ua = (A < 0 ? -G : 0) + ta;
         const int ub = (B >= n ? G : 0) + tb;
         // elements of each end range that are used: the partial tile (head /
@@ -139,6 +147,13 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         double red[2] = {0.0, 0.0};
         double zo[EPT][V];
         double2 xo[EPT];
+        auto stage_val = [&](uint32_t i, double* z) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double yy = ld32(yb[v], i);
+                z[v] = stage == 1 ? yy : fma(cdt, (double)ld32(kb[v], i), yy);
+            }
+        };
         {
             // all loads first, from always-valid (clamped) indices, so they are
             // issued back to back; masks are applied to the values afterwards
@@ -146,15 +161,15 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int m = e * BS + tid;
-                const int64_t il = m < lneed ? ring_wrap(A + m, n) : t0;
-                const int64_t ir = m < rneed ? ring_wrap(B + m, n) : t0;
-                const int64_t io = m < cnt ? t0 + m : t0;
-                stage_z<V, KT>(y, kp, cdt, n, il, zl[e]);
-                stage_z<V, KT>(y, kp, cdt, n, ir, zr[e]);
+                const int il = m < lneed ? ring_wrap32(A + m, n) : t0;
+                const int ir = m < rneed ? ring_wrap32(B + m, n) : t0;
+                const int io = m < cnt ? t0 + m : t0;
+                stage_val(il, zl[e]);
+                stage_val(ir, zr[e]);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const double yy = y[v * n + io];
-                    const double kk = stage == 1 ? 0.0 : (double)kp[v * n + io];
+                    const double yy = ld32(yb[v], io);
+                    const double kk = stage == 1 ? 0.0 : (double)ld32(kb[v], io);
                     zo[e][v] = stage == 1 ? yy : fma(cdt, kk, yy);
                     if constexpr (kNeedY) sy[v * T + m] = yy;
                     if constexpr (kNeedK) sk[v * T + m] = kk;
@@ -195,9 +210,9 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int m = e * BS + tid;
-            const int64_t i = t0 + (m < cnt ? m : 0);
+            const int i = t0 + (m < cnt ? m : 0);
 #pragma unroll
-            for (int v = 0; v < V; ++v) av[e][v] = stage == 4 ? acc[v * n + i] : 0.0;
+            for (int v = 0; v < V; ++v) av[e][v] = stage == 4 ? ld32(ab[v], i) : 0.0;
         }
         // ---- phase 2 (blocked, elements EPT*tid ..): exclusive scan of the
         // differences; LDS then holds the inclusive window sum of every element
@@ -239,7 +254,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
         for (int e = 0; e < EPT; ++e) {
             const int m = e * BS + tid;
             if (m < cnt) {
-                const int64_t i = t0 + m;
+                const int i = t0 + m;
                 const double2 wi = sd[m];
                 const double2 W = make_double2(wi.x - xo[e].x, wi.y - xo[e].y);
                 double k[V];
@@ -247,22 +262,15 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 double zn[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const int64_t q = v * n + i;
                     const double yy = yv[e][v];
                     const double kk = kq<KT>(k[v]);
-                    if (stage == 1) {
-                        gp((KT*)d.k[0])[q] = (KT)kk;
-                        zn[v] = fma(0.5 * dt, kk, yy);
-                    } else if (stage == 2) {
-                        gp((KT*)d.k[1])[q] = (KT)kk;
-                        gp(d.acc)[q] = fma(d.dt3, kk, fma(d.dt6, kv[e][v], yy));
-                        zn[v] = fma(0.5 * dt, kk, yy);
-                    } else if (stage == 3) {
-                        gp((KT*)d.k[2])[q] = (KT)kk;
-                        zn[v] = fma(dt, kk, yy);
+                    if (stage <= 3) {
+                        st32(gp((KT*)d.k[stage - 1]) + (int64_t)v * n, i, (KT)kk);
+                        zn[v] = fma(stage == 3 ? dt : 0.5 * dt, kk, yy);
+                        if (stage == 2) st32((ND_GLOBAL double*)ab[v], i, fma(d.dt3, kk, fma(d.dt6, kv[e][v], yy)));
                     } else {
                         const double yo = fma(d.dt6, kk, fma(d.dt3, kv[e][v], av[e][v]));
-                        gp(d.y[par ^ 1])[q] = yo;
+                        st32(gp(d.y[par ^ 1]) + (int64_t)v * n, i, yo);
                         zn[v] = yo;
                     }
                 }
@@ -270,7 +278,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 nx[0] += xn.x;
                 nx[1] += xn.y;
                 if constexpr (MODEL == ND_FHN) {
-                    if (stage == 4) {
+                    if (stage == 4 && (d.obs & OBS_R)) {
                         const double r = sqrt(zn[0] * zn[0] + zn[1] * zn[1]);
                         nx[2] += zn[0] / r;
                         nx[3] += zn[1] / r;

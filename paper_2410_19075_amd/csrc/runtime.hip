@@ -70,6 +70,8 @@ nd_status validate_problem(const nd_problem* p) {
             if (p->radius < 1 || 2 * p->radius + 1 > p->n)
                 return fail(ND_ERR_INVALID_ARG, "ring radius P must satisfy 1 <= P and 2P+1 <= n (n=%lld, P=%lld)",
                             (long long)p->n, (long long)p->radius);
+            if (p->n >= (int64_t(1) << 29))
+                return fail(ND_ERR_INVALID_ARG, "ring networks hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         case ND_CUBE3D: {
             if (p->model != ND_KURAMOTO) return fail(ND_ERR_INVALID_ARG, "the cube topology is for Kuramoto");
@@ -111,7 +113,7 @@ nd_kernel_config default_config(const nd_problem* p) {
         if (p->n <= 1024) c.tile = -1024;
         else if (p->n <= 2048) c.tile = -2048;
         else if (p->n <= 4096) c.tile = -4096;
-        else c.tile = p->n <= (int64_t(1) << 18) ? 256 : (p->n <= (int64_t(1) << 20) ? 512 : 1024);
+        else c.tile = p->n <= (int64_t(1) << 20) ? 512 : 1024;
         c.block = ring_block(c.tile);
     } else if (p->topo == ND_CUBE3D) {
         // 20 x 20 outputs per plane (28 x 28 halo columns at h = 4) and 40-plane
