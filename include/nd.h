@@ -32,7 +32,8 @@
  *   ND_RING      element i couples to i +- 1 .. i +- P (periodic), requires 1 <= P, 2P+1 <= n
  *                and n < 2^29.
  *   ND_CUBE3D    periodic n1 x n2 x n3 lattice, index x + n1*y + n1*n2*z (the paper's 3D index
- *                map), neighbours = the (2h+1)^3 cube minus the element itself; n1,n2,n3 >= 2h+1.
+ *                map), neighbours = the (2h+1)^3 cube minus the element itself; n1,n2,n3 >= 2h+1,
+ *                n < 2^29.
  *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,
  *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
  *

@@ -10,9 +10,10 @@
 // through z (a 2.5D scheme):
 //   * one thread per halo column (cx+2H) x (cy+2H) maps its stage values
 //     (cos z, sin z) plane by plane and keeps the last 2H+1 of them in
-//     registers, so the z-direction sum is a register sum;
-//   * the z-sums go to LDS, an x-pass and a y-pass (each 2H+1 terms) finish
-//     the cube sum for the cx x cy outputs of the plane;
+//     registers; the z-direction sum is a running sum (new plane in, oldest
+//     out) in double;
+//   * the z-sums go to LDS; an x-pass (sliding along runs of 4 outputs) and a
+//     y-pass (2H+1 terms) finish the cube sum for the cx x cy outputs;
 //   * the RHS and the RK bookkeeping follow the 13-access schedule of the ring
 //     kernels (y double-buffered, k in the bulk type).
 // The next plane's column values and RK operands are prefetched one plane
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         if (j >= d.nsteps) continue;  // uniform over the block
         const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
         const int64_t n = d.n;
-        const int64_t plane = (int64_t)n1 * n2;
+        // 32-bit element offsets (lattices below 2^29 elements) on uniform bases
+        const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
         const int cx = d.cx, cy = d.cy, cz = d.cz, gx = d.gx, gy = d.gy;
         const int HX = cx + 2 * H, HY = cy + 2 * H;
         const int t = wk.y;
@@ -107,12 +109,22 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         const bool col = tid < HX * HY;
         const int hx = col ? tid % HX : 0, hy = col ? tid / HX : 0;
         const bool inner = col && hx >= H && hx < H + cx && hy >= H && hy < H + cy;
-        const int64_t colbase = wrapm(x0 - H + hx, n1) + (int64_t)n1 * wrapm(y0 - H + hy, n2);
+        const uint32_t colbase = (uint32_t)wrapm(x0 - H + hx, n1) + (uint32_t)n1 * (uint32_t)wrapm(y0 - H + hy, n2);
         // output thread
         const bool outv = tid < cx * cy && (tid % cx) < ex && (tid / cx) < ey;
         const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
-        const int64_t obase = (int64_t)(x0 + ox) + (int64_t)n1 * (y0 + oy);
+        const uint32_t obase = (uint32_t)(x0 + ox) + (uint32_t)n1 * (uint32_t)(y0 + oy);
+        // x-pass thread: a run of up to kRunX consecutive outputs of one row
+        constexpr int kRunX = 4;
+        const int nsx = (cx + kRunX - 1) / kRunX;
+        const bool xr = tid < HY * nsx;
+        const int xrow = xr ? tid / nsx : 0, xs0 = xr ? (tid - xrow * nsx) * kRunX : 0;
+        const int xcnt = xr ? min(kRunX, cx - xs0) : 0;
 
+        auto zval = [&](uint32_t i) {
+            const double yy = ld32(y, i);
+            return stage == 1 ? yy : fma(cdt, (double)ld32(kp, i), yy);
+        };
         // the last 2H+1 mapped planes of this column; in the bulk type, which is
         // exact (FP32-bulk maps are computed in float)
         using RB = typename std::conditional<sizeof(KT) == 8, double2, float2>::type;
@@ -123,28 +135,31 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
             return r;
         };
         RB rb[S];
+        // running z-sum of the planes in the window that are already mapped
+        double zsx = 0.0, zsy = 0.0;
 #pragma unroll
         for (int u = 0; u < 2 * H; ++u) {
-            double z[1];
-            stage_z<1, KT>(y, kp, cdt, n, colbase + plane * wrapm(z0 - H + u, n3), z);
+            double z[1] = {zval(colbase + plane * (uint32_t)wrapm(z0 - H + u, n3))};
             rb[u] = to_rb(M::map(z));
+            zsx += (double)rb[u].x;
+            zsy += (double)rb[u].y;
         }
         rb[2 * H] = to_rb(make_double2(0.0, 0.0));
         // prefetched operands, PF planes ahead (a shift queue with static
-        // indices): the column values of the plane entering the z window and
+        // indices): the column value of the plane entering the z window and
         // the RK operands of the output plane
-        constexpr int PF = 2;
+        constexpr int PF = sizeof(KT) == 8 ? 1 : 2;  // FP64 registers are the tighter budget
         double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
         auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
             // operands of output plane z0 + ahead (clamped inside this work item)
             const int zo_ = z0 + min(ahead, nz - 1);
-            const int64_t ci = colbase + plane * wrapm(zo_ + H, n3);
-            cy_ = y[ci];
-            ck_ = stage != 1 ? (double)kp[ci] : 0.0;
-            const int64_t oi = obase + plane * zo_;
-            ry_ = y[oi];
-            rk_ = (stage == 2 || stage == 4) ? (double)kp[oi] : 0.0;
-            ra_ = stage == 4 ? acc[oi] : 0.0;
+            const uint32_t ci = colbase + plane * (uint32_t)wrapm(zo_ + H, n3);
+            cy_ = ld32(y, ci);
+            ck_ = stage != 1 ? (double)ld32(kp, ci) : 0.0;
+            const uint32_t oi = obase + plane * (uint32_t)zo_;
+            ry_ = ld32(y, oi);
+            rk_ = (stage == 2 || stage == 4) ? (double)ld32(kp, oi) : 0.0;
+            ra_ = stage == 4 ? ld32(acc, oi) : 0.0;
         };
 #pragma unroll
         for (int f = 0; f < PF; ++f) fetch(f, qy[f], qk[f], qry[f], qrk[f], qra[f]);
@@ -165,33 +180,42 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         qra[f] = qra[f + 1];
                     }
                     fetch(zb + u + PF, qy[PF - 1], qk[PF - 1], qry[PF - 1], qrk[PF - 1], qra[PF - 1]);
+                    // z window of output plane zo: planes zo-H .. zo+H; the new
+                    // plane enters the running sum, the oldest leaves it after
                     {
                         double z[1] = {zc};
                         rb[(u + 2 * H) % S] = to_rb(M::map(z));
                     }
-                    double2 sz = make_double2(0.0, 0.0);
-#pragma unroll
-                    for (int dz = -H; dz <= H; ++dz) {
-                        sz.x += (double)rb[(u + dz + H) % S].x;
-                        sz.y += (double)rb[(u + dz + H) % S].y;
-                    }
+                    const double2 sz = make_double2(zsx + (double)rb[(u + 2 * H) % S].x,
+                                                    zsy + (double)rb[(u + 2 * H) % S].y);
+                    zsx = sz.x - (double)rb[u % S].x;
+                    zsy = sz.y - (double)rb[u % S].y;
                     const int buf = (zb + u) & 1;
                     if (col) S1[buf * HX * HY + tid] = sz;
                     if (inner)
                         S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
                             make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
                     lds_barrier();
-                    // x-pass over the HY rows
-                    for (int q = tid; q < HY * cx; q += blockDim.x) {
-                        const int row = q / cx, xx = q - row * cx;
-                        const double2* src = S1 + buf * HX * HY + row * HX + xx;
+                    // x-pass over the HY rows: sliding window along each run
+                    if (xr) {
+                        const double2* src = S1 + buf * HX * HY + xrow * HX + xs0;
+                        double2* dst = S2 + buf * HY * cx + xrow * cx + xs0;
                         double2 a = make_double2(0.0, 0.0);
 #pragma unroll
                         for (int dx = 0; dx < S; ++dx) {
                             a.x += src[dx].x;
                             a.y += src[dx].y;
                         }
-                        S2[buf * HY * cx + q] = a;
+                        dst[0] = a;
+#pragma unroll
+                        for (int r = 1; r < kRunX; ++r) {
+                            if (r < xcnt) {
+                                const double2 in = src[r + 2 * H], out = src[r - 1];
+                                a.x = (a.x + in.x) - out.x;
+                                a.y = (a.y + in.y) - out.y;
+                                dst[r] = a;
+                            }
+                        }
                     }
                     lds_barrier();
                     // y-pass, RHS, RK bookkeeping
@@ -208,20 +232,20 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         double zdummy[1] = {0.0};
                         double k[1];
                         M::rhs(d, zdummy, xo, W, k);
-                        const int64_t q = obase + plane * zo;
+                        const uint32_t q = obase + plane * (uint32_t)zo;
                         const double kk = kq<KT>(k[0]);
                         if (stage == 1) {
-                            gp((KT*)d.k[0])[q] = (KT)kk;
+                            st32(gp((KT*)d.k[0]), q, (KT)kk);
                             part[0] += xo.x;
                             part[1] += xo.y;
-                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) gp(d.mv)[q] = cry;
+                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) st32(gp(d.mv), q, cry);
                         } else if (stage == 2) {
-                            gp((KT*)d.k[1])[q] = (KT)kk;
-                            gp(d.acc)[q] = fma(d.dt3, kk, fma(d.dt6, crk, cry));
+                            st32(gp((KT*)d.k[1]), q, (KT)kk);
+                            st32(gp(d.acc), q, fma(d.dt3, kk, fma(d.dt6, crk, cry)));
                         } else if (stage == 3) {
-                            gp((KT*)d.k[2])[q] = (KT)kk;
+                            st32(gp((KT*)d.k[2]), q, (KT)kk);
                         } else {
-                            gp(d.y[par ^ 1])[q] = fma(d.dt6, kk, fma(d.dt3, crk, cra));
+                            st32(gp(d.y[par ^ 1]), q, fma(d.dt6, kk, fma(d.dt3, crk, cra)));
                         }
                     }
                 }

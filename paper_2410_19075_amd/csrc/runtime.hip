@@ -79,6 +79,8 @@ nd_status validate_problem(const nd_problem* p) {
             if (p->radius < 1 || p->n1 < side || p->n2 < side || p->n3 < side)
                 return fail(ND_ERR_INVALID_ARG, "cube extents must be >= 2h+1");
             if (p->n1 * p->n2 * p->n3 != p->n) return fail(ND_ERR_INVALID_ARG, "n must equal n1*n2*n3");
+            if (p->n >= (int64_t(1) << 29))
+                return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         }
         case ND_CSR: {
