@@ -17,6 +17,7 @@ nd_status hip_fail(hipError_t e, const char* what);
 int nvars_of(int model);
 nd_status validate_problem(const nd_problem* p);
 nd_kernel_config default_config(const nd_problem* p);
+int device_cu_count();
 bool tuned_config(const nd_problem* p, nd_kernel_config* out);
 int ring_block(int tile);
 int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c);

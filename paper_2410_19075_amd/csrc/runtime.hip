@@ -105,6 +105,52 @@ nd_status validate_problem(const nd_problem* p) {
 }
 
 // ------------------------------------------------------------ configuration
+// Compute units of the current device (256 on MI355X; also the answer when no
+// device can be queried, e.g. for footprint estimates on a host without GPU).
+int device_cu_count() {
+    static const int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+            (void)hipGetLastError();
+            return 256;
+        }
+        return n;
+    }();
+    return cus;
+}
+
+// Cube tiling.  One workgroup of (cx+2h)(cy+2h) column threads holds a CU, and
+// the time of a stage is about (rounds of workgroups over the CUs) x (planes
+// per work item, including the 2h lead-in) x (threads per workgroup), so the
+// tiling minimising that product is taken (ties: fewer halo columns, then
+// wider x for coalescing).
+static void cube_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_) {
+    const int h = (int)p->radius;
+    const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
+    double best = 1e300;
+    *cx_ = 1, *cy_ = 1, *cz_ = n3;
+    for (int cx = 1; cx <= std::min(n1, 64); ++cx) {
+        for (int cy = 1; cy <= std::min(n2, 64); ++cy) {
+            const int halo = (cx + 2 * h) * (cy + 2 * h);
+            if (halo > 1024) break;
+            const int64_t threads = (halo + 63) / 64 * 64;
+            const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
+            for (int zt = 1; zt <= std::min(n3, 256); ++zt) {
+                const int cz = (n3 + zt - 1) / zt;
+                if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;  // same split as a smaller zt
+                const int64_t G = tiles * zt;
+                const int64_t rounds = (G + cus - 1) / cus;
+                const double cost = (double)rounds * (cz + 2 * h) * threads + 1e-2 * halo - 1e-4 * cx;
+                if (cost < best) {
+                    best = cost;
+                    *cx_ = cx, *cy_ = cy, *cz_ = cz;
+                }
+            }
+        }
+    }
+}
+
 nd_kernel_config default_config(const nd_problem* p) {
     nd_kernel_config c{};
     c.grid = 0;
@@ -118,16 +164,13 @@ nd_kernel_config default_config(const nd_problem* p) {
         else c.tile = p->n <= (int64_t(1) << 20) ? 512 : 1024;
         c.block = ring_block(c.tile);
     } else if (p->topo == ND_CUBE3D) {
-        // 20 x 20 outputs per plane (28 x 28 halo columns at h = 4) and 40-plane
-        // z runs: ~500 work items on a 200^3 lattice
+        // e.g. 25 x 20 x 67 on a 200^3 lattice at h = 4: 240 work items, one round
         const int h = (int)p->radius;
-        int cx = (int)std::min<int64_t>(20, p->n1), cy = (int)std::min<int64_t>(20, p->n2);
-        while ((cx + 2 * h) * (cy + 2 * h) > 1024) {
-            if (cx >= cy) --cx; else --cy;
-        }
+        int cx, cy, cz;
+        cube_tiles(p, device_cu_count(), &cx, &cy, &cz);
         c.tile = cx;
         c.tile_y = cy;
-        c.tile_z = (int)std::min<int64_t>(40, p->n3);
+        c.tile_z = cz;
         c.block = cube_block(h, cx, cy);
     } else {
         c.tile = 256;    // target rows per work item
