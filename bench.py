@@ -41,6 +41,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (FMA = 2 flops), vendor figure
+# FP64 flops per element and RK4 step of the resident Kuramoto ring kernel, per
+# stage: sin+cos by reduction and two Horner polynomials (37), window sums from
+# the prefix sums and the self term (8), the rotated RHS (15), stage value and
+# RK bookkeeping (4)
+KURAMOTO_RESIDENT_FLOPS = 4 * (37 + 8 + 15 + 4)
+PROFILES = os.path.join(ROOT, "profiles")
 FHN_PRM = [0.05, 0.5, 0.1, math.pi / 2 - 0.1]
 HH_PRM = [1.0, 120.0, 36.0, 0.3, 50.0, -77.0, -54.387, 0.0, 0.0, 2.0]
 
@@ -51,6 +58,7 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "hh": (1, 5000, 0.01, 1000000),
     "serve": (24, 0, 0.01, 0),
 }
+DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000}
 
 
 def parse():
@@ -99,12 +107,14 @@ class Workload:
                          f"phi=pi/2-0.1, RK4 dt=0.01, {args.horizon} steps per ring, {args.batch} rings "
                          f"(seeds 1000..) per benchmark step")
             self.kernel = "k_ring_stage<FHN>"
+            self.prof = ("ring_stage_fhn_65536_x64.md", "k_ring_stage", ["ring.hip", "models.h", "nd_dev.h", "runtime.hip"])
         elif w == "kuramoto":
             self.n, self.P = args.n, args.n // 4
             self.nvars, self.links = 1, 2 * self.P
             self.name = (f"Kuramoto-Sakaguchi ring N={self.n} P={self.P}, alpha=1.46 mu=1 omega=0, RK4 dt=0.01, "
                          f"{args.horizon} steps, {args.batch} rings per benchmark step")
-            self.kernel = "k_ring_stage<Kuramoto>"
+            self.kernel = "k_ring_resident<Kuramoto>"
+            self.prof = None
         elif w == "cube":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, 4
@@ -112,12 +122,14 @@ class Workload:
             self.name = (f"Kuramoto-Sakaguchi 3D lattice {args.n}^3 periodic, cube half-width 4 (728 neighbours), "
                          f"alpha=0.8 mu=1 omega=0, RK4 dt=0.05, {args.horizon} steps, planted coherent ball")
             self.kernel = "k_cube_stage"
+            self.prof = ("cube_stage_200cubed_h4.md", "k_cube_stage", ["cube.hip", "models.h", "nd_dev.h", "runtime.hip"])
         else:
             self.n = args.n
             self.nvars, self.links = 4, 100
             self.name = (f"Hodgkin-Huxley N={self.n}, random directed graph out-degree 100 (nnz={self.n * 100}), "
                          f"w U[0,0.1], I_app U[8,12], RK4 dt=0.01 ms, {args.horizon} steps")
-            self.kernel = "k_csr_stage"
+            self.kernel = "k_csr_gather + k_csr_update"
+            self.prof = ("csr_hh_1e6_deg100.md", "k_csr_gather|k_csr_update", ["csr.hip", "nd_dev.h", "runtime.hip"])
             from paper_2410_19075_amd import inputs
             self.graph = inputs.random_out_graph(1, self.n, 100)
             self.iapp = inputs.hh_iapp(1, self.n)
@@ -232,16 +244,37 @@ def cpu_baseline(wl, args):
             "sample": f"{what}, {steps} RK4 step(s), FP64, direct neighbour sums, {dt:.2f} s"}
 
 
-def roofline(wl, args, prec, ev_total):
+def roofline(wl, args, prec, ev_total, cfg):
     """Algorithmic bytes of one stage launch over the measured average stage time
     (HIP events on the launch stream; the chunk's few small bookkeeping kernels
-    are included, so the stage time is an upper bound)."""
+    are included, so the stage time is an upper bound).  `traffic` is the HBM
+    bytes per launch from the committed rocprofv3 counter summary, when that was
+    taken on the current kernel sources (else null)."""
+    from paper_2410_19075_amd import profsum
+    if args.workload == "kuramoto" and cfg["tile"] < 0:
+        # rings resident in one workgroup for a whole chunk: no HBM traffic
+        # between stages, so the bound is the FP64 ALU rate
+        launches = args.steps * -(-args.horizon // max(1, cfg["chunk"]))
+        flops = args.batch * wl.n * args.horizon * args.steps * KURAMOTO_RESIDENT_FLOPS
+        achieved = flops / ev_total / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": wl.kernel,
+                "flops_per_launch": flops / launches, "avg_launch_us": ev_total / launches * 1e6}
     n_stage = 4 * args.horizon * args.steps
     stage_s = ev_total / n_stage
     per_launch = args.batch * wl.n * wl.bytes_alg_per_elem_step(prec) / 4.0
     achieved = per_launch / stage_s / 1e9
+    traffic = None
+    if wl.prof:
+        md, kf, files = wl.prof
+        t = profsum.read_traffic(os.path.join(PROFILES, md), kf, "f64" if prec == 0 else "f32", files)
+        # the summary's workload is the default one; other sizes scale with the elements
+        default_shape = (args.batch == DEFAULTS[args.workload][0] and wl.n == DEFAULTS_N[args.workload]
+                         and not (args.tile or args.tile_y or args.tile_z or args.grid or args.chunk))
+        if t is not None and default_shape:
+            traffic = t
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": wl.kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": wl.kernel,
             "bytes_per_launch": per_launch, "avg_launch_us": stage_s * 1e6}
 
 
@@ -409,14 +442,14 @@ def main():
         "batch_latency_ms": {"p50": 1e3 * float(np.percentile(times, 50)),
                              "p99": 1e3 * float(np.percentile(times, 99))},
         "state_finite": finite,
-        "roofline": roofline(wl, args, 0, ev_total),
+        "roofline": roofline(wl, args, 0, ev_total, cfg),
     }
     if not args.no_fp32:
-        wall32, times32, ev32, fin32, _ = run(nd, torch, wl, args, nd.ND_FP32_BULK, stream)
+        wall32, times32, ev32, fin32, cfg32 = run(nd, torch, wl, args, nd.ND_FP32_BULK, stream)
         v32 = osc_per_step * args.steps / wall32
         out["fp32_bulk"] = {"value": v32, "unit": "oscillator-steps/s", "ms_per_step": 1e3 * wall32 / args.steps,
                             "coupling_terms_per_s": v32 * wl.links * 4,
-                            "roofline": roofline(wl, args, 1, ev32), "state_finite": fin32}
+                            "roofline": roofline(wl, args, 1, ev32, cfg32), "state_finite": fin32}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args)
     print(json.dumps(out), flush=True)
