@@ -73,10 +73,11 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
         }
     } else if (p->topo == ND_CUBE3D) {
         const int h = (int)p->radius;
+        v.push_back(base);  // the cost-model tiling (one round of workgroups where possible)
         const int shapes[][2] = {{20, 20}, {24, 24}, {32, 16}, {16, 16}, {40, 10}, {25, 20}};
         for (auto& sh : shapes) {
             if ((sh[0] + 2 * h) * (sh[1] + 2 * h) > 1024) continue;
-            for (int cz : {20, 40, 100}) {
+            for (int cz : {base.tile_z, 40, 100}) {
                 nd_kernel_config c = base;
                 c.tile = (int)std::min<int64_t>(sh[0], p->n1);
                 c.tile_y = (int)std::min<int64_t>(sh[1], p->n2);

@@ -218,3 +218,21 @@ def test_tile_grid_and_chunk_configs(nd, tile, grid, chunk):
     ref, Rref, _ = O.run(O.ring(O.FHN, n, P, FHN_PRM), y0, 0.01, 37, record_every=4)
     assert normwise(y, ref, 2) < 1e-12
     assert np.max(np.abs(R - Rref)) < 1e-12
+
+
+@pytest.mark.parametrize("tile", [-1024, -4096, 512])
+def test_kuramoto_phase_shift_invariance_large_phases(nd, tile):
+    """Shifting every phase by its own multiple 2*pi*k_i (|k_i| up to 1e5, phases
+    up to ~6e5) leaves the dynamics unchanged: the GPU run from the shifted state,
+    minus the shifts, matches the oracle from the unshifted one.  Exercises the
+    argument reduction of the FP64 sin/cos far from the origin."""
+    n, P, prm = (1000, 300, [0.3, 1.0, 1.46]) if tile != 512 else (5000, 1400, [0.3, 1.0, 1.46])
+    y0 = inputs.kuramoto_phases(21, n)
+    k = np.floor(inputs.uniform(22, inputs.TAG_MISC, n) * 2e5 - 1e5)
+    shift = 2 * np.pi * k
+    ys = y0 + shift
+    print(f"case shift tile={tile} n={n}", flush=True)
+    y, _ = run_with_config(nd, nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, prm, radius=P), ys, 0.01, 50, tile=tile)
+    ref, _, _ = O.run(O.ring(O.KURAMOTO, n, P, prm), y0, 0.01, 50)
+    # the shifted state carries ~1e-10 rounding per step in y itself
+    assert np.max(np.abs((y - shift) - ref)) < 2e-8
