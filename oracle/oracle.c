@@ -25,6 +25,10 @@
  *     or on a periodic n1 x n2 x n3 lattice with the cube neighbourhood of
  *     half-width h minus the element itself (L = (2h+1)^3 - 1); lattice index
  *     x + n1*y + n1*n2*z as in the paper's 3D index map (Sec. IV).
+ *   Kuramoto-Sakaguchi with inertia, Eq. (3) with m != 0 (plus omega), as a
+ *     first-order system in (phi, psi = dphi/dt), same neighbourhoods:
+ *       dphi_i/dt = psi_i
+ *       m dpsi_i/dt = omega - eps psi_i + (mu / L) * sum_j sin(phi_j - phi_i - alpha)
  *   FitzHugh-Nagumo, Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational
  *     coupling matrix B(phi) acting on (u_j - u_i, v_j - v_i), averaged over
  *     the 2P ring neighbours and placed inside the eps-scaled fast equation:
@@ -52,7 +56,7 @@
 #define ORC_EINVAL -1
 #define ORC_ENOMEM -2
 
-enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2 };
+enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2, ORC_INERTIA = 3 };
 enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2 };
 
 typedef struct {
@@ -74,22 +78,67 @@ static int64_t wrapi(int64_t i, int64_t n) {
 }
 
 /* ---------------------------------------------------------------- Kuramoto */
-/* prm = {omega, mu, alpha} */
-static void rhs_kuramoto_ring(const orc_net* m, const double* z, double* f) {
+/* Coupling term of element i: (1/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
+ * the neighbour sum of Eq. (3) divided by the link count (Alg. 1). */
+static double kuramoto_ring_coupling(const orc_net* m, const double* z, int64_t i, double alpha) {
     const int64_t n = m->n, P = m->radius;
+    double s = 0.0;
+    /* neighbour order: i-P, ..., i-1, i+1, ..., i+P (or reversed) */
+    for (int64_t t = 0; t < 2 * P; ++t) {
+        int64_t q = m->reverse ? (2 * P - 1 - t) : t;
+        int64_t k = (q < P) ? (q - P) : (q - P + 1);
+        int64_t j = wrapi(i + k, n);
+        s += sin(z[j] - z[i] - alpha);
+    }
+    return s * (1.0 / (double)(2 * P));
+}
+
+/* Kuramoto, prm = {omega, mu, alpha} */
+static void rhs_kuramoto_ring(const orc_net* m, const double* z, double* f) {
     const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2];
-    const double inv_links = 1.0 / (double)(2 * P);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m->n; ++i) f[i] = omega + mu * kuramoto_ring_coupling(m, z, i, alpha);
+}
+
+/* Kuramoto with inertia, prm = {omega, mu, alpha, m, eps}; z = (phi, psi) */
+static void rhs_inertia_ring(const orc_net* m, const double* z, double* f) {
+    const int64_t n = m->n;
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2], mass = m->prm[3], eps = m->prm[4];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
-        /* neighbour order: i-P, ..., i-1, i+1, ..., i+P (or reversed) */
-        for (int64_t t = 0; t < 2 * P; ++t) {
-            int64_t q = m->reverse ? (2 * P - 1 - t) : t;
-            int64_t k = (q < P) ? (q - P) : (q - P + 1);
-            int64_t j = wrapi(i + k, n);
-            s += sin(z[j] - z[i] - alpha);
-        }
-        f[i] = omega + mu * (s * inv_links);
+        const double psi = z[n + i];
+        f[i] = psi;
+        f[n + i] = (omega - eps * psi + mu * kuramoto_ring_coupling(m, z, i, alpha)) / mass;
+    }
+}
+
+static double kuramoto_cube_coupling(const orc_net* m, const double* z, int64_t i, double alpha) {
+    const int64_t n1 = m->n1, n2 = m->n2, n3 = m->n3, h = m->radius;
+    const int64_t side = 2 * h + 1;
+    const int64_t links = side * side * side - 1;
+    const int64_t x = i % n1, y = (i / n1) % n2, zz = i / (n1 * n2);
+    double s = 0.0;
+    /* lexicographic dz, dy, dx in [-h, h], self skipped (or reversed) */
+    for (int64_t t = 0; t < side * side * side; ++t) {
+        int64_t q = m->reverse ? (side * side * side - 1 - t) : t;
+        int64_t dz = q / (side * side) - h;
+        int64_t dy = (q / side) % side - h;
+        int64_t dx = q % side - h;
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        int64_t j = wrapi(x + dx, n1) + n1 * (wrapi(y + dy, n2) + n2 * wrapi(zz + dz, n3));
+        s += sin(z[j] - z[i] - alpha);
+    }
+    return s * (1.0 / (double)links);
+}
+
+static void rhs_inertia_cube(const orc_net* m, const double* z, double* f) {
+    const int64_t n = m->n;
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2], mass = m->prm[3], eps = m->prm[4];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double psi = z[n + i];
+        f[i] = psi;
+        f[n + i] = (omega - eps * psi + mu * kuramoto_cube_coupling(m, z, i, alpha)) / mass;
     }
 }
 
@@ -181,11 +230,15 @@ static void rhs_hh_csr(const orc_net* m, const double* z, double* f) {
     }
 }
 
-static int nvars(int model) { return model == ORC_KURAMOTO ? 1 : (model == ORC_FHN ? 2 : 4); }
+static int nvars(int model) {
+    return model == ORC_KURAMOTO ? 1 : (model == ORC_HH ? 4 : 2);
+}
 
 static int rhs(const orc_net* m, const double* z, double* f) {
     if (m->model == ORC_KURAMOTO && m->topo == ORC_RING) rhs_kuramoto_ring(m, z, f);
     else if (m->model == ORC_KURAMOTO && m->topo == ORC_CUBE) rhs_kuramoto_cube(m, z, f);
+    else if (m->model == ORC_INERTIA && m->topo == ORC_RING) rhs_inertia_ring(m, z, f);
+    else if (m->model == ORC_INERTIA && m->topo == ORC_CUBE) rhs_inertia_cube(m, z, f);
     else if (m->model == ORC_FHN && m->topo == ORC_RING) rhs_fhn_ring(m, z, f);
     else if (m->model == ORC_HH && m->topo == ORC_CSR) rhs_hh_csr(m, z, f);
     else return ORC_EINVAL;

@@ -7,15 +7,16 @@ Model / topology codes and parameter vectors follow oracle.c:
   Kuramoto  params = (omega, mu, alpha)                       Eq. (3), m=0, eps=1
   FHN       params = (eps, a, sigma, phi)                     Eq. (2) + rotational coupling
   HH        params = (C, gNa, gK, gL, ENa, EK, EL, Esyn, theta_s, k_s)   Eq. (1)
+  Inertia   params = (omega, mu, alpha, m, eps)                Eq. (3), m != 0; state (phi, psi)
 """
 import ctypes
 import os
 
 import numpy as np
 
-KURAMOTO, FHN, HH = 0, 1, 2
+KURAMOTO, FHN, HH, INERTIA = 0, 1, 2, 3
 RING, CUBE, CSR = 0, 1, 2
-NVARS = {KURAMOTO: 1, FHN: 2, HH: 4}
+NVARS = {KURAMOTO: 1, FHN: 2, HH: 4, INERTIA: 2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -72,10 +73,10 @@ def ring(model, n, P, params):
     return Net(model, RING, n, params, radius=P)
 
 
-def cube(n1, h, params, n2=None, n3=None):
+def cube(n1, h, params, n2=None, n3=None, model=KURAMOTO):
     n2 = n1 if n2 is None else n2
     n3 = n1 if n3 is None else n3
-    return Net(KURAMOTO, CUBE, n1 * n2 * n3, params, radius=h, dims=(n1, n2, n3))
+    return Net(model, CUBE, n1 * n2 * n3, params, radius=h, dims=(n1, n2, n3))
 
 
 def csr(n, row_ptr, col, w, params, i_app):

@@ -543,3 +543,100 @@ def test_fp64_self_floor_c1_small():
     e = np.max(np.abs(a - b)) / np.max(np.abs(a))
     assert 0 < e < 1e-13
     assert np.max(np.abs(Ra - Rb)) < 1e-13
+
+
+# ------------------------------------------------- Kuramoto with inertia, Eq. (3)
+def inert(omega, mu, alpha, m, eps):
+    return np.array([omega, mu, alpha, m, eps])
+
+
+def test_inertia_zero_coupling_closed_form():
+    """mu = 0: m psi' = omega - eps psi is linear, so
+    psi(t) = w + (psi0 - w) e^{-eps t/m},  phi(t) = phi0 + w t + (psi0 - w)(m/eps)(1 - e^{-eps t/m}),
+    w = omega/eps.  Checks the placement of m, eps and omega."""
+    n, P = 40, 3
+    omega, m, eps = 0.7, 2.5, 0.4
+    phi0 = inputs.kuramoto_phases(5, n)
+    psi0 = inputs.uniform_range(6, inputs.TAG_MISC, n, -1.0, 1.0)
+    dt, steps = 0.01, 500
+    y, _, _ = O.run(O.ring(O.INERTIA, n, P, inert(omega, 0.0, 1.0, m, eps)), np.concatenate([phi0, psi0]), dt, steps)
+    t = dt * steps
+    w = omega / eps
+    decay = math.exp(-eps * t / m)
+    psi = w + (psi0 - w) * decay
+    phi = phi0 + w * t + (psi0 - w) * (m / eps) * (1.0 - decay)
+    assert np.max(np.abs(y[n:] - psi)) < 1e-12
+    assert np.max(np.abs(y[:n] - phi)) < 1e-11
+
+
+@pytest.mark.parametrize("q", [0, 1, 3, 7])
+def test_inertia_ring_twisted_state_steady_rotation(q):
+    """A q-twisted state with psi = Omega everywhere is an exact solution when
+    eps Omega = omega + mu * (coupling of the twist) = eps * (first-order
+    twist frequency with omega -> omega, i.e. Omega = f_q / eps)."""
+    n, P = 60, 11
+    omega, mu, alpha, m, eps = 0.3, 1.2, 0.45, 1.0, 0.05
+    f = ring_twist_frequency(n, P, q, omega, mu, alpha)  # omega + mu * coupling
+    Om = f / eps
+    phi0 = 2 * math.pi * q * np.arange(n) / n
+    y0 = np.concatenate([phi0, np.full(n, Om)])
+    dt, steps = 0.01, 100
+    y, _, _ = O.run(O.ring(O.INERTIA, n, P, inert(omega, mu, alpha, m, eps)), y0, dt, steps)
+    assert np.max(np.abs(y[n:] - Om)) < 1e-10 * max(1.0, abs(Om))
+    assert np.max(np.abs((y[:n] - phi0) - Om * dt * steps)) < 1e-10 * max(1.0, abs(Om))
+
+
+def test_inertia_cube_plane_wave_steady_rotation():
+    dims, h = (9, 10, 11), 2
+    n1, n2, n3 = dims
+    idx = np.arange(n1 * n2 * n3)
+    x, yy, z = idx % n1, (idx // n1) % n2, idx // (n1 * n2)
+    q = (1, -2, 1)
+    phi0 = 2 * math.pi * (q[0] * x / n1 + q[1] * yy / n2 + q[2] * z / n3)
+    omega, mu, alpha, m, eps = 0.1, 0.9, 0.45, 1.0, 0.5
+    Om = cube_wave_frequency(dims, h, q, omega, mu, alpha) / eps
+    y0 = np.concatenate([phi0, np.full(phi0.size, Om)])
+    net = O.cube(n1, h, inert(omega, mu, alpha, m, eps), n2=n2, n3=n3, model=O.INERTIA)
+    y, _, _ = O.run(net, y0, 0.05, 20)
+    assert np.max(np.abs(y[phi0.size:] - Om)) < 1e-12
+    assert np.max(np.abs((y[:phi0.size] - phi0) - Om * 1.0)) < 1e-12
+
+
+def test_inertia_time_rescaling_invariance():
+    """Multiplying m, eps, mu and omega by the same factor leaves the equations
+    unchanged (every term of m psi' = ... scales alike)."""
+    n, P = 50, 6
+    y0 = np.concatenate([inputs.kuramoto_phases(8, n), inputs.uniform_range(9, inputs.TAG_MISC, n, -0.5, 0.5)])
+    a, _, _ = O.run(O.ring(O.INERTIA, n, P, inert(0.2, 1.0, 0.45, 1.0, 0.05)), y0, 0.01, 200)
+    b, _, _ = O.run(O.ring(O.INERTIA, n, P, inert(0.2 * 4, 1.0 * 4, 0.45, 1.0 * 4, 0.05 * 4)), y0, 0.01, 200)
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def inertia_dense(A, omega, mu, alpha, m, eps):
+    L = A.sum(axis=1)
+    n = A.shape[0]
+
+    def F(y):
+        phi, psi = y[:n], y[n:]
+        coup = np.imag(np.exp(-1j * (phi + alpha)) * (A @ np.exp(1j * phi))) / L
+        return np.concatenate([psi, (omega - eps * psi + mu * coup) / m])
+
+    return F
+
+
+@pytest.mark.parametrize("topo", ["ring", "cube"])
+def test_inertia_dense_brute_force(topo):
+    prm = (0.15, 1.3, 0.45, 1.7, 0.3)
+    if topo == "ring":
+        n, P = 40, 9
+        A = ring_adjacency(n, P)
+        net = O.ring(O.INERTIA, n, P, inert(*prm))
+    else:
+        dims, h = (6, 7, 8), 2
+        n = 6 * 7 * 8
+        A = cube_adjacency(dims, h)
+        net = O.cube(6, h, inert(*prm), n2=7, n3=8, model=O.INERTIA)
+    y0 = np.concatenate([inputs.kuramoto_phases(11, n), inputs.uniform_range(12, inputs.TAG_MISC, n, -1.0, 1.0)])
+    ref = dense_rk4(inertia_dense(A, *prm), y0, 0.02, 100)
+    y, _, _ = O.run(net, y0, 0.02, 100)
+    assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-13
