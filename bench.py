@@ -17,6 +17,10 @@ Other workloads (one JSON line each, same fields):
                        out-degree 100, weights U[0, 0.1], I_app U[8, 12],
                        dt = 0.01 ms, 5000 steps
   --workload kuramoto  Kuramoto rings N = 1024, P = 256, alpha = 1.46, 200 steps
+  --workload inertia   3D Kuramoto-Sakaguchi with inertia, 100^3 periodic lattice,
+                       m = 1, eps = 0.05, mu = 0.01, alpha = 0.45 (the paper's
+                       performance state), cube half-width 2 (124 neighbours),
+                       dt = 0.05, 1000 steps (50 time units), psi = 0 initially
   --workload serve     continuous-batching server fed by seeded Poisson arrivals of
                        Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
                        [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
@@ -56,9 +60,11 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "kuramoto": (4096, 200, 0.01, 1024),
     "cube": (1, 2000, 0.05, 200),
     "hh": (1, 5000, 0.01, 1000000),
+    "inertia": (1, 1000, 0.05, 100),
     "serve": (24, 0, 0.01, 0),
 }
-DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000}
+DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3}
+INERTIA_PRM = [0.0, 0.01, 0.45, 1.0, 0.05]  # omega, mu, alpha, m, eps (Sec. V, Fig. 6c)
 
 
 def parse():
@@ -115,6 +121,15 @@ class Workload:
                          f"{args.horizon} steps, {args.batch} rings per benchmark step")
             self.kernel = "k_ring_resident<Kuramoto>"
             self.prof = None
+        elif w == "inertia":
+            self.n1 = args.n
+            self.n, self.P = args.n ** 3, 2
+            self.nvars, self.links = 2, 124
+            self.name = (f"Kuramoto-Sakaguchi with inertia, 3D lattice {args.n}^3 periodic, cube half-width 2 "
+                         f"(124 neighbours), m=1 eps=0.05 mu=0.01 alpha=0.45 omega=0, RK4 dt=0.05, "
+                         f"{args.horizon} steps, planted coherent ball, psi=0")
+            self.kernel = "k_cube_stage<inertia>"
+            self.prof = None
         elif w == "cube":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, 4
@@ -143,6 +158,9 @@ class Workload:
         if w == "cube":
             return nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, self.n, [0.0, 1.0, 0.8], precision=prec, radius=4,
                               dims=(self.n1,) * 3)
+        if w == "inertia":
+            return nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_CUBE3D, self.n, INERTIA_PRM, precision=prec, radius=2,
+                              dims=(self.n1,) * 3)
         rp, col, wt = self.graph
         return nd.problem(nd.ND_HH, nd.ND_CSR, self.n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=wt,
                           per_elem=self.iapp)
@@ -156,6 +174,8 @@ class Workload:
             return inputs.kuramoto_phases(1000 + b, self.n)
         if w == "cube":
             return inputs.cube_phases_with_patch(1000 + b, self.n1)
+        if w == "inertia":
+            return np.concatenate([inputs.cube_phases_with_patch(1000 + b, self.n1), np.zeros(self.n)])
         return inputs.hh_state(1000 + b, self.n)
 
     def bytes_alg_per_elem_step(self, prec):
@@ -233,6 +253,9 @@ def cpu_baseline(wl, args):
         net, steps, what = O.ring(O.KURAMOTO, wl.n, wl.P, [0.0, 1.0, 1.46]), 200, f"one Kuramoto ring N={wl.n}"
     elif w == "cube":
         net, steps, what = O.cube(wl.n1, 4, [0.0, 1.0, 0.8]), 1, f"the {wl.n1}^3 lattice, h=4"
+    elif w == "inertia":
+        net, steps, what = (O.cube(wl.n1, 2, INERTIA_PRM, model=O.INERTIA), 2,
+                            f"the {wl.n1}^3 lattice with inertia, h=2")
     else:
         rp, col, wt = wl.graph
         net, steps, what = O.csr(wl.n, rp, col, wt, HH_PRM, wl.iapp), args.cpu_sample_steps, f"HH N={wl.n} deg 100"

@@ -17,6 +17,11 @@
  *                dphi_i/dt = omega + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
  *                L = number of neighbours (the paper's Alg. 1 divides by the link count).
  *                params = {omega, mu, alpha}.  Topology ND_RING or ND_CUBE3D.
+ *   ND_KURAMOTO_INERTIA  Eq. (3) with inertia (m != 0) as a first-order system in
+ *                (phi, psi = dphi/dt), plus a natural frequency:
+ *                dphi_i/dt = psi_i,
+ *                m dpsi_i/dt = omega - eps psi_i + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha).
+ *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING or ND_CUBE3D.
  *   ND_FHN       Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational coupling
  *                matrix B(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] applied to
  *                (u_j - u_i, v_j - v_i), averaged over the 2P ring neighbours, inside the
@@ -38,7 +43,8 @@
  *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
  *
  * State layout: variable-major FP64, length nvars * n: Kuramoto phi[n] (unwrapped, never reduced
- * mod 2 pi); FHN u[n] then v[n]; HH V[n], m[n], h[n], n[n].
+ * mod 2 pi); Kuramoto with inertia phi[n] then psi[n]; FHN u[n] then v[n]; HH V[n], m[n], h[n],
+ * n[n].
  *
  * Precision: ND_FP64 computes everything in IEEE double.  ND_FP32_BULK computes the per-element
  * maps (sin/cos, sigmoid, rate functions) and the local right-hand side in float and stores the
@@ -80,6 +86,7 @@ typedef int32_t nd_status;
 #define ND_KURAMOTO 0
 #define ND_FHN 1
 #define ND_HH 2
+#define ND_KURAMOTO_INERTIA 3
 
 #define ND_RING 0
 #define ND_CUBE3D 1
@@ -92,7 +99,7 @@ typedef int32_t nd_status;
 
 /* A network: model, parameters, topology, precision.  All pointers are host pointers. */
 typedef struct nd_problem {
-    int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH */
+    int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA */
     int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR */
     int32_t precision;  /* ND_FP64, ND_FP32_BULK */
     int32_t reserved;   /* must be 0 */

@@ -52,10 +52,11 @@ __device__ __forceinline__ void block_sum_rt(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
-template <class KT, int H, int STAGE, bool MV>
+template <int MODEL, class KT, int H, int STAGE, bool MV>
 __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
                                                     const int* __restrict__ nwork_p, int j) {
-    using M = RingModel<ND_KURAMOTO, KT>;
+    using M = RingModel<MODEL, KT>;  // Kuramoto (phi) or Kuramoto with inertia (phi, psi)
+    constexpr int V = M::V;
     constexpr int S = 2 * H + 1;
     constexpr int stage = STAGE;
     extern __shared__ double2 smem[];
@@ -229,11 +230,26 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         }
                         const double2 xo = S0[buf * cx * cy + oy * cx + ox];
                         const double2 W = make_double2(bsum.x - xo.x, bsum.y - xo.y);
-                        double zdummy[1] = {0.0};
-                        double k[1];
-                        M::rhs(d, zdummy, xo, W, k);
                         const uint32_t q = obase + plane * (uint32_t)zo;
+                        // variable 1 (psi, inertia only): operands read here, not prefetched
+                        double y1 = 0.0, kp1 = 0.0, a1 = 0.0;
+                        double zz[V];
+                        zz[0] = 0.0;  // the phase enters through xo
+                        if constexpr (V == 2) {
+                            y1 = ld32(y + n, q);
+                            kp1 = stage != 1 ? (double)ld32(kp + n, q) : 0.0;
+                            a1 = stage == 4 ? ld32(acc + n, q) : 0.0;
+                            zz[V - 1] = stage == 1 ? y1 : fma(cdt, kp1, y1);
+                        }
+                        double k[V];
+                        M::rhs(d, zz, xo, W, k);
                         const double kk = kq<KT>(k[0]);
+                        if constexpr (V == 2) {
+                            const double kk1 = kq<KT>(k[1]);
+                            if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + n, q, (KT)kk1);
+                            if (stage == 2) st32(gp(d.acc) + n, q, fma(d.dt3, kk1, fma(d.dt6, kp1, y1)));
+                            if (stage == 4) st32(gp(d.y[par ^ 1]) + n, q, fma(d.dt6, kk1, fma(d.dt3, kp1, a1)));
+                        }
                         if (stage == 1) {
                             st32(gp((KT*)d.k[0]), q, (KT)kk);
                             part[0] += xo.x;
@@ -317,38 +333,45 @@ __global__ __launch_bounds__(256) void k_cube_final_R(const NetDesc* __restrict_
 }
 
 // ------------------------------------------------------------------ launch
-template <class KT, int H>
+template <int MODEL, class KT, int H>
 static void cube_entry(CubeLaunch* r) {
-    r->stage[0] = k_cube_stage<KT, H, 1, false>;
-    r->stage[1] = k_cube_stage<KT, H, 2, false>;
-    r->stage[2] = k_cube_stage<KT, H, 3, false>;
-    r->stage[3] = k_cube_stage<KT, H, 4, false>;
-    r->stage_mv[0] = k_cube_stage<KT, H, 1, true>;
-    r->stage_mv[1] = k_cube_stage<KT, H, 2, true>;
-    r->stage_mv[2] = k_cube_stage<KT, H, 3, true>;
-    r->stage_mv[3] = k_cube_stage<KT, H, 4, true>;
+    r->stage[0] = k_cube_stage<MODEL, KT, H, 1, false>;
+    r->stage[1] = k_cube_stage<MODEL, KT, H, 2, false>;
+    r->stage[2] = k_cube_stage<MODEL, KT, H, 3, false>;
+    r->stage[3] = k_cube_stage<MODEL, KT, H, 4, false>;
+    r->stage_mv[0] = k_cube_stage<MODEL, KT, H, 1, true>;
+    r->stage_mv[1] = k_cube_stage<MODEL, KT, H, 2, true>;
+    r->stage_mv[2] = k_cube_stage<MODEL, KT, H, 3, true>;
+    r->stage_mv[3] = k_cube_stage<MODEL, KT, H, 4, true>;
     r->final_partials = k_cube_final_partials<KT>;
     r->final_R = k_cube_final_R;
 }
 
-bool cube_select(int prec, int h, CubeLaunch* out) {
-    if (h < 1 || h > 4) return false;
+template <int MODEL>
+static bool cube_pick(int prec, int h, CubeLaunch* out) {
     if (prec == ND_FP64) {
         switch (h) {
-            case 1: cube_entry<double, 1>(out); break;
-            case 2: cube_entry<double, 2>(out); break;
-            case 3: cube_entry<double, 3>(out); break;
-            default: cube_entry<double, 4>(out); break;
+            case 1: cube_entry<MODEL, double, 1>(out); break;
+            case 2: cube_entry<MODEL, double, 2>(out); break;
+            case 3: cube_entry<MODEL, double, 3>(out); break;
+            default: cube_entry<MODEL, double, 4>(out); break;
         }
     } else {
         switch (h) {
-            case 1: cube_entry<float, 1>(out); break;
-            case 2: cube_entry<float, 2>(out); break;
-            case 3: cube_entry<float, 3>(out); break;
-            default: cube_entry<float, 4>(out); break;
+            case 1: cube_entry<MODEL, float, 1>(out); break;
+            case 2: cube_entry<MODEL, float, 2>(out); break;
+            case 3: cube_entry<MODEL, float, 3>(out); break;
+            default: cube_entry<MODEL, float, 4>(out); break;
         }
     }
     return true;
+}
+
+bool cube_select(int model, int prec, int h, CubeLaunch* out) {
+    if (h < 1 || h > 4) return false;
+    if (model == ND_KURAMOTO) return cube_pick<ND_KURAMOTO>(prec, h, out);
+    if (model == ND_KURAMOTO_INERTIA) return cube_pick<ND_KURAMOTO_INERTIA>(prec, h, out);
+    return false;
 }
 
 size_t cube_smem_bytes(int h, int cx, int cy) {

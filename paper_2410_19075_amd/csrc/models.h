@@ -84,6 +84,27 @@ struct RingModel<ND_KURAMOTO, KT> {
     }
 };
 
+// Kuramoto-Sakaguchi with inertia, Eq. (3) with m != 0, as a first-order
+// system in (phi, psi = dphi/dt); the coupling is the Kuramoto one on phi:
+//   dphi = psi,  dpsi = (omega - eps psi + mu/L [cos(phi+alpha) S - sin(phi+alpha) C]) / m
+// p = {omega, mu/L, cos alpha, sin alpha, eps, 1/m}
+template <class KT>
+struct RingModel<ND_KURAMOTO_INERTIA, KT> {
+    static constexpr int V = 2;
+    __device__ static __forceinline__ double2 map(const double* z) { return RingModel<ND_KURAMOTO, KT>::map(z); }
+    __device__ static __forceinline__ void rhs(const NetDesc& d, const double* z, double2 xo, double2 W,
+                                               double* k) {
+        double force[1];
+        RingModel<ND_KURAMOTO, KT>::rhs(d, z, xo, W, force);  // omega + coupling, as first-order Kuramoto
+        k[0] = z[1];
+        if constexpr (sizeof(KT) == 8) {
+            k[1] = fma(-d.p[4], z[1], force[0]) * d.p[5];
+        } else {
+            k[1] = (double)(((float)force[0] - (float)d.p[4] * (float)z[1]) * (float)d.p[5]);
+        }
+    }
+};
+
 // FitzHugh-Nagumo, Eq. (2) (tau = 0, D = 0, I_app = 0) with the rotational
 // coupling B(phi) on (u_j - u_i, v_j - v_i), kappa = sigma / 2P:
 //   eps du = u - u^3/3 - v + kappa ( cos phi Du + sin phi Dv)

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                 }
                 // mean phase velocity (compiled only into the MV variants)
                 if (MV && (d.obs & OBS_MV) && g >= d.mv_start) {
-                    if constexpr (MODEL == ND_KURAMOTO) {
+                    if constexpr (MODEL != ND_FHN) {  // phase models: unwrapped phase is variable 0
                         if (stage == 1 && g == d.mv_start) gp(d.mv)[i] = yv[e][0];
                     } else {
                         if (stage == 4) {
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
                         const double2 W = make_double2(w0 - x[e].x, w1 - x[e].y);
                         double k[V];
                         M::rhs(d, z[e], x[e], W, k);
-                        if (MV && (d.obs & OBS_MV) && g == d.mv_start && s == 1 && MODEL == ND_KURAMOTO)
+                        if (MV && (d.obs & OBS_MV) && g == d.mv_start && s == 1 && MODEL != ND_FHN)
                             gp(d.mv)[i] = y[e][0];
                         double yo[V];
 #pragma unroll
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(BS) void k_ring_epilogue(const NetDesc* __restrict_
             const double* y = d.y[par];
             for (int m = threadIdx.x; m < cnt; m += BS) {
                 const int64_t i = t0 + m;
-                if constexpr (MODEL == ND_KURAMOTO)
+                if constexpr (MODEL != ND_FHN)
                     d.mv[i] = (y[i] - d.mv[i]) * d.mv_scale;
                 else
                     d.mv[i] = d.mv[i] * d.mv_scale;
@@ -580,6 +580,9 @@ bool ring_select(int model, int prec, int tile, RingLaunch* out) {
         return prec == ND_FP64 ? ring_pick<ND_KURAMOTO, double>(tile, out) : ring_pick<ND_KURAMOTO, float>(tile, out);
     if (model == ND_FHN)
         return prec == ND_FP64 ? ring_pick<ND_FHN, double>(tile, out) : ring_pick<ND_FHN, float>(tile, out);
+    if (model == ND_KURAMOTO_INERTIA)
+        return prec == ND_FP64 ? ring_pick<ND_KURAMOTO_INERTIA, double>(tile, out)
+                               : ring_pick<ND_KURAMOTO_INERTIA, float>(tile, out);
     return false;
 }
 

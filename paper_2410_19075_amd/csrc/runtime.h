@@ -101,7 +101,7 @@ struct CubeLaunch {
     void (*final_partials)(const NetDesc*, const int2*, const int*, int);
     void (*final_R)(const NetDesc*, const int2*, const int*, int);
 };
-bool cube_select(int prec, int h, CubeLaunch* out);
+bool cube_select(int model, int prec, int h, CubeLaunch* out);
 size_t cube_smem_bytes(int h, int cx, int cy);
 int cube_block(int h, int cx, int cy);
 hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,

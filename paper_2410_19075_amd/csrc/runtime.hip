@@ -43,7 +43,7 @@ nd_status hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 // ------------------------------------------------------------ validation
-int nvars_of(int model) { return model == ND_KURAMOTO ? 1 : (model == ND_FHN ? 2 : 4); }
+int nvars_of(int model) { return model == ND_KURAMOTO ? 1 : (model == ND_HH ? 4 : 2); }
 
 static bool finite_all(const double* p, int n) {
     for (int i = 0; i < n; ++i)
@@ -58,10 +58,12 @@ nd_status validate_problem(const nd_problem* p) {
         return fail(ND_ERR_INVALID_ARG, "unknown precision %d", p->precision);
     if (p->n < 1) return fail(ND_ERR_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)p->n);
     if (p->n > (int64_t(1) << 31) - 1) return fail(ND_ERR_INVALID_ARG, "n must be < 2^31");
-    const int np = p->model == ND_KURAMOTO ? 3 : (p->model == ND_FHN ? 4 : 10);
-    if (p->model < 0 || p->model > 2) return fail(ND_ERR_INVALID_ARG, "unknown model %d", p->model);
+    if (p->model < 0 || p->model > 3) return fail(ND_ERR_INVALID_ARG, "unknown model %d", p->model);
+    const int np = p->model == ND_KURAMOTO ? 3 : (p->model == ND_FHN ? 4 : (p->model == ND_HH ? 10 : 5));
     if (!finite_all(p->params, np)) return fail(ND_ERR_INVALID_ARG, "model parameters must be finite");
     if (p->model == ND_FHN && p->params[0] == 0.0) return fail(ND_ERR_INVALID_ARG, "FHN eps must be non-zero");
+    if (p->model == ND_KURAMOTO_INERTIA && p->params[3] == 0.0)
+        return fail(ND_ERR_INVALID_ARG, "the mass m must be non-zero (m = 0 is ND_KURAMOTO)");
     if (p->model == ND_HH && (p->params[0] == 0.0 || p->params[9] == 0.0))
         return fail(ND_ERR_INVALID_ARG, "HH C and k_s must be non-zero");
     switch (p->topo) {
@@ -74,7 +76,8 @@ nd_status validate_problem(const nd_problem* p) {
                 return fail(ND_ERR_INVALID_ARG, "ring networks hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         case ND_CUBE3D: {
-            if (p->model != ND_KURAMOTO) return fail(ND_ERR_INVALID_ARG, "the cube topology is for Kuramoto");
+            if (p->model != ND_KURAMOTO && p->model != ND_KURAMOTO_INERTIA)
+                return fail(ND_ERR_INVALID_ARG, "the cube topology is for the Kuramoto models");
             const int64_t side = 2 * p->radius + 1;
             if (p->radius < 1 || p->n1 < side || p->n2 < side || p->n3 < side)
                 return fail(ND_ERR_INVALID_ARG, "cube extents must be >= 2h+1");
@@ -218,13 +221,17 @@ Net::~Net() {
 
 static void derive_params(const nd_problem* p, NetDesc& d) {
     std::memset(d.p, 0, sizeof d.p);
-    if (p->model == ND_KURAMOTO) {
+    if (p->model == ND_KURAMOTO || p->model == ND_KURAMOTO_INERTIA) {
         const double L = p->topo == ND_RING ? 2.0 * (double)p->radius
                                             : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
         d.p[0] = p->params[0];
         d.p[1] = p->params[1] / L;
         d.p[2] = std::cos(p->params[2]);
         d.p[3] = std::sin(p->params[2]);
+        if (p->model == ND_KURAMOTO_INERTIA) {
+            d.p[4] = p->params[4];        // eps
+            d.p[5] = 1.0 / p->params[3];  // 1/m
+        }
     } else if (p->model == ND_FHN) {
         d.p[0] = p->params[0];
         d.p[1] = p->params[1];
@@ -479,7 +486,8 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
             return hip_fail(e, "ring epilogue");
     } else if (g.topo == ND_CUBE3D) {
         CubeLaunch L;
-        if (!cube_select(g.prec, g.h, &L)) return fail(ND_ERR_UNSUPPORTED, "no cube kernel for h = %d", g.h);
+        if (!cube_select(g.model, g.prec, g.h, &L))
+            return fail(ND_ERR_UNSUPPORTED, "no cube kernel for model %d, h = %d", g.model, g.h);
         const int block = cube_block(g.h, g.tile, g.tile_y);
         const size_t smem = cube_smem_bytes(g.h, g.tile, g.tile_y);
         for (int j = 0; j < chunk; ++j)
