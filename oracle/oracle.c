@@ -29,6 +29,11 @@
  *     first-order system in (phi, psi = dphi/dt), same neighbourhoods:
  *       dphi_i/dt = psi_i
  *       m dpsi_i/dt = omega - eps psi_i + (mu / L) * sum_j sin(phi_j - phi_i - alpha)
+ *   Both Kuramoto models also run on the periodic lattice with the ball
+ *     neighbourhood of the paper's 3D studies: every lattice point within
+ *     Euclidean distance P, the element itself included (Sec. V counts 33 links
+ *     for P = 2 and 925 for P = 6), L = that count, taken in lexicographic
+ *     (dz, dy, dx) order.
  *   FitzHugh-Nagumo, Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational
  *     coupling matrix B(phi) acting on (u_j - u_i, v_j - v_i), averaged over
  *     the 2P ring neighbours and placed inside the eps-scaled fast equation:
@@ -57,7 +62,7 @@
 #define ORC_ENOMEM -2
 
 enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2, ORC_INERTIA = 3 };
-enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2 };
+enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3 };
 
 typedef struct {
     int model, topo;
@@ -129,6 +134,51 @@ static double kuramoto_cube_coupling(const orc_net* m, const double* z, int64_t 
         s += sin(z[j] - z[i] - alpha);
     }
     return s * (1.0 / (double)links);
+}
+
+/* Ball neighbourhood: lattice offsets with dx^2 + dy^2 + dz^2 <= P^2, the
+ * centre included, lexicographic (dz, dy, dx) (or reversed). */
+static int64_t ball_links(int64_t P) {
+    int64_t c = 0;
+    for (int64_t dz = -P; dz <= P; ++dz)
+        for (int64_t dy = -P; dy <= P; ++dy)
+            for (int64_t dx = -P; dx <= P; ++dx)
+                if (dx * dx + dy * dy + dz * dz <= P * P) ++c;
+    return c;
+}
+
+static double kuramoto_ball_coupling(const orc_net* m, const double* z, int64_t i, double alpha) {
+    const int64_t n1 = m->n1, n2 = m->n2, n3 = m->n3, P = m->radius;
+    const int64_t side = 2 * P + 1, cells = side * side * side;
+    const int64_t x = i % n1, y = (i / n1) % n2, zz = i / (n1 * n2);
+    double s = 0.0;
+    for (int64_t t = 0; t < cells; ++t) {
+        int64_t q = m->reverse ? (cells - 1 - t) : t;
+        int64_t dz = q / (side * side) - P;
+        int64_t dy = (q / side) % side - P;
+        int64_t dx = q % side - P;
+        if (dx * dx + dy * dy + dz * dz > P * P) continue;
+        int64_t j = wrapi(x + dx, n1) + n1 * (wrapi(y + dy, n2) + n2 * wrapi(zz + dz, n3));
+        s += sin(z[j] - z[i] - alpha);
+    }
+    return s * (1.0 / (double)ball_links(P));
+}
+
+static void rhs_kuramoto_ball(const orc_net* m, const double* z, double* f) {
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m->n; ++i) f[i] = omega + mu * kuramoto_ball_coupling(m, z, i, alpha);
+}
+
+static void rhs_inertia_ball(const orc_net* m, const double* z, double* f) {
+    const int64_t n = m->n;
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2], mass = m->prm[3], eps = m->prm[4];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double psi = z[n + i];
+        f[i] = psi;
+        f[n + i] = (omega - eps * psi + mu * kuramoto_ball_coupling(m, z, i, alpha)) / mass;
+    }
 }
 
 static void rhs_inertia_cube(const orc_net* m, const double* z, double* f) {
@@ -239,6 +289,8 @@ static int rhs(const orc_net* m, const double* z, double* f) {
     else if (m->model == ORC_KURAMOTO && m->topo == ORC_CUBE) rhs_kuramoto_cube(m, z, f);
     else if (m->model == ORC_INERTIA && m->topo == ORC_RING) rhs_inertia_ring(m, z, f);
     else if (m->model == ORC_INERTIA && m->topo == ORC_CUBE) rhs_inertia_cube(m, z, f);
+    else if (m->model == ORC_KURAMOTO && m->topo == ORC_BALL) rhs_kuramoto_ball(m, z, f);
+    else if (m->model == ORC_INERTIA && m->topo == ORC_BALL) rhs_inertia_ball(m, z, f);
     else if (m->model == ORC_FHN && m->topo == ORC_RING) rhs_fhn_ring(m, z, f);
     else if (m->model == ORC_HH && m->topo == ORC_CSR) rhs_hh_csr(m, z, f);
     else return ORC_EINVAL;
@@ -249,7 +301,7 @@ static int validate(const orc_net* m) {
     if (m->n <= 0) return ORC_EINVAL;
     if (m->topo == ORC_RING) {
         if (m->radius < 1 || 2 * m->radius + 1 > m->n) return ORC_EINVAL;
-    } else if (m->topo == ORC_CUBE) {
+    } else if (m->topo == ORC_CUBE || m->topo == ORC_BALL) {
         int64_t side = 2 * m->radius + 1;
         if (m->radius < 1 || m->n1 < side || m->n2 < side || m->n3 < side) return ORC_EINVAL;
         if (m->n1 * m->n2 * m->n3 != m->n) return ORC_EINVAL;

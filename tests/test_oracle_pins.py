@@ -640,3 +640,96 @@ def test_inertia_dense_brute_force(topo):
     ref = dense_rk4(inertia_dense(A, *prm), y0, 0.02, 100)
     y, _, _ = O.run(net, y0, 0.02, 100)
     assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+# ------------------------------------------ ball neighbourhood (3D lattice)
+def ball_offsets(P):
+    r = np.arange(-P, P + 1)
+    X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
+    keep = X ** 2 + Y ** 2 + Z ** 2 <= P * P
+    return X[keep], Y[keep], Z[keep]
+
+
+@pytest.mark.parametrize("P", [2, 6])
+def test_ball_link_count_matches_the_paper(golden, P):
+    """Perturb one element inside the ball of element 0 and one outside it; the
+    RHS of element 0 changes by mu/L (sin(d - alpha) + sin alpha) for the inside
+    one and not at all for the outside one, which measures L: the paper's link
+    count (33 for P = 2, 925 for P = 6, centre included)."""
+    count = dict(golden("sphere_link_counts.txt"))[P]
+    n1 = 2 * P + 3
+    omega, mu, alpha, d = 0.2, 1.3, 0.45, 0.9
+    net = O.ball(n1, P, kur(omega, mu, alpha))
+    base = O.rhs(net, np.zeros(n1 ** 3))[0]
+    assert base == pytest.approx(omega - mu * math.sin(alpha), abs=1e-13)
+    inside = np.zeros(n1 ** 3)
+    inside[1 + n1 * 1] = d  # offset (1, 1, 0): |d|^2 = 2 <= P^2
+    L = mu * (math.sin(d - alpha) + math.sin(alpha)) / (O.rhs(net, inside)[0] - base)
+    assert L == pytest.approx(count, rel=1e-9)
+    outside = np.zeros(n1 ** 3)
+    outside[P + n1 * P] = d  # offset (P, P, 0): |d|^2 = 2 P^2 > P^2
+    assert O.rhs(net, outside)[0] == pytest.approx(base, abs=1e-13)
+
+
+@pytest.mark.parametrize("P,q", [(2, (1, 0, 0)), (2, (1, -1, 2)), (3, (0, 2, 1)), (1, (1, 1, 1))])
+def test_ball_plane_wave_rotates_at_closed_form(P, q):
+    """On a plane wave phi = theta . x the ball sum of sin(theta.d - alpha) is
+    -sin(alpha) sum_d cos(theta.d) (the sine part cancels between d and -d), so
+    every element rotates at omega - mu sin(alpha) <cos(theta.d)>_ball."""
+    dims = (9, 10, 11)
+    n1, n2, n3 = dims
+    idx = np.arange(n1 * n2 * n3)
+    x, y, z = idx % n1, (idx // n1) % n2, idx // (n1 * n2)
+    th = [2 * math.pi * q[0] / n1, 2 * math.pi * q[1] / n2, 2 * math.pi * q[2] / n3]
+    phi0 = th[0] * x + th[1] * y + th[2] * z
+    omega, mu, alpha = 0.1, 0.8, 0.45
+    dx, dy, dz = ball_offsets(P)
+    om = omega - mu * math.sin(alpha) * float(np.mean(np.cos(th[0] * dx + th[1] * dy + th[2] * dz)))
+    yt, _, _ = O.run(O.ball(n1, P, kur(omega, mu, alpha), n2=n2, n3=n3), phi0, 0.05, 20)
+    assert np.max(np.abs((yt - phi0) - om * 1.0)) < 1e-12
+
+
+def ball_adjacency(dims, P):
+    n1, n2, n3 = dims
+    n = n1 * n2 * n3
+    idx = np.arange(n)
+    x, y, z = idx % n1, (idx // n1) % n2, idx // (n1 * n2)
+    A = np.zeros((n, n))
+    for ox, oy, oz in zip(*ball_offsets(P)):
+        j = (x + ox) % n1 + n1 * (((y + oy) % n2) + n2 * ((z + oz) % n3))
+        A[idx, j] += 1.0
+    return A
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "inertia"])
+def test_ball_dense_brute_force(model):
+    dims, P = (7, 8, 9), 3
+    n = 7 * 8 * 9
+    A = ball_adjacency(dims, P)
+    assert np.all(A.sum(axis=1) == 123)  # lattice points within distance 3
+    if model == "kuramoto":
+        prm = kur(0.2, 1.1, 0.45)
+        F = kuramoto_dense(A, *prm)
+        y0 = inputs.kuramoto_phases(13, n)
+        net = O.ball(7, P, prm, n2=8, n3=9)
+    else:
+        prm = inert(0.2, 1.1, 0.45, 1.5, 0.2)
+        F = inertia_dense(A, *prm)
+        y0 = np.concatenate([inputs.kuramoto_phases(13, n), inputs.uniform_range(14, inputs.TAG_MISC, n, -1, 1)])
+        net = O.ball(7, P, prm, n2=8, n3=9, model=O.INERTIA)
+    ref = dense_rk4(F, y0, 0.05, 30)
+    y, _, _ = O.run(net, y0, 0.05, 30)
+    assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+def test_ball_axis_permutation_symmetry():
+    """The ball is invariant under permutations of the axes: on a cubic lattice,
+    transposing the initial state transposes the result (up to the changed
+    summation order of the neighbour sum)."""
+    n1, P = 9, 2
+    net = O.ball(n1, P, kur(0.0, 1.0, 0.45))
+    y0 = inputs.kuramoto_phases(15, n1 ** 3)
+    y, _, _ = O.run(net, y0, 0.05, 10)
+    perm = (2, 0, 1)
+    yp, _, _ = O.run(net, np.transpose(y0.reshape(n1, n1, n1), perm).ravel().copy(), 0.05, 10)
+    assert np.max(np.abs(np.transpose(y.reshape(n1, n1, n1), perm).ravel() - yp)) < 1e-13
