@@ -21,6 +21,9 @@ Other workloads (one JSON line each, same fields):
                        m = 1, eps = 0.05, mu = 0.01, alpha = 0.45 (the paper's
                        performance state), cube half-width 2 (124 neighbours),
                        dt = 0.05, 1000 steps (50 time units), psi = 0 initially
+  --workload ball      the same state with the paper's ball neighbourhood of
+                       radius --radius (2: 33 links, the default; 6: 925 links),
+                       centre included
   --workload serve     continuous-batching server fed by seeded Poisson arrivals of
                        Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
                        [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
@@ -61,9 +64,11 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "cube": (1, 2000, 0.05, 200),
     "hh": (1, 5000, 0.01, 1000000),
     "inertia": (1, 1000, 0.05, 100),
+    "ball": (1, 1000, 0.05, 100),
     "serve": (24, 0, 0.01, 0),
 }
-DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3}
+DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3,
+              "ball": 100 ** 3}
 INERTIA_PRM = [0.0, 0.01, 0.45, 1.0, 0.05]  # omega, mu, alpha, m, eps (Sec. V, Fig. 6c)
 
 
@@ -75,6 +80,7 @@ def parse():
     ap.add_argument("--workload", choices=sorted(DEFAULTS), default="fhn")
     ap.add_argument("--batch", type=int, default=0, help="networks per benchmark step (0 = workload default)")
     ap.add_argument("--n", type=int, default=0, help="elements (cube: edge) per network (0 = default)")
+    ap.add_argument("--radius", type=int, default=2, help="ball: neighbourhood radius P")
     ap.add_argument("--horizon", type=int, default=0, help="RK4 steps per benchmark step (0 = workload default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -130,6 +136,17 @@ class Workload:
                          f"{args.horizon} steps, planted coherent ball, psi=0")
             self.kernel = "k_cube_stage<inertia>"
             self.prof = None
+        elif w == "ball":
+            self.n1 = args.n
+            self.n, self.P = args.n ** 3, args.radius
+            r = np.arange(-args.radius, args.radius + 1)
+            X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
+            self.nvars, self.links = 2, int(np.sum(X ** 2 + Y ** 2 + Z ** 2 <= args.radius ** 2))
+            self.name = (f"Kuramoto-Sakaguchi with inertia, 3D lattice {args.n}^3 periodic, ball of radius "
+                         f"{args.radius} ({self.links} links incl. the element), m=1 eps=0.05 mu=0.01 alpha=0.45 "
+                         f"omega=0, RK4 dt=0.05, {args.horizon} steps, planted coherent ball, psi=0")
+            self.kernel = "k_ball_stage<inertia>"
+            self.prof = None
         elif w == "cube":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, 4
@@ -161,6 +178,9 @@ class Workload:
         if w == "inertia":
             return nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_CUBE3D, self.n, INERTIA_PRM, precision=prec, radius=2,
                               dims=(self.n1,) * 3)
+        if w == "ball":
+            return nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, self.n, INERTIA_PRM, precision=prec,
+                              radius=self.P, dims=(self.n1,) * 3)
         rp, col, wt = self.graph
         return nd.problem(nd.ND_HH, nd.ND_CSR, self.n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=wt,
                           per_elem=self.iapp)
@@ -174,7 +194,7 @@ class Workload:
             return inputs.kuramoto_phases(1000 + b, self.n)
         if w == "cube":
             return inputs.cube_phases_with_patch(1000 + b, self.n1)
-        if w == "inertia":
+        if w in ("inertia", "ball"):
             return np.concatenate([inputs.cube_phases_with_patch(1000 + b, self.n1), np.zeros(self.n)])
         return inputs.hh_state(1000 + b, self.n)
 
@@ -256,6 +276,9 @@ def cpu_baseline(wl, args):
     elif w == "inertia":
         net, steps, what = (O.cube(wl.n1, 2, INERTIA_PRM, model=O.INERTIA), 2,
                             f"the {wl.n1}^3 lattice with inertia, h=2")
+    elif w == "ball":
+        net, steps, what = (O.ball(wl.n1, wl.P, INERTIA_PRM, model=O.INERTIA), 1,
+                            f"the {wl.n1}^3 lattice with inertia, ball radius {wl.P}")
     else:
         rp, col, wt = wl.graph
         net, steps, what = O.csr(wl.n, rp, col, wt, HH_PRM, wl.iapp), args.cpu_sample_steps, f"HH N={wl.n} deg 100"

@@ -16,12 +16,12 @@
  *   ND_KURAMOTO  Eq. (3) with m = 0, eps = 1 and a natural frequency:
  *                dphi_i/dt = omega + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
  *                L = number of neighbours (the paper's Alg. 1 divides by the link count).
- *                params = {omega, mu, alpha}.  Topology ND_RING or ND_CUBE3D.
+ *                params = {omega, mu, alpha}.  Topology ND_RING, ND_CUBE3D or ND_BALL3D.
  *   ND_KURAMOTO_INERTIA  Eq. (3) with inertia (m != 0) as a first-order system in
  *                (phi, psi = dphi/dt), plus a natural frequency:
  *                dphi_i/dt = psi_i,
  *                m dpsi_i/dt = omega - eps psi_i + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha).
- *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING or ND_CUBE3D.
+ *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING, ND_CUBE3D or ND_BALL3D.
  *   ND_FHN       Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational coupling
  *                matrix B(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] applied to
  *                (u_j - u_i, v_j - v_i), averaged over the 2P ring neighbours, inside the
@@ -39,6 +39,10 @@
  *   ND_CUBE3D    periodic n1 x n2 x n3 lattice, index x + n1*y + n1*n2*z (the paper's 3D index
  *                map), neighbours = the (2h+1)^3 cube minus the element itself; n1,n2,n3 >= 2h+1,
  *                n < 2^29.
+ *   ND_BALL3D    periodic n1 x n2 x n3 lattice as ND_CUBE3D, neighbours = every lattice point within
+ *                Euclidean distance P = radius, the element itself included (the paper's 3D
+ *                studies: 33 links for P = 2, 925 for P = 6, Sec. V); L = that count; 1 <= P <= 8,
+ *                n1,n2,n3 >= 2P+1, n < 2^29.  Kuramoto models only.
  *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,
  *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
  *
@@ -91,6 +95,7 @@ typedef int32_t nd_status;
 #define ND_RING 0
 #define ND_CUBE3D 1
 #define ND_CSR 2
+#define ND_BALL3D 3
 
 #define ND_FP64 0
 #define ND_FP32_BULK 1
@@ -100,7 +105,7 @@ typedef int32_t nd_status;
 /* A network: model, parameters, topology, precision.  All pointers are host pointers. */
 typedef struct nd_problem {
     int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA */
-    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR */
+    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D */
     int32_t precision;  /* ND_FP64, ND_FP32_BULK */
     int32_t reserved;   /* must be 0 */
     int64_t n;          /* number of elements */

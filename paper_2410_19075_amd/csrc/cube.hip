@@ -279,6 +279,187 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
     }
 }
 
+// ------------------------------------------------------------------ ball
+// Ball neighbourhood of the paper's 3D studies: every lattice point within
+// Euclidean distance P, the element itself included (L = that count).  The
+// ball is the union over (dy, dz) with dy^2 + dz^2 <= P^2 of x-runs of
+// half-width r = floor(sqrt(P^2 - dy^2 - dz^2)), so with per-row prefix sums
+// along x every run is one difference of two prefix values.
+// Each work item owns a cx x cy output tile and a run of cz planes and streams
+// through z.  Per plane, wave w maps halo rows w, w+16, ... (one lane per x of
+// the HX = cx + 2P <= 64 halo columns), scans each row with DPP and stores
+// the row's inclusive prefix in a ring of 2P+2 prefix planes in LDS.  After
+// one LDS-only barrier every output sums its 2 * (#(dy, dz) pairs) prefix
+// differences over the 2P+1 planes of its window, re-maps its own stage
+// value for the RHS and does the RK bookkeeping.  The ring holds one spare
+// plane, so the next plane's rows are written while this plane's sums read.
+constexpr int kBallBlock = 1024, kBallWaves = kBallBlock / kWave, kBallRowsPerWave = 4;
+
+template <int MODEL, class KT, int STAGE, bool MV>
+__global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+                                                    const int* __restrict__ nwork_p, int j) {
+    using M = RingModel<MODEL, KT>;
+    constexpr int V = M::V;
+    constexpr int stage = STAGE;
+    extern __shared__ double2 smem[];
+    __shared__ double lds[2 * 16];
+    __shared__ int rt[kBallMaxP * kBallMaxP + 1];  // floor(sqrt(q)) for q <= P^2
+    const int nwork = *nwork_p;
+    const int nvb = ((nwork + 7) >> 3) << 3;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int w = xcd_work(vb, nwork);
+        if (w < 0) continue;
+        const int2 wk = work[w];
+        const NetDesc& d = D[wk.x];
+        if (j >= d.nsteps) continue;  // uniform over the block
+        const int n1 = d.n1, n2 = d.n2, n3 = d.n3, P = (int)d.P;
+        const int64_t n = d.n;
+        const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
+        const int cx = d.cx, cy = d.cy, cz = d.cz, gx = d.gx, gy = d.gy;
+        const int HX = cx + 2 * P, HY = cy + 2 * P, NS = 2 * P + 2, RW = HX + 1;
+        const int t = wk.y;
+        const int tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
+        const int x0 = tx * cx, y0 = ty * cy, z0 = tz * cz;
+        const int ex = min(cx, n1 - x0), ey = min(cy, n2 - y0);
+        const int nz = min(cz, n3 - z0);
+        const int64_t g = d.g0 + j;
+        const int par = (d.ypar + j) & 1;
+        const ND_GLOBAL double* __restrict__ y = gp(d.y[par]);
+        const ND_GLOBAL KT* __restrict__ kp =
+            stage == 1 ? nullptr : gp((const KT*)d.k[stage > 1 ? stage - 2 : 0]);
+        const ND_GLOBAL double* __restrict__ acc = gp(d.acc);
+        const double dt = d.dt;
+        const double cdt = stage == 4 ? dt : 0.5 * dt;
+
+        if (stage == 2 && t == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
+            double s[2] = {0.0, 0.0};
+            const ND_GLOBAL double* ts = gp(d.tsum[0]);
+            for (int u = tid; u < d.G; u += blockDim.x) {
+                s[0] += ts[2 * u];
+                s[1] += ts[2 * u + 1];
+            }
+            block_sum_rt<2>(s, lds);
+            if (tid == 0) gp(d.R)[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
+        }
+        for (int q = tid; q <= P * P; q += blockDim.x) {
+            int r = 0;
+            while ((r + 1) * (r + 1) <= q) ++r;
+            rt[q] = r;
+        }
+
+        // mapper rows of this wave (lane = halo x); columns beyond the halo or
+        // rows beyond HY load a valid element and contribute nothing
+        const bool lx = lane < HX;
+        const uint32_t xcol = (uint32_t)wrapm(x0 - P + (lx ? lane : 0), n1);
+        uint32_t rowbase[kBallRowsPerWave];
+        bool rv[kBallRowsPerWave];
+#pragma unroll
+        for (int k = 0; k < kBallRowsPerWave; ++k) {
+            const int r = wave + k * kBallWaves;
+            rv[k] = r < HY;
+            rowbase[k] = xcol + (uint32_t)n1 * (uint32_t)wrapm(y0 - P + (rv[k] ? r : 0), n2);
+        }
+        auto zval = [&](uint32_t i) {
+            const double yy = ld32(y, i);
+            return stage == 1 ? yy : fma(cdt, (double)ld32(kp, i), yy);
+        };
+        // map plane q (relative: absolute z = z0 - P + q) into ring slot q % NS
+        double qz[kBallRowsPerWave];
+        auto load_plane = [&](int q) {
+            const uint32_t zb = plane * (uint32_t)wrapm(z0 - P + min(q, nz + 2 * P - 1), n3);
+#pragma unroll
+            for (int k = 0; k < kBallRowsPerWave; ++k)
+                if (rv[k]) qz[k] = zval(rowbase[k] + zb);
+        };
+        auto store_plane = [&](int q) {
+            double2* pre = smem + (size_t)(q % NS) * HY * RW;
+#pragma unroll
+            for (int k = 0; k < kBallRowsPerWave; ++k) {
+                if (!rv[k]) continue;  // uniform over the wave
+                double z[1] = {qz[k]};
+                double2 m = M::map(z);
+                if (!lx) m = make_double2(0.0, 0.0);
+                const double px = wave_incl_scan(m.x), py = wave_incl_scan(m.y);
+                double2* row = pre + (size_t)(wave + k * kBallWaves) * RW;
+                if (lx) row[lane + 1] = make_double2(px, py);
+                if (lane == 0) row[0] = make_double2(0.0, 0.0);
+            }
+        };
+        for (int q = 0; q < 2 * P; ++q) {
+            load_plane(q);
+            store_plane(q);
+        }
+        load_plane(2 * P);
+
+        // output thread
+        const bool outv = tid < cx * cy && (tid % cx) < ex && (tid / cx) < ey;
+        const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
+        const uint32_t obase = (uint32_t)(x0 + ox) + (uint32_t)n1 * (uint32_t)(y0 + oy);
+        double part[2] = {0.0, 0.0};
+        for (int i = 0; i < nz; ++i) {
+            const int zo = z0 + i;
+            const uint32_t q = obase + plane * (uint32_t)zo;
+            // own operands of this plane (issued before the mapping work)
+            double yv[V], kv[V], av[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                yv[v] = kv[v] = av[v] = 0.0;
+                if (outv) {
+                    yv[v] = ld32(y + (int64_t)v * n, q);
+                    kv[v] = stage != 1 ? (double)ld32(kp + (int64_t)v * n, q) : 0.0;
+                    av[v] = stage == 4 ? ld32(acc + (int64_t)v * n, q) : 0.0;
+                }
+            }
+            store_plane(i + 2 * P);   // the plane entering the window of output plane zo
+            load_plane(i + 2 * P + 1);
+            lds_barrier();
+            if (outv) {
+                double2 W = make_double2(0.0, 0.0);
+                for (int dz = -P; dz <= P; ++dz) {
+                    const double2* pre = smem + (size_t)((i + P + dz) % NS) * HY * RW;
+                    const int rho2 = P * P - dz * dz, rho = rt[rho2];
+                    for (int dy = -rho; dy <= rho; ++dy) {
+                        const int r = rt[rho2 - dy * dy];
+                        const double2* row = pre + (size_t)(oy + P + dy) * RW + ox + P;
+                        const double2 hi = row[r + 1], lo = row[-r];
+                        W.x += hi.x - lo.x;
+                        W.y += hi.y - lo.y;
+                    }
+                }
+                double zz[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) zz[v] = stage == 1 ? yv[v] : fma(cdt, kv[v], yv[v]);
+                const double2 xo = M::map(zz);
+                double k[V];
+                M::rhs(d, zz, xo, W, k);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const double kk = kq<KT>(k[v]);
+                    if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + (int64_t)v * n, q, (KT)kk);
+                    if (stage == 2) st32(gp(d.acc) + (int64_t)v * n, q, fma(d.dt3, kk, fma(d.dt6, kv[v], yv[v])));
+                    if (stage == 4)
+                        st32(gp(d.y[par ^ 1]) + (int64_t)v * n, q, fma(d.dt6, kk, fma(d.dt3, kv[v], av[v])));
+                }
+                if (stage == 1) {
+                    part[0] += xo.x;
+                    part[1] += xo.y;
+                    if (MV && (d.obs & OBS_MV) && g == d.mv_start) st32(gp(d.mv), q, yv[0]);
+                }
+            }
+        }
+        if (stage == 1) {
+            block_sum_rt<2>(part, lds);
+            if (tid == 0) {
+                gp(d.tsum[0])[2 * t] = part[0];
+                gp(d.tsum[0])[2 * t + 1] = part[1];
+            }
+        } else {
+            __syncthreads();  // LDS reuse by the next work item
+        }
+    }
+}
+
 // After the last step of a run: partial sums of map(y) over flat element ranges
 // (one per work item) and the mean phase velocity.
 template <class KT>
@@ -365,6 +546,37 @@ static bool cube_pick(int prec, int h, CubeLaunch* out) {
         }
     }
     return true;
+}
+
+template <int MODEL, class KT>
+static void ball_entry(CubeLaunch* r) {
+    r->stage[0] = k_ball_stage<MODEL, KT, 1, false>;
+    r->stage[1] = k_ball_stage<MODEL, KT, 2, false>;
+    r->stage[2] = k_ball_stage<MODEL, KT, 3, false>;
+    r->stage[3] = k_ball_stage<MODEL, KT, 4, false>;
+    r->stage_mv[0] = k_ball_stage<MODEL, KT, 1, true>;
+    r->stage_mv[1] = k_ball_stage<MODEL, KT, 2, true>;
+    r->stage_mv[2] = k_ball_stage<MODEL, KT, 3, true>;
+    r->stage_mv[3] = k_ball_stage<MODEL, KT, 4, true>;
+    r->final_partials = k_cube_final_partials<KT>;
+    r->final_R = k_cube_final_R;
+}
+
+bool ball_select(int model, int prec, CubeLaunch* out) {
+    if (model == ND_KURAMOTO) {
+        if (prec == ND_FP64) ball_entry<ND_KURAMOTO, double>(out); else ball_entry<ND_KURAMOTO, float>(out);
+        return true;
+    }
+    if (model == ND_KURAMOTO_INERTIA) {
+        if (prec == ND_FP64) ball_entry<ND_KURAMOTO_INERTIA, double>(out);
+        else ball_entry<ND_KURAMOTO_INERTIA, float>(out);
+        return true;
+    }
+    return false;
+}
+
+size_t ball_smem_bytes(int P, int cx, int cy) {
+    return (size_t)(2 * P + 2) * (cy + 2 * P) * (cx + 2 * P + 1) * sizeof(double2);
 }
 
 bool cube_select(int model, int prec, int h, CubeLaunch* out) {

@@ -102,6 +102,13 @@ struct CubeLaunch {
     void (*final_R)(const NetDesc*, const int2*, const int*, int);
 };
 bool cube_select(int model, int prec, int h, CubeLaunch* out);
+// Ball neighbourhood (3D lattice, radius P <= kBallMaxP): same launch shape as
+// the cube stage, 1024 threads; LDS = ball_smem_bytes.
+constexpr int kBallMaxP = 8;
+bool ball_select(int model, int prec, CubeLaunch* out);
+size_t ball_smem_bytes(int P, int cx, int cy);
+constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB per CU, minus statics)
+int64_t ball_points(int64_t P);
 size_t cube_smem_bytes(int h, int cx, int cy);
 int cube_block(int h, int cx, int cy);
 hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,

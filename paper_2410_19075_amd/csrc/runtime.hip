@@ -86,6 +86,19 @@ nd_status validate_problem(const nd_problem* p) {
                 return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         }
+        case ND_BALL3D: {
+            if (p->model != ND_KURAMOTO && p->model != ND_KURAMOTO_INERTIA)
+                return fail(ND_ERR_INVALID_ARG, "the ball topology is for the Kuramoto models");
+            const int64_t side = 2 * p->radius + 1;
+            if (p->radius < 1 || p->radius > kBallMaxP)
+                return fail(ND_ERR_INVALID_ARG, "ball radius must be in [1, %d]", kBallMaxP);
+            if (p->n1 < side || p->n2 < side || p->n3 < side)
+                return fail(ND_ERR_INVALID_ARG, "lattice extents must be >= 2P+1");
+            if (p->n1 * p->n2 * p->n3 != p->n) return fail(ND_ERR_INVALID_ARG, "n must equal n1*n2*n3");
+            if (p->n >= (int64_t(1) << 29))
+                return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
+            break;
+        }
         case ND_CSR: {
             if (p->model != ND_HH) return fail(ND_ERR_INVALID_ARG, "the CSR topology is for HH");
             if (!p->row_ptr || (p->nnz > 0 && (!p->col || !p->weight)) || !p->per_elem)
@@ -105,6 +118,43 @@ nd_status validate_problem(const nd_problem* p) {
             return fail(ND_ERR_INVALID_ARG, "unknown topology %d", p->topo);
     }
     return ND_OK;
+}
+
+// Lattice points within distance P of the origin, the origin included.
+int64_t ball_points(int64_t P) {
+    int64_t c = 0;
+    for (int64_t dz = -P; dz <= P; ++dz)
+        for (int64_t dy = -P; dy <= P; ++dy)
+            for (int64_t dx = -P; dx <= P; ++dx) c += dx * dx + dy * dy + dz * dz <= P * P;
+    return c;
+}
+
+// Ball tiling: halo rows of HX = cx + 2P <= 64 lanes, at most 1024 outputs and
+// 64 halo rows, and the prefix ring within the LDS budget; then z runs so that
+// the work items fill the CUs in as few rounds as possible.
+static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_) {
+    const int P = (int)p->radius;
+    const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
+    double best = 1e300;
+    *cx_ = 1, *cy_ = 1, *cz_ = n3;
+    for (int cx = 1; cx <= std::min(n1, 64 - 2 * P); ++cx) {
+        for (int cy = 1; cy <= std::min(n2, 64 - 2 * P); ++cy) {
+            if (cx * cy > 1024 || ball_smem_bytes(P, cx, cy) > kBallSmemMax) break;
+            const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
+            const int64_t rows = cy + 2 * P;  // mapped halo rows per plane (one wave row each)
+            for (int zt = 1; zt <= std::min(n3, 256); ++zt) {
+                const int cz = (n3 + zt - 1) / zt;
+                if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;
+                const int64_t rounds = (tiles * zt + cus - 1) / cus;
+                // per plane: the mapped rows plus the outputs' prefix reads
+                const double cost = (double)rounds * ((cz + 2 * P) * rows * 64.0 + cz * (double)cx * cy * 2.0 * P * P);
+                if (cost < best) {
+                    best = cost;
+                    *cx_ = cx, *cy_ = cy, *cz_ = cz;
+                }
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------ configuration
@@ -175,6 +225,13 @@ nd_kernel_config default_config(const nd_problem* p) {
         c.tile_y = cy;
         c.tile_z = cz;
         c.block = cube_block(h, cx, cy);
+    } else if (p->topo == ND_BALL3D) {
+        int cx, cy, cz;
+        ball_tiles(p, device_cu_count(), &cx, &cy, &cz);
+        c.tile = cx;
+        c.tile_y = cy;
+        c.tile_z = cz;
+        c.block = 1024;
     } else {
         c.tile = 256;    // target rows per work item
         c.tile_y = 8;    // edges per thread per chunk
@@ -196,7 +253,7 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
     const int64_t V = nvars_of(p->model), n = p->n, kb = bulk_bytes(p->precision);
     int64_t b = 3 * V * n * 8 + 3 * V * n * kb;  // y[2], acc, k[3]
     if (p->topo == ND_RING) b += 3 * 2 * ring_tiles(n, c.tile) * 8;
-    if (p->topo == ND_CUBE3D)
+    if (p->topo == ND_CUBE3D || p->topo == ND_BALL3D)
         b += 3 * 2 * 8 * ((p->n1 + c.tile - 1) / c.tile) * ((p->n2 + c.tile_y - 1) / c.tile_y) *
              ((p->n3 + c.tile_z - 1) / c.tile_z);
     if (p->topo == ND_CSR)
@@ -222,8 +279,9 @@ Net::~Net() {
 static void derive_params(const nd_problem* p, NetDesc& d) {
     std::memset(d.p, 0, sizeof d.p);
     if (p->model == ND_KURAMOTO || p->model == ND_KURAMOTO_INERTIA) {
-        const double L = p->topo == ND_RING ? 2.0 * (double)p->radius
-                                            : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
+        const double L = p->topo == ND_RING     ? 2.0 * (double)p->radius
+                         : p->topo == ND_BALL3D ? (double)ball_points(p->radius)
+                                                : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
         d.p[0] = p->params[0];
         d.p[1] = p->params[1] / L;
         d.p[2] = std::cos(p->params[2]);
@@ -342,9 +400,9 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         cfg.block = ring_block(cfg.tile);
         tmpl.tile = cfg.tile;
         tmpl.G = (int32_t)ring_tiles(n, cfg.tile);
-    } else if (prob.topo == ND_CUBE3D) {
+    } else if (prob.topo == ND_CUBE3D || prob.topo == ND_BALL3D) {
         const int h = (int)prob.radius;
-        cfg.block = cube_block(h, cfg.tile, cfg.tile_y);
+        cfg.block = prob.topo == ND_BALL3D ? 1024 : cube_block(h, cfg.tile, cfg.tile_y);
         tmpl.cx = cfg.tile;
         tmpl.cy = cfg.tile_y;
         tmpl.cz = cfg.tile_z;
@@ -496,6 +554,16 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
                     return hip_fail(e, "cube stage");
         if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "cube final");
+    } else if (g.topo == ND_BALL3D) {
+        CubeLaunch L;
+        if (!ball_select(g.model, g.prec, &L)) return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d", g.model);
+        const size_t smem = ball_smem_bytes(g.h, g.tile, g.tile_y);
+        for (int j = 0; j < chunk; ++j)
+            for (int s = 1; s <= 4; ++s)
+                if ((e = cube_launch_stage(L, grid, 1024, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
+                    return hip_fail(e, "ball stage");
+        if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
+            return hip_fail(e, "ball final");
     } else {
         CsrLaunch L;
         if (!csr_select(g.prec, g.tile_y, &L)) return fail(ND_ERR_UNSUPPORTED, "no CSR kernel for %d edges per thread", g.tile_y);
@@ -561,7 +629,7 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const Net* n = nets[i];
-        const int h = n->prob.topo == ND_CUBE3D ? (int)n->prob.radius : 0;
+        const int h = (n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D) ? (int)n->prob.radius : 0;
         groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h)]
             .push_back(i);
     }
@@ -757,6 +825,17 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
         if ((c.tile + 2 * h) * (c.tile_y + 2 * h) > 1024)
             return fail(ND_ERR_INVALID_ARG, "cube tile: (tile+2h)*(tile_y+2h) must be <= 1024");
+    } else if (p.topo == ND_BALL3D) {
+        const int P = (int)p.radius;
+        if (c.tile < 1 || c.tile_y < 1 || c.tile_z < 1)
+            return fail(ND_ERR_INVALID_ARG, "ball tile extents must be >= 1");
+        c.tile = (int32_t)std::min<int64_t>(c.tile, p.n1);
+        c.tile_y = (int32_t)std::min<int64_t>(c.tile_y, p.n2);
+        c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
+        if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > 64 || c.tile * c.tile_y > 1024 ||
+            ball_smem_bytes(P, c.tile, c.tile_y) > kBallSmemMax)
+            return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 64, tile*tile_y <= 1024 "
+                                            "and the prefix ring within LDS");
     } else {
         if (c.tile != 256) return fail(ND_ERR_INVALID_ARG, "CSR work items hold 256 rows (tile must be 256)");
         if (c.tile_y < 2 || c.tile_y > 16 || (c.tile_y & (c.tile_y - 1)))

@@ -49,7 +49,7 @@ static int log2_bucket(int64_t v) {
 static TuneKey tune_key(const nd_problem* p, const std::string& arch) {
     // ring: width bucket = floor(8 P / n) (P/n in eighths); cube: half-width h
     const int wb = p->topo == ND_RING ? (int)(8 * p->radius / p->n) : 0;
-    const int h = p->topo == ND_CUBE3D ? (int)p->radius : 0;
+    const int h = (p->topo == ND_CUBE3D || p->topo == ND_BALL3D) ? (int)p->radius : 0;
     return TuneKey(arch, p->model, p->topo, p->precision, log2_bucket(p->n), wb, h);
 }
 
@@ -84,6 +84,13 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
                 c.tile_z = (int)std::min<int64_t>(cz, p->n3);
                 v.push_back(c);
             }
+        }
+    } else if (p->topo == ND_BALL3D) {
+        v.push_back(base);  // the cost-model tiling
+        for (int cz : {base.tile_z * 2, (base.tile_z + 1) / 2}) {
+            nd_kernel_config c = base;
+            c.tile_z = (int)std::max<int64_t>(1, std::min<int64_t>(cz, p->n3));
+            v.push_back(c);
         }
     } else {
         for (int l : {4, 8, 16}) {

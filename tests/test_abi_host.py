@@ -45,11 +45,15 @@ def test_status_strings():
     (dict(model=0, topo=1, n=999, radius=4, dims=(10, 10, 10)), "n1*n2*n3"),
     (dict(model=1, topo=1, n=1000, radius=1, dims=(10, 10, 10)), "Kuramoto"),
     (dict(model=7, topo=0, n=10, radius=1), "model"),
+    (dict(model=1, topo=3, n=1000, radius=1, dims=(10, 10, 10)), "Kuramoto"),
+    (dict(model=0, topo=3, n=20 ** 3, radius=9, dims=(20, 20, 20)), "ball radius"),
+    (dict(model=0, topo=3, n=8 ** 3, radius=4, dims=(8, 8, 8)), "2P+1"),
+    (dict(model=3, topo=0, n=100, radius=3, zero_mass=True), "mass"),
 ])
 def test_invalid_problems_are_rejected_on_the_host(kw, needle):
     from paper_2410_19075_amd import nd
-    p = nd.problem(kw["model"], kw["topo"], kw["n"], [1.0, 1.0, 1.0, 0.5, 0, 0, 0, 0, 0, 1.0],
-                   radius=kw["radius"], dims=kw.get("dims", (0, 0, 0)))
+    prm = [1.0, 1.0, 1.0, 0.0 if kw.get("zero_mass") else 0.5, 0, 0, 0, 0, 0, 1.0]
+    p = nd.problem(kw["model"], kw["topo"], kw["n"], prm, radius=kw["radius"], dims=kw.get("dims", (0, 0, 0)))
     with pytest.raises(nd.NDError) as ei:
         nd.nd_footprint(p)
     assert ei.value.status == nd.ND_ERR_INVALID_ARG
@@ -135,3 +139,19 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_ball_link_counts_and_footprint():
+    """Ball problems are accepted up to P = 8 and cost the same state memory as
+    cube problems of the lattice size (up to the per-work-item sums).  The
+    normalisation by the closed-ball count (925 at P = 6) is checked on the GPU
+    against the oracle, whose count is pinned to the paper's."""
+    from paper_2410_19075_amd import nd
+    for P, count in ((2, 33), (6, 925)):
+        pb = nd.problem(nd.ND_KURAMOTO, nd.ND_BALL3D, 40 ** 3, [0.0, 1.0, 0.4], radius=P, dims=(40, 40, 40))
+        pc = nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, 40 ** 3, [0.0, 1.0, 0.4], radius=min(P, 4), dims=(40, 40, 40))
+        fb, fc = nd.nd_footprint(pb), nd.nd_footprint(pc)
+        assert abs(fb - fc) < 2e5
+    r = np.arange(-6, 7)
+    X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
+    assert int(np.sum(X ** 2 + Y ** 2 + Z ** 2 <= 36)) == 925

@@ -1,0 +1,114 @@
+"""GPU parity of the ball neighbourhood (lattice points within distance P,
+centre included: the paper's 3D topology) for both Kuramoto models against the
+FP64 CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2410_19075_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KUR = [0.1, 1.0, 0.45]
+INERT = [0.1, 1.0, 0.45, 1.0, 0.05]
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_19075_amd import nd as _nd
+    return _nd
+
+
+def normwise(a, ref, nvars):
+    a, ref = a.reshape(nvars, -1), ref.reshape(nvars, -1)
+    return max(np.max(np.abs(a[v] - ref[v])) / np.max(np.abs(ref[v])) for v in range(nvars))
+
+
+def case(nd, model, dims, P, seed, steps, prec=0, cfg=None, record_every=0, mv=-1, dt=0.05):
+    n1, n2, n3 = dims
+    n = n1 * n2 * n3
+    phases = inputs.kuramoto_phases(seed, n)
+    if model == "inertia":
+        y0 = np.concatenate([phases, inputs.uniform_range(seed, inputs.TAG_MISC, n, -0.5, 0.5)])
+        code, ocode, prm, nv = nd.ND_KURAMOTO_INERTIA, O.INERTIA, INERT, 2
+    else:
+        y0, code, ocode, prm, nv = phases, nd.ND_KURAMOTO, O.KURAMOTO, KUR, 1
+    p = nd.problem(code, nd.ND_BALL3D, n, prm, precision=prec, radius=P, dims=dims)
+    h = nd.nd_create(p)
+    try:
+        if cfg:
+            c = nd.nd_get_config(h)
+            for k, v in cfg.items():
+                setattr(c, k, v)
+            nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, dt, steps, nd.observe(record_every, mv))
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+        R = mvel = None
+        if record_every or mv >= 0:
+            R = np.empty(steps // record_every + 1) if record_every else None
+            mvel = np.empty(n) if mv >= 0 else None
+            nd.nd_get_observables(h, R=R, mean_vel=mvel, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    ref, Rref, mvref = O.run(O.ball(n1, P, prm, n2=n2, n3=n3, model=ocode), y0, dt, steps,
+                             record_every=record_every, mv_start=mv if mv >= 0 else None)
+    return y, ref, R, Rref, mvel, mvref, nv
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "inertia"])
+@pytest.mark.parametrize("dims,P", [((12, 12, 12), 1), ((20, 18, 16), 2), ((13, 14, 15), 3), ((13, 13, 13), 6),
+                                    ((11, 30, 9), 4)])
+def test_ball_fp64_parity(nd, model, dims, P):
+    print(f"case ball {model} dims={dims} P={P}", flush=True)
+    y, ref, R, Rref, mv, mvref, nv = case(nd, model, dims, P, sum(dims) + P, 25, record_every=5, mv=10)
+    assert normwise(y, ref, nv) < 1e-12
+    assert np.max(np.abs(R - Rref)) < 1e-12
+    assert np.max(np.abs(mv - mvref)) < 1e-10
+
+
+@pytest.mark.parametrize("cfg", [dict(tile=7, tile_y=5, tile_z=3), dict(tile=24, tile_y=9, tile_z=17),
+                                 dict(tile=1, tile_y=1, tile_z=1), dict(tile=16, tile_y=16, tile_z=4, grid=8, chunk=3)])
+def test_ball_tilings(nd, cfg):
+    """Ragged tiles in every direction, single-element tiles, a persistent grid
+    smaller than the work and graph chunks that do not divide the steps."""
+    print(f"case ball cfg={cfg}", flush=True)
+    y, ref, _, _, _, _, nv = case(nd, "inertia", (24, 22, 20), 2, 3, 11, cfg=cfg)
+    assert normwise(y, ref, nv) < 1e-12
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "inertia"])
+def test_ball_fp32_bulk(nd, model):
+    y, ref, _, _, _, _, nv = case(nd, model, (16, 16, 16), 3, 4, 200, prec=1)
+    e = normwise(y, ref, nv)
+    print(f"ball {model} fp32-bulk error {e:.3e}")
+    assert e < 1e-4
+
+
+def test_ball_restart_is_bitwise(nd):
+    n1, P = 18, 2
+    n = n1 ** 3
+    y0 = np.concatenate([inputs.cube_phases_with_patch(5, n1), np.zeros(n)])
+    p = nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, INERT, radius=P, dims=(n1,) * 3)
+    a, _, _ = nd.simulate(p, y0, 0.05, 30)
+    b, _, _ = nd.simulate(p, y0, 0.05, 12)
+    c, _, _ = nd.simulate(p, b, 0.05, 18)
+    assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("n1,P,steps", [(100, 2, 2), (60, 6, 1)])
+def test_ball_paper_performance_shapes(nd, n1, P, steps):
+    """The paper's performance state (Sec. V, Fig. 6c): Kuramoto with inertia,
+    m = 1, eps = 0.05, mu = 0.01, alpha = 0.45, ball radius 2 (33 links) on
+    100^3, and radius 6 (925 links) on 60^3; psi = 0 initially."""
+    n = n1 ** 3
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(6, n1), np.zeros(n)])
+    p = nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, radius=P, dims=(n1,) * 3)
+    y, _, _ = nd.simulate(p, y0, 0.05, steps)
+    ref, _, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, steps)
+    assert normwise(y, ref, 2) < 1e-12
