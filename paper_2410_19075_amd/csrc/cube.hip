@@ -294,6 +294,8 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
 // value for the RHS and does the RK bookkeeping.  The ring holds one spare
 // plane, so the next plane's rows are written while this plane's sums read.
 constexpr int kBallBlock = 1024, kBallWaves = kBallBlock / kWave, kBallRowsPerWave = 4;
+constexpr int kBallUnroll = 8;
+constexpr int kBallMaxRuns = 224;  // (dy, dz) runs of the largest ball (P = 8: 197), padded to kBallUnroll
 
 template <int MODEL, class KT, int STAGE, bool MV>
 __global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
@@ -303,7 +305,10 @@ __global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__
     constexpr int stage = STAGE;
     extern __shared__ double2 smem[];
     __shared__ double lds[2 * 16];
-    __shared__ int rt[kBallMaxP * kBallMaxP + 1];  // floor(sqrt(q)) for q <= P^2
+    // the (dy, dz) runs of the ball: {dz, dy, r + 1, -r}, padded with empty runs
+    // ({0, 0, 0, 0}: hi - lo = 0 exactly) to a multiple of kBallUnroll
+    __shared__ int4 runs[kBallMaxRuns];
+    __shared__ int nruns;
     const int nwork = *nwork_p;
     const int nvb = ((nwork + 7) >> 3) << 3;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -342,10 +347,18 @@ __global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__
             block_sum_rt<2>(s, lds);
             if (tid == 0) gp(d.R)[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
         }
-        for (int q = tid; q <= P * P; q += blockDim.x) {
-            int r = 0;
-            while ((r + 1) * (r + 1) <= q) ++r;
-            rt[q] = r;
+        if (tid == 0) {
+            int c = 0;
+            for (int dz = -P; dz <= P; ++dz)
+                for (int dy = -P; dy <= P; ++dy) {
+                    const int q = P * P - dz * dz - dy * dy;
+                    if (q < 0) continue;
+                    int r = 0;
+                    while ((r + 1) * (r + 1) <= q) ++r;
+                    runs[c++] = make_int4(dz, dy, r + 1, -r);
+                }
+            while (c % kBallUnroll) runs[c++] = make_int4(0, 0, 0, 0);
+            nruns = c;
         }
 
         // mapper rows of this wave (lane = halo x); columns beyond the halo or
@@ -415,16 +428,28 @@ __global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__
             load_plane(i + 2 * P + 1);
             lds_barrier();
             if (outv) {
+                // runs in (dz, dy) order, kBallUnroll at a time so their LDS
+                // reads are in flight together; the sum order is fixed
                 double2 W = make_double2(0.0, 0.0);
-                for (int dz = -P; dz <= P; ++dz) {
-                    const double2* pre = smem + (size_t)((i + P + dz) % NS) * HY * RW;
-                    const int rho2 = P * P - dz * dz, rho = rt[rho2];
-                    for (int dy = -rho; dy <= rho; ++dy) {
-                        const int r = rt[rho2 - dy * dy];
-                        const double2* row = pre + (size_t)(oy + P + dy) * RW + ox + P;
-                        const double2 hi = row[r + 1], lo = row[-r];
-                        W.x += hi.x - lo.x;
-                        W.y += hi.y - lo.y;
+                const int s0 = (i + P) % NS;  // slot of the centre plane
+                const double2* centre = smem + (size_t)(oy + P) * RW + ox + P;
+                const int nr = nruns;
+                for (int k0 = 0; k0 < nr; k0 += kBallUnroll) {
+                    double2 hi[kBallUnroll], lo[kBallUnroll];
+#pragma unroll
+                    for (int u = 0; u < kBallUnroll; ++u) {
+                        const int4 e = runs[k0 + u];
+                        int sl = s0 + e.x;
+                        sl += sl < 0 ? NS : 0;
+                        sl -= sl >= NS ? NS : 0;
+                        const double2* row = centre + (size_t)sl * HY * RW + e.y * RW;
+                        hi[u] = row[e.z];
+                        lo[u] = row[e.w];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kBallUnroll; ++u) {
+                        W.x += hi[u].x - lo[u].x;
+                        W.y += hi[u].y - lo[u].y;
                     }
                 }
                 double zz[V];
