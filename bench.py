@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="persistent grid override (0 = one block per work item)")
+    ap.add_argument("--block", type=int, default=0, help="ball: workgroup size override (256 or 1024)")
     ap.add_argument("--chunk", type=int, default=0, help="steps per captured graph chunk (0 = default)")
     ap.add_argument("--hmin", type=float, default=1e3, help="serve: shortest horizon (RK4 steps)")
     ap.add_argument("--hmax", type=float, default=1e4, help="serve: longest horizon (RK4 steps)")
@@ -214,13 +215,14 @@ def run(nd, torch, wl, args, prec, stream):
     hs = []
     for b in range(args.batch):
         h = nd.nd_create(wl.problem(prec))
-        if args.tile or args.grid or args.chunk or args.tile_y or args.tile_z:
+        if args.tile or args.grid or args.chunk or args.tile_y or args.tile_z or args.block:
             c = nd.nd_get_config(h)
             c.tile = args.tile or c.tile
             c.tile_y = args.tile_y or c.tile_y
             c.tile_z = args.tile_z or c.tile_z
             c.grid = args.grid or c.grid
             c.chunk = args.chunk or c.chunk
+            c.block = args.block or c.block
             nd.nd_set_config(h, c)
         y0 = torch.from_numpy(wl.state(b)).cuda()
         nd.nd_set_state(h, y0, stream=stream)
@@ -316,7 +318,7 @@ def roofline(wl, args, prec, ev_total, cfg):
         t = profsum.read_traffic(os.path.join(PROFILES, md), kf, "f64" if prec == 0 else "f32", files)
         # the summary's workload is the default one; other sizes scale with the elements
         default_shape = (args.batch == DEFAULTS[args.workload][0] and wl.n == DEFAULTS_N[args.workload]
-                         and not (args.tile or args.tile_y or args.tile_z or args.grid or args.chunk))
+                         and not (args.tile or args.tile_y or args.tile_z or args.grid or args.chunk or args.block))
         if t is not None and default_shape:
             traffic = t
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -172,7 +172,8 @@ typedef struct nd_kernel_config {
     int32_t tile;   /* ring: elements per tile (128, 256, 512, 1024 or 2048), or -1024 / -2048 / -4096:
                        the whole ring (n <= that capacity) resident in one workgroup;
                        cube: output tile extent along x; CSR: rows per workgroup */
-    int32_t block;  /* threads per workgroup (derived; ignored by nd_set_config) */
+    int32_t block;  /* threads per workgroup: derived (ignored by nd_set_config), except for
+                       ND_BALL3D, where it selects 256 or 1024 */
     int32_t grid;   /* persistent grid size in workgroups; 0 = one workgroup per work item */
     int32_t chunk;  /* steps per captured graph chunk */
     int32_t tile_y; /* cube: output tile extent along y ((tile+2h)*(tile_y+2h) <= 1024);

@@ -286,23 +286,24 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
 // half-width r = floor(sqrt(P^2 - dy^2 - dz^2)), so with per-row prefix sums
 // along x every run is one difference of two prefix values.
 // Each work item owns a cx x cy output tile and a run of cz planes and streams
-// through z.  Per plane, wave w maps halo rows w, w+16, ... (one lane per x of
+// through z.  Per plane, wave w of W maps halo rows w, w+W, ... (one lane per x of
 // the HX = cx + 2P <= 64 halo columns), scans each row with DPP and stores
 // the row's inclusive prefix in a ring of 2P+2 prefix planes in LDS.  After
 // one LDS-only barrier every output sums its 2 * (#(dy, dz) pairs) prefix
 // differences over the 2P+1 planes of its window, re-maps its own stage
 // value for the RHS and does the RK bookkeeping.  The ring holds one spare
 // plane, so the next plane's rows are written while this plane's sums read.
-constexpr int kBallBlock = 1024, kBallWaves = kBallBlock / kWave, kBallRowsPerWave = 4;
+constexpr int kBallRowsPerWave = 4;
 constexpr int kBallUnroll = 8;
 constexpr int kBallMaxRuns = 224;  // (dy, dz) runs of the largest ball (P = 8: 197), padded to kBallUnroll
 
-template <int MODEL, class KT, int STAGE, bool MV>
-__global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
+template <int MODEL, class KT, int BS, int STAGE, bool MV>
+__global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D, const int2* __restrict__ work,
                                                     const int* __restrict__ nwork_p, int j) {
     using M = RingModel<MODEL, KT>;
     constexpr int V = M::V;
     constexpr int stage = STAGE;
+    constexpr int kBallWaves = BS / kWave;
     extern __shared__ double2 smem[];
     __shared__ double lds[2 * 16];
     // the (dy, dz) runs of the ball: {dz, dy, r + 1, -r}, padded with empty runs
@@ -410,20 +411,32 @@ __global__ __launch_bounds__(1024) void k_ball_stage(const NetDesc* __restrict__
         const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
         const uint32_t obase = (uint32_t)(x0 + ox) + (uint32_t)n1 * (uint32_t)(y0 + oy);
         double part[2] = {0.0, 0.0};
+        // own RK operands, one plane ahead
+        double ny[V], nk[V], na[V];
+        auto own = [&](int i) {
+            const uint32_t q = obase + plane * (uint32_t)(z0 + min(i, nz - 1));
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                ny[v] = nk[v] = na[v] = 0.0;
+                if (outv) {
+                    ny[v] = ld32(y + (int64_t)v * n, q);
+                    nk[v] = stage != 1 ? (double)ld32(kp + (int64_t)v * n, q) : 0.0;
+                    na[v] = stage == 4 ? ld32(acc + (int64_t)v * n, q) : 0.0;
+                }
+            }
+        };
+        own(0);
         for (int i = 0; i < nz; ++i) {
             const int zo = z0 + i;
             const uint32_t q = obase + plane * (uint32_t)zo;
-            // own operands of this plane (issued before the mapping work)
             double yv[V], kv[V], av[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                yv[v] = kv[v] = av[v] = 0.0;
-                if (outv) {
-                    yv[v] = ld32(y + (int64_t)v * n, q);
-                    kv[v] = stage != 1 ? (double)ld32(kp + (int64_t)v * n, q) : 0.0;
-                    av[v] = stage == 4 ? ld32(acc + (int64_t)v * n, q) : 0.0;
-                }
+                yv[v] = ny[v];
+                kv[v] = nk[v];
+                av[v] = na[v];
             }
+            own(i + 1);
             store_plane(i + 2 * P);   // the plane entering the window of output plane zo
             load_plane(i + 2 * P + 1);
             lds_barrier();
@@ -573,30 +586,34 @@ static bool cube_pick(int prec, int h, CubeLaunch* out) {
     return true;
 }
 
-template <int MODEL, class KT>
+template <int MODEL, class KT, int BS>
 static void ball_entry(CubeLaunch* r) {
-    r->stage[0] = k_ball_stage<MODEL, KT, 1, false>;
-    r->stage[1] = k_ball_stage<MODEL, KT, 2, false>;
-    r->stage[2] = k_ball_stage<MODEL, KT, 3, false>;
-    r->stage[3] = k_ball_stage<MODEL, KT, 4, false>;
-    r->stage_mv[0] = k_ball_stage<MODEL, KT, 1, true>;
-    r->stage_mv[1] = k_ball_stage<MODEL, KT, 2, true>;
-    r->stage_mv[2] = k_ball_stage<MODEL, KT, 3, true>;
-    r->stage_mv[3] = k_ball_stage<MODEL, KT, 4, true>;
+    r->stage[0] = k_ball_stage<MODEL, KT, BS, 1, false>;
+    r->stage[1] = k_ball_stage<MODEL, KT, BS, 2, false>;
+    r->stage[2] = k_ball_stage<MODEL, KT, BS, 3, false>;
+    r->stage[3] = k_ball_stage<MODEL, KT, BS, 4, false>;
+    r->stage_mv[0] = k_ball_stage<MODEL, KT, BS, 1, true>;
+    r->stage_mv[1] = k_ball_stage<MODEL, KT, BS, 2, true>;
+    r->stage_mv[2] = k_ball_stage<MODEL, KT, BS, 3, true>;
+    r->stage_mv[3] = k_ball_stage<MODEL, KT, BS, 4, true>;
     r->final_partials = k_cube_final_partials<KT>;
     r->final_R = k_cube_final_R;
 }
 
-bool ball_select(int model, int prec, CubeLaunch* out) {
-    if (model == ND_KURAMOTO) {
-        if (prec == ND_FP64) ball_entry<ND_KURAMOTO, double>(out); else ball_entry<ND_KURAMOTO, float>(out);
-        return true;
-    }
-    if (model == ND_KURAMOTO_INERTIA) {
-        if (prec == ND_FP64) ball_entry<ND_KURAMOTO_INERTIA, double>(out);
-        else ball_entry<ND_KURAMOTO_INERTIA, float>(out);
-        return true;
-    }
+template <int MODEL, class KT>
+static bool ball_pick(int block, CubeLaunch* out) {
+    if (block == 256) ball_entry<MODEL, KT, 256>(out);
+    else if (block == 1024) ball_entry<MODEL, KT, 1024>(out);
+    else return false;
+    return true;
+}
+
+bool ball_select(int model, int prec, int block, CubeLaunch* out) {
+    if (model == ND_KURAMOTO)
+        return prec == ND_FP64 ? ball_pick<ND_KURAMOTO, double>(block, out) : ball_pick<ND_KURAMOTO, float>(block, out);
+    if (model == ND_KURAMOTO_INERTIA)
+        return prec == ND_FP64 ? ball_pick<ND_KURAMOTO_INERTIA, double>(block, out)
+                               : ball_pick<ND_KURAMOTO_INERTIA, float>(block, out);
     return false;
 }
 

@@ -59,6 +59,7 @@ struct Net {
 struct Group {
     int model, topo, prec, tile;
     int tile_y, h;  // cube: y tile extent and half-width (kernel shape)
+    int block;      // ball: workgroup size (256 or 1024)
     bool mv;        // some network records the mean phase velocity
     int ndesc;
     int grid;
@@ -102,10 +103,11 @@ struct CubeLaunch {
     void (*final_R)(const NetDesc*, const int2*, const int*, int);
 };
 bool cube_select(int model, int prec, int h, CubeLaunch* out);
-// Ball neighbourhood (3D lattice, radius P <= kBallMaxP): same launch shape as
-// the cube stage, 1024 threads; LDS = ball_smem_bytes.
+// Ball neighbourhood (3D lattice, radius P <= kBallMaxP): workgroups of 256 or
+// 1024 threads (up to 4 halo rows per wave, one output per thread); LDS =
+// ball_smem_bytes.
 constexpr int kBallMaxP = 8;
-bool ball_select(int model, int prec, CubeLaunch* out);
+bool ball_select(int model, int prec, int block, CubeLaunch* out);
 size_t ball_smem_bytes(int P, int cx, int cy);
 constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB per CU, minus statics)
 int64_t ball_points(int64_t P);

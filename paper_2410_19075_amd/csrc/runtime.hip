@@ -129,28 +129,45 @@ int64_t ball_points(int64_t P) {
     return c;
 }
 
-// Ball tiling: halo rows of HX = cx + 2P <= 64 lanes, at most 1024 outputs and
-// 64 halo rows, and the prefix ring within the LDS budget; then z runs so that
-// the work items fill the CUs in as few rounds as possible.
-static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_) {
+// (dy, dz) runs of the ball of radius P, padded to the kernel's unroll of 8.
+static int ball_runs(int P) {
+    int c = 0;
+    for (int dz = -P; dz <= P; ++dz)
+        for (int dy = -P; dy <= P; ++dy) c += dz * dz + dy * dy <= P * P;
+    return (c + 7) / 8 * 8;
+}
+
+// Ball tiling and workgroup size.  Halo rows of HX = cx + 2P <= 64 lanes, at
+// most 4 rows per wave and one output per thread, the prefix ring within the
+// LDS budget.  A 256-thread workgroup leaves room for up to 4 per CU (LDS
+// permitting), a 1024-thread one holds the CU alone.  The estimated time is
+// (rounds of workgroups over the CU slots) x (planes per work item incl. the
+// 2P lead-in) x (halo rows per wave + the outputs' prefix reads / 10).
+static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_, int* bs_) {
     const int P = (int)p->radius;
     const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
+    const double reads = 0.1 * ball_runs(P);
     double best = 1e300;
-    *cx_ = 1, *cy_ = 1, *cz_ = n3;
-    for (int cx = 1; cx <= std::min(n1, 64 - 2 * P); ++cx) {
-        for (int cy = 1; cy <= std::min(n2, 64 - 2 * P); ++cy) {
-            if (cx * cy > 1024 || ball_smem_bytes(P, cx, cy) > kBallSmemMax) break;
-            const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
-            const int64_t rows = cy + 2 * P;  // mapped halo rows per plane (one wave row each)
-            for (int zt = 1; zt <= std::min(n3, 256); ++zt) {
-                const int cz = (n3 + zt - 1) / zt;
-                if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;
-                const int64_t rounds = (tiles * zt + cus - 1) / cus;
-                // per plane: the mapped rows plus the outputs' prefix reads
-                const double cost = (double)rounds * ((cz + 2 * P) * rows * 64.0 + cz * (double)cx * cy * 2.0 * P * P);
-                if (cost < best) {
-                    best = cost;
-                    *cx_ = cx, *cy_ = cy, *cz_ = cz;
+    *cx_ = 1, *cy_ = 1, *cz_ = n3, *bs_ = 1024;
+    for (int bs : {256, 1024}) {
+        const int waves = bs / 64;
+        for (int cx = 1; cx <= std::min(n1, 64 - 2 * P); ++cx) {
+            for (int cy = 1; cy <= std::min(n2, 4 * waves - 2 * P); ++cy) {
+                if (cx * cy > bs) break;
+                const size_t sm = ball_smem_bytes(P, cx, cy);
+                if (sm > kBallSmemMax) break;
+                const int per_cu = bs == 1024 ? 1 : std::max(1, std::min<int>(4, (int)(kBallSmemMax / sm)));
+                const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
+                const double plane_cost = (double)((cy + 2 * P + waves - 1) / waves) + reads;
+                for (int zt = 1; zt <= std::min(n3, 256); ++zt) {
+                    const int cz = (n3 + zt - 1) / zt;
+                    if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;
+                    const int64_t rounds = (tiles * zt + (int64_t)cus * per_cu - 1) / ((int64_t)cus * per_cu);
+                    const double cost = (double)rounds * (cz + 2 * P) * plane_cost - 1e-6 * cx * cy;
+                    if (cost < best) {
+                        best = cost;
+                        *cx_ = cx, *cy_ = cy, *cz_ = cz, *bs_ = bs;
+                    }
                 }
             }
         }
@@ -226,12 +243,12 @@ nd_kernel_config default_config(const nd_problem* p) {
         c.tile_z = cz;
         c.block = cube_block(h, cx, cy);
     } else if (p->topo == ND_BALL3D) {
-        int cx, cy, cz;
-        ball_tiles(p, device_cu_count(), &cx, &cy, &cz);
+        int cx, cy, cz, bs;
+        ball_tiles(p, device_cu_count(), &cx, &cy, &cz, &bs);
         c.tile = cx;
         c.tile_y = cy;
         c.tile_z = cz;
-        c.block = 1024;
+        c.block = bs;
     } else {
         c.tile = 256;    // target rows per work item
         c.tile_y = 8;    // edges per thread per chunk
@@ -402,7 +419,7 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         tmpl.G = (int32_t)ring_tiles(n, cfg.tile);
     } else if (prob.topo == ND_CUBE3D || prob.topo == ND_BALL3D) {
         const int h = (int)prob.radius;
-        cfg.block = prob.topo == ND_BALL3D ? 1024 : cube_block(h, cfg.tile, cfg.tile_y);
+        if (prob.topo == ND_CUBE3D) cfg.block = cube_block(h, cfg.tile, cfg.tile_y);
         tmpl.cx = cfg.tile;
         tmpl.cy = cfg.tile_y;
         tmpl.cz = cfg.tile_z;
@@ -556,11 +573,12 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
             return hip_fail(e, "cube final");
     } else if (g.topo == ND_BALL3D) {
         CubeLaunch L;
-        if (!ball_select(g.model, g.prec, &L)) return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d", g.model);
+        if (!ball_select(g.model, g.prec, g.block, &L))
+            return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d, block %d", g.model, g.block);
         const size_t smem = ball_smem_bytes(g.h, g.tile, g.tile_y);
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
-                if ((e = cube_launch_stage(L, grid, 1024, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
+                if ((e = cube_launch_stage(L, grid, g.block, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
                     return hip_fail(e, "ball stage");
         if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "ball final");
@@ -625,12 +643,13 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
     for (int i = 0; i < count; ++i)
         if ((s = nets[i]->prepare_observe(steps[i], obs ? &obs[i] : nullptr))) return s;
     // group by kernel class
-    std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int, int, int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const Net* n = nets[i];
         const int h = (n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D) ? (int)n->prob.radius : 0;
-        groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h)]
+        const int bs = n->prob.topo == ND_BALL3D ? n->cfg.block : 0;
+        groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h, bs)]
             .push_back(i);
     }
     for (auto& kv : groups) {
@@ -642,6 +661,7 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         g.tile = std::get<3>(kv.first);
         g.tile_y = std::get<4>(kv.first);
         g.h = std::get<5>(kv.first);
+        g.block = std::get<6>(kv.first);
         g.ndesc = (int)idx.size();
         int64_t maxsteps = 0;
         std::vector<NetDesc> descs;
@@ -832,10 +852,12 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         c.tile = (int32_t)std::min<int64_t>(c.tile, p.n1);
         c.tile_y = (int32_t)std::min<int64_t>(c.tile_y, p.n2);
         c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
-        if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > 64 || c.tile * c.tile_y > 1024 ||
+        if (c.block != 256 && c.block != 1024) c.block = 1024;
+        const int rows = 4 * (c.block / 64);
+        if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > rows || c.tile * c.tile_y > c.block ||
             ball_smem_bytes(P, c.tile, c.tile_y) > kBallSmemMax)
-            return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 64, tile*tile_y <= 1024 "
-                                            "and the prefix ring within LDS");
+            return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 4*block/64, "
+                                            "tile*tile_y <= block and the prefix ring within LDS");
     } else {
         if (c.tile != 256) return fail(ND_ERR_INVALID_ARG, "CSR work items hold 256 rows (tile must be 256)");
         if (c.tile_y < 2 || c.tile_y > 16 || (c.tile_y & (c.tile_y - 1)))

@@ -34,11 +34,12 @@ namespace nd {
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
-using ClassKey = std::tuple<int, int, int, int, int, int>;
+using ClassKey = std::tuple<int, int, int, int, int, int, int>;
 
 static ClassKey class_key(const Net* n) {
     const int h = (n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D) ? (int)n->prob.radius : 0;
-    return ClassKey(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h);
+    const int bs = n->prob.topo == ND_BALL3D ? n->cfg.block : 0;
+    return ClassKey(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h, bs);
 }
 
 struct Request {
@@ -151,6 +152,7 @@ nd_status Server::table_for(Request* r, ClassTable** out) {
     g.tile = std::get<3>(key);
     g.tile_y = std::get<4>(key);
     g.h = std::get<5>(key);
+    g.block = std::get<6>(key);
     g.ndesc = t->cap_desc;
     g.grid = cfg.grid;
     HIPC(hipHostMalloc((void**)&t->h_desc, (size_t)t->cap_desc * sizeof(NetDesc)));
