@@ -33,7 +33,8 @@
  *     neighbourhood of the paper's 3D studies: every lattice point within
  *     Euclidean distance P, the element itself included (Sec. V counts 33 links
  *     for P = 2 and 925 for P = 6), L = that count, taken in lexicographic
- *     (dz, dy, dx) order.
+ *     (dz, dy, dx) order; and on the periodic n1 x n2 plane with the disk of
+ *     radius P (the 2D studies), centre included, in (dy, dx) order.
  *   FitzHugh-Nagumo, Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational
  *     coupling matrix B(phi) acting on (u_j - u_i, v_j - v_i), averaged over
  *     the 2P ring neighbours and placed inside the eps-scaled fast equation:
@@ -62,7 +63,7 @@
 #define ORC_ENOMEM -2
 
 enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2, ORC_INERTIA = 3 };
-enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3 };
+enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3, ORC_DISK = 4 };
 
 typedef struct {
     int model, topo;
@@ -147,9 +148,19 @@ static int64_t ball_links(int64_t P) {
     return c;
 }
 
+static int64_t disk_links(int64_t P) {
+    int64_t c = 0;
+    for (int64_t dy = -P; dy <= P; ++dy)
+        for (int64_t dx = -P; dx <= P; ++dx)
+            if (dx * dx + dy * dy <= P * P) ++c;
+    return c;
+}
+
+/* The ball (3D) or the disk (2D: the z offset is always 0). */
 static double kuramoto_ball_coupling(const orc_net* m, const double* z, int64_t i, double alpha) {
     const int64_t n1 = m->n1, n2 = m->n2, n3 = m->n3, P = m->radius;
-    const int64_t side = 2 * P + 1, cells = side * side * side;
+    const int disk = m->topo == ORC_DISK;
+    const int64_t side = 2 * P + 1, cells = disk ? side * side : side * side * side;
     const int64_t x = i % n1, y = (i / n1) % n2, zz = i / (n1 * n2);
     double s = 0.0;
     for (int64_t t = 0; t < cells; ++t) {
@@ -161,7 +172,7 @@ static double kuramoto_ball_coupling(const orc_net* m, const double* z, int64_t 
         int64_t j = wrapi(x + dx, n1) + n1 * (wrapi(y + dy, n2) + n2 * wrapi(zz + dz, n3));
         s += sin(z[j] - z[i] - alpha);
     }
-    return s * (1.0 / (double)ball_links(P));
+    return s * (1.0 / (double)(disk ? disk_links(P) : ball_links(P)));
 }
 
 static void rhs_kuramoto_ball(const orc_net* m, const double* z, double* f) {
@@ -289,8 +300,8 @@ static int rhs(const orc_net* m, const double* z, double* f) {
     else if (m->model == ORC_KURAMOTO && m->topo == ORC_CUBE) rhs_kuramoto_cube(m, z, f);
     else if (m->model == ORC_INERTIA && m->topo == ORC_RING) rhs_inertia_ring(m, z, f);
     else if (m->model == ORC_INERTIA && m->topo == ORC_CUBE) rhs_inertia_cube(m, z, f);
-    else if (m->model == ORC_KURAMOTO && m->topo == ORC_BALL) rhs_kuramoto_ball(m, z, f);
-    else if (m->model == ORC_INERTIA && m->topo == ORC_BALL) rhs_inertia_ball(m, z, f);
+    else if (m->model == ORC_KURAMOTO && (m->topo == ORC_BALL || m->topo == ORC_DISK)) rhs_kuramoto_ball(m, z, f);
+    else if (m->model == ORC_INERTIA && (m->topo == ORC_BALL || m->topo == ORC_DISK)) rhs_inertia_ball(m, z, f);
     else if (m->model == ORC_FHN && m->topo == ORC_RING) rhs_fhn_ring(m, z, f);
     else if (m->model == ORC_HH && m->topo == ORC_CSR) rhs_hh_csr(m, z, f);
     else return ORC_EINVAL;
@@ -301,6 +312,10 @@ static int validate(const orc_net* m) {
     if (m->n <= 0) return ORC_EINVAL;
     if (m->topo == ORC_RING) {
         if (m->radius < 1 || 2 * m->radius + 1 > m->n) return ORC_EINVAL;
+    } else if (m->topo == ORC_DISK) {
+        int64_t side = 2 * m->radius + 1;
+        if (m->radius < 1 || m->n1 < side || m->n2 < side || m->n3 != 1) return ORC_EINVAL;
+        if (m->n1 * m->n2 != m->n) return ORC_EINVAL;
     } else if (m->topo == ORC_CUBE || m->topo == ORC_BALL) {
         int64_t side = 2 * m->radius + 1;
         if (m->radius < 1 || m->n1 < side || m->n2 < side || m->n3 < side) return ORC_EINVAL;

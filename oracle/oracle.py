@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 KURAMOTO, FHN, HH, INERTIA = 0, 1, 2, 3
-RING, CUBE, CSR, BALL = 0, 1, 2, 3
+RING, CUBE, CSR, BALL, DISK = 0, 1, 2, 3, 4
 NVARS = {KURAMOTO: 1, FHN: 2, HH: 4, INERTIA: 2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +84,12 @@ def ball(n1, P, params, n2=None, n3=None, model=KURAMOTO):
     n2 = n1 if n2 is None else n2
     n3 = n1 if n3 is None else n3
     return Net(model, BALL, n1 * n2 * n3, params, radius=P, dims=(n1, n2, n3))
+
+
+def disk(n1, P, params, n2=None, model=KURAMOTO):
+    """Periodic n1 x n2 plane, neighbours = lattice points within distance P, centre included."""
+    n2 = n1 if n2 is None else n2
+    return Net(model, DISK, n1 * n2, params, radius=P, dims=(n1, n2, 1))
 
 
 def csr(n, row_ptr, col, w, params, i_app):

@@ -733,3 +733,55 @@ def test_ball_axis_permutation_symmetry():
     perm = (2, 0, 1)
     yp, _, _ = O.run(net, np.transpose(y0.reshape(n1, n1, n1), perm).ravel().copy(), 0.05, 10)
     assert np.max(np.abs(np.transpose(y.reshape(n1, n1, n1), perm).ravel() - yp)) < 1e-13
+
+
+# ------------------------------------------------ disk neighbourhood (2D plane)
+def disk_offsets(P):
+    r = np.arange(-P, P + 1)
+    X, Y = np.meshgrid(r, r, indexing="ij")
+    keep = X ** 2 + Y ** 2 <= P * P
+    return X[keep], Y[keep]
+
+
+@pytest.mark.parametrize("P,count", [(1, 5), (2, 13), (3, 29), (6, 113)])
+def test_disk_link_count(P, count):
+    """Gauss circle counts N(P) = #{x^2 + y^2 <= P^2}: 5, 13, 29, 113; the oracle's
+    normalisation is recovered from a single perturbed neighbour."""
+    assert len(disk_offsets(P)[0]) == count
+    n1 = 2 * P + 3
+    omega, mu, alpha, d = 0.2, 1.3, 0.45, 0.9
+    net = O.disk(n1, P, kur(omega, mu, alpha))
+    base = O.rhs(net, np.zeros(n1 * n1))[0]
+    z = np.zeros(n1 * n1)
+    z[1] = d  # offset (1, 0), inside every disk
+    L = mu * (math.sin(d - alpha) + math.sin(alpha)) / (O.rhs(net, z)[0] - base)
+    assert L == pytest.approx(count, rel=1e-9)
+
+
+@pytest.mark.parametrize("P,q", [(2, (1, 0)), (3, (1, -2)), (5, (2, 3))])
+def test_disk_plane_wave_rotates_at_closed_form(P, q):
+    n1, n2 = 17, 19
+    idx = np.arange(n1 * n2)
+    x, y = idx % n1, idx // n1
+    th = (2 * math.pi * q[0] / n1, 2 * math.pi * q[1] / n2)
+    phi0 = th[0] * x + th[1] * y
+    omega, mu, alpha = 0.1, 0.8, 0.45
+    dx, dy = disk_offsets(P)
+    om = omega - mu * math.sin(alpha) * float(np.mean(np.cos(th[0] * dx + th[1] * dy)))
+    yt, _, _ = O.run(O.disk(n1, P, kur(omega, mu, alpha), n2=n2), phi0, 0.05, 20)
+    assert np.max(np.abs((yt - phi0) - om * 1.0)) < 1e-12
+
+
+def test_disk_dense_brute_force_inertia():
+    n1, n2, P = 11, 13, 3
+    n = n1 * n2
+    idx = np.arange(n)
+    x, y = idx % n1, idx // n1
+    A = np.zeros((n, n))
+    for ox, oy in zip(*disk_offsets(P)):
+        A[idx, (x + ox) % n1 + n1 * ((y + oy) % n2)] += 1.0
+    prm = inert(0.2, 1.1, 0.45, 1.5, 0.2)
+    y0 = np.concatenate([inputs.kuramoto_phases(16, n), inputs.uniform_range(17, inputs.TAG_MISC, n, -1, 1)])
+    ref = dense_rk4(inertia_dense(A, *prm), y0, 0.05, 30)
+    yy, _, _ = O.run(O.disk(n1, P, prm, n2=n2, model=O.INERTIA), y0, 0.05, 30)
+    assert np.max(np.abs(yy - ref)) / np.max(np.abs(ref)) < 1e-13
