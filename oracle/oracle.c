@@ -165,7 +165,7 @@ static double kuramoto_ball_coupling(const orc_net* m, const double* z, int64_t 
     double s = 0.0;
     for (int64_t t = 0; t < cells; ++t) {
         int64_t q = m->reverse ? (cells - 1 - t) : t;
-        int64_t dz = q / (side * side) - P;
+        int64_t dz = disk ? 0 : q / (side * side) - P;
         int64_t dy = (q / side) % side - P;
         int64_t dx = q % side - P;
         if (dx * dx + dy * dy + dz * dz > P * P) continue;
