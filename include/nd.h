@@ -16,12 +16,13 @@
  *   ND_KURAMOTO  Eq. (3) with m = 0, eps = 1 and a natural frequency:
  *                dphi_i/dt = omega + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
  *                L = number of neighbours (the paper's Alg. 1 divides by the link count).
- *                params = {omega, mu, alpha}.  Topology ND_RING, ND_CUBE3D or ND_BALL3D.
+ *                params = {omega, mu, alpha}.  Topology ND_RING, ND_CUBE3D, ND_BALL3D or ND_DISK2D.
  *   ND_KURAMOTO_INERTIA  Eq. (3) with inertia (m != 0) as a first-order system in
  *                (phi, psi = dphi/dt), plus a natural frequency:
  *                dphi_i/dt = psi_i,
  *                m dpsi_i/dt = omega - eps psi_i + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha).
- *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING, ND_CUBE3D or ND_BALL3D.
+ *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING, ND_CUBE3D, ND_BALL3D or
+ *                ND_DISK2D.
  *   ND_FHN       Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational coupling
  *                matrix B(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] applied to
  *                (u_j - u_i, v_j - v_i), averaged over the 2P ring neighbours, inside the
@@ -43,6 +44,9 @@
  *                Euclidean distance P = radius, the element itself included (the paper's 3D
  *                studies: 33 links for P = 2, 925 for P = 6, Sec. V); L = that count; 1 <= P <= 8,
  *                n1,n2,n3 >= 2P+1, n < 2^29.  Kuramoto models only.
+ *   ND_DISK2D    periodic n1 x n2 plane (n3 = 1, index x + n1*y), neighbours = every lattice point
+ *                within distance P, the element included (the paper's 2D studies); 1 <= P <= 8,
+ *                n1, n2 >= 2P+1.  Kuramoto models only.
  *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,
  *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
  *
@@ -96,6 +100,7 @@ typedef int32_t nd_status;
 #define ND_CUBE3D 1
 #define ND_CSR 2
 #define ND_BALL3D 3
+#define ND_DISK2D 4
 
 #define ND_FP64 0
 #define ND_FP32_BULK 1
@@ -105,7 +110,7 @@ typedef int32_t nd_status;
 /* A network: model, parameters, topology, precision.  All pointers are host pointers. */
 typedef struct nd_problem {
     int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA */
-    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D */
+    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D */
     int32_t precision;  /* ND_FP64, ND_FP32_BULK */
     int32_t reserved;   /* must be 0 */
     int64_t n;          /* number of elements */
@@ -173,7 +178,7 @@ typedef struct nd_kernel_config {
                        the whole ring (n <= that capacity) resident in one workgroup;
                        cube: output tile extent along x; CSR: rows per workgroup */
     int32_t block;  /* threads per workgroup: derived (ignored by nd_set_config), except for
-                       ND_BALL3D, where it selects 256 or 1024 */
+                       ND_BALL3D / ND_DISK2D, where it selects 256 or 1024 */
     int32_t grid;   /* persistent grid size in workgroups; 0 = one workgroup per work item */
     int32_t chunk;  /* steps per captured graph chunk */
     int32_t tile_y; /* cube: output tile extent along y ((tile+2h)*(tile_y+2h) <= 1024);

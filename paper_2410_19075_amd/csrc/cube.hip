@@ -281,7 +281,9 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
 
 // ------------------------------------------------------------------ ball
 // Ball neighbourhood of the paper's 3D studies: every lattice point within
-// Euclidean distance P, the element itself included (L = that count).  The
+// Euclidean distance P, the element itself included (L = that count); the
+// disk of the 2D studies is the same kernel with a z half-width of 0 on an
+// n1 x n2 x 1 lattice.  The
 // ball is the union over (dy, dz) with dy^2 + dz^2 <= P^2 of x-runs of
 // half-width r = floor(sqrt(P^2 - dy^2 - dz^2)), so with per-row prefix sums
 // along x every run is one difference of two prefix values.
@@ -323,7 +325,8 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
         const int64_t n = d.n;
         const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
         const int cx = d.cx, cy = d.cy, cz = d.cz, gx = d.gx, gy = d.gy;
-        const int HX = cx + 2 * P, HY = cy + 2 * P, NS = 2 * P + 2, RW = HX + 1;
+        const int PZ = d.pz;  // z half-width: P (ball) or 0 (disk)
+        const int HX = cx + 2 * P, HY = cy + 2 * P, NS = 2 * PZ + 2, RW = HX + 1;
         const int t = wk.y;
         const int tx = t % gx, ty = (t / gx) % gy, tz = t / (gx * gy);
         const int x0 = tx * cx, y0 = ty * cy, z0 = tz * cz;
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
         }
         if (tid == 0) {
             int c = 0;
-            for (int dz = -P; dz <= P; ++dz)
+            for (int dz = -PZ; dz <= PZ; ++dz)
                 for (int dy = -P; dy <= P; ++dy) {
                     const int q = P * P - dz * dz - dy * dy;
                     if (q < 0) continue;
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
         // map plane q (relative: absolute z = z0 - P + q) into ring slot q % NS
         double qz[kBallRowsPerWave];
         auto load_plane = [&](int q) {
-            const uint32_t zb = plane * (uint32_t)wrapm(z0 - P + min(q, nz + 2 * P - 1), n3);
+            const uint32_t zb = plane * (uint32_t)wrapm(z0 - PZ + min(q, nz + 2 * PZ - 1), n3);
 #pragma unroll
             for (int k = 0; k < kBallRowsPerWave; ++k)
                 if (rv[k]) qz[k] = zval(rowbase[k] + zb);
@@ -400,11 +403,11 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
                 if (lane == 0) row[0] = make_double2(0.0, 0.0);
             }
         };
-        for (int q = 0; q < 2 * P; ++q) {
+        for (int q = 0; q < 2 * PZ; ++q) {
             load_plane(q);
             store_plane(q);
         }
-        load_plane(2 * P);
+        load_plane(2 * PZ);
 
         // output thread
         const bool outv = tid < cx * cy && (tid % cx) < ex && (tid / cx) < ey;
@@ -437,14 +440,14 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
                 av[v] = na[v];
             }
             own(i + 1);
-            store_plane(i + 2 * P);   // the plane entering the window of output plane zo
-            load_plane(i + 2 * P + 1);
+            store_plane(i + 2 * PZ);   // the plane entering the window of output plane zo
+            load_plane(i + 2 * PZ + 1);
             lds_barrier();
             if (outv) {
                 // runs in (dz, dy) order, kBallUnroll at a time so their LDS
                 // reads are in flight together; the sum order is fixed
                 double2 W = make_double2(0.0, 0.0);
-                const int s0 = (i + P) % NS;  // slot of the centre plane
+                const int s0 = (i + PZ) % NS;  // slot of the centre plane
                 const double2* centre = smem + (size_t)(oy + P) * RW + ox + P;
                 const int nr = nruns;
                 for (int k0 = 0; k0 < nr; k0 += kBallUnroll) {
@@ -617,8 +620,8 @@ bool ball_select(int model, int prec, int block, CubeLaunch* out) {
     return false;
 }
 
-size_t ball_smem_bytes(int P, int cx, int cy) {
-    return (size_t)(2 * P + 2) * (cy + 2 * P) * (cx + 2 * P + 1) * sizeof(double2);
+size_t ball_smem_bytes(int P, int pz, int cx, int cy) {
+    return (size_t)(2 * pz + 2) * (cy + 2 * P) * (cx + 2 * P + 1) * sizeof(double2);
 }
 
 bool cube_select(int model, int prec, int h, CubeLaunch* out) {

@@ -23,6 +23,7 @@ struct NetDesc {
     int32_t model, prec, obs, tile;
     int32_t cx, cy, cz; // cube: output tile extents per work item (x, y, z)
     int32_t gx, gy;     // cube: tiles along x and y
+    int32_t pz;         // ball / disk: z half-width of the neighbourhood (P, or 0 for the disk)
     double dt;
     double dt3, dt6;    // dt/3 and dt/6 (rounded once, on the host)
     double p[12];       // derived model constants (layout per model, see runtime)

@@ -108,9 +108,11 @@ bool cube_select(int model, int prec, int h, CubeLaunch* out);
 // ball_smem_bytes.
 constexpr int kBallMaxP = 8;
 bool ball_select(int model, int prec, int block, CubeLaunch* out);
-size_t ball_smem_bytes(int P, int cx, int cy);
+size_t ball_smem_bytes(int P, int pz, int cx, int cy);
+inline int ball_pz(int topo, int64_t P) { return topo == ND_DISK2D ? 0 : (int)P; }
 constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB per CU, minus statics)
 int64_t ball_points(int64_t P);
+int64_t disk_points(int64_t P);
 size_t cube_smem_bytes(int h, int cx, int cy);
 int cube_block(int h, int cx, int cy);
 hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,

@@ -99,6 +99,19 @@ nd_status validate_problem(const nd_problem* p) {
                 return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         }
+        case ND_DISK2D: {
+            if (p->model != ND_KURAMOTO && p->model != ND_KURAMOTO_INERTIA)
+                return fail(ND_ERR_INVALID_ARG, "the disk topology is for the Kuramoto models");
+            const int64_t side = 2 * p->radius + 1;
+            if (p->radius < 1 || p->radius > kBallMaxP)
+                return fail(ND_ERR_INVALID_ARG, "disk radius must be in [1, %d]", kBallMaxP);
+            if (p->n1 < side || p->n2 < side || p->n3 != 1)
+                return fail(ND_ERR_INVALID_ARG, "the disk needs n1, n2 >= 2P+1 and n3 = 1");
+            if (p->n1 * p->n2 != p->n) return fail(ND_ERR_INVALID_ARG, "n must equal n1*n2");
+            if (p->n >= (int64_t(1) << 29))
+                return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
+            break;
+        }
         case ND_CSR: {
             if (p->model != ND_HH) return fail(ND_ERR_INVALID_ARG, "the CSR topology is for HH");
             if (!p->row_ptr || (p->nnz > 0 && (!p->col || !p->weight)) || !p->per_elem)
@@ -121,6 +134,13 @@ nd_status validate_problem(const nd_problem* p) {
 }
 
 // Lattice points within distance P of the origin, the origin included.
+int64_t disk_points(int64_t P) {
+    int64_t c = 0;
+    for (int64_t dy = -P; dy <= P; ++dy)
+        for (int64_t dx = -P; dx <= P; ++dx) c += dx * dx + dy * dy <= P * P;
+    return c;
+}
+
 int64_t ball_points(int64_t P) {
     int64_t c = 0;
     for (int64_t dz = -P; dz <= P; ++dz)
@@ -130,9 +150,9 @@ int64_t ball_points(int64_t P) {
 }
 
 // (dy, dz) runs of the ball of radius P, padded to the kernel's unroll of 8.
-static int ball_runs(int P) {
+static int ball_runs(int P, int pz) {
     int c = 0;
-    for (int dz = -P; dz <= P; ++dz)
+    for (int dz = -pz; dz <= pz; ++dz)
         for (int dy = -P; dy <= P; ++dy) c += dz * dz + dy * dy <= P * P;
     return (c + 7) / 8 * 8;
 }
@@ -144,9 +164,9 @@ static int ball_runs(int P) {
 // (rounds of workgroups over the CU slots) x (planes per work item incl. the
 // 2P lead-in) x (halo rows per wave + the outputs' prefix reads / 10).
 static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_, int* bs_) {
-    const int P = (int)p->radius;
+    const int P = (int)p->radius, pz = ball_pz(p->topo, p->radius);
     const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
-    const double reads = 0.1 * ball_runs(P);
+    const double reads = 0.1 * ball_runs(P, pz);
     double best = 1e300;
     *cx_ = 1, *cy_ = 1, *cz_ = n3, *bs_ = 1024;
     for (int bs : {256, 1024}) {
@@ -154,7 +174,7 @@ static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz
         for (int cx = 1; cx <= std::min(n1, 64 - 2 * P); ++cx) {
             for (int cy = 1; cy <= std::min(n2, 4 * waves - 2 * P); ++cy) {
                 if (cx * cy > bs) break;
-                const size_t sm = ball_smem_bytes(P, cx, cy);
+                const size_t sm = ball_smem_bytes(P, pz, cx, cy);
                 if (sm > kBallSmemMax) break;
                 const int per_cu = bs == 1024 ? 1 : std::max(1, std::min<int>(4, (int)(kBallSmemMax / sm)));
                 const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
@@ -163,7 +183,7 @@ static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz
                     const int cz = (n3 + zt - 1) / zt;
                     if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;
                     const int64_t rounds = (tiles * zt + (int64_t)cus * per_cu - 1) / ((int64_t)cus * per_cu);
-                    const double cost = (double)rounds * (cz + 2 * P) * plane_cost - 1e-6 * cx * cy;
+                    const double cost = (double)rounds * (cz + 2 * pz) * plane_cost - 1e-6 * cx * cy;
                     if (cost < best) {
                         best = cost;
                         *cx_ = cx, *cy_ = cy, *cz_ = cz, *bs_ = bs;
@@ -242,7 +262,7 @@ nd_kernel_config default_config(const nd_problem* p) {
         c.tile_y = cy;
         c.tile_z = cz;
         c.block = cube_block(h, cx, cy);
-    } else if (p->topo == ND_BALL3D) {
+    } else if (p->topo == ND_BALL3D || p->topo == ND_DISK2D) {
         int cx, cy, cz, bs;
         ball_tiles(p, device_cu_count(), &cx, &cy, &cz, &bs);
         c.tile = cx;
@@ -270,7 +290,7 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
     const int64_t V = nvars_of(p->model), n = p->n, kb = bulk_bytes(p->precision);
     int64_t b = 3 * V * n * 8 + 3 * V * n * kb;  // y[2], acc, k[3]
     if (p->topo == ND_RING) b += 3 * 2 * ring_tiles(n, c.tile) * 8;
-    if (p->topo == ND_CUBE3D || p->topo == ND_BALL3D)
+    if (p->topo == ND_CUBE3D || p->topo == ND_BALL3D || p->topo == ND_DISK2D)
         b += 3 * 2 * 8 * ((p->n1 + c.tile - 1) / c.tile) * ((p->n2 + c.tile_y - 1) / c.tile_y) *
              ((p->n3 + c.tile_z - 1) / c.tile_z);
     if (p->topo == ND_CSR)
@@ -298,6 +318,7 @@ static void derive_params(const nd_problem* p, NetDesc& d) {
     if (p->model == ND_KURAMOTO || p->model == ND_KURAMOTO_INERTIA) {
         const double L = p->topo == ND_RING     ? 2.0 * (double)p->radius
                          : p->topo == ND_BALL3D ? (double)ball_points(p->radius)
+                         : p->topo == ND_DISK2D ? (double)disk_points(p->radius)
                                                 : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
         d.p[0] = p->params[0];
         d.p[1] = p->params[1] / L;
@@ -417,7 +438,7 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         cfg.block = ring_block(cfg.tile);
         tmpl.tile = cfg.tile;
         tmpl.G = (int32_t)ring_tiles(n, cfg.tile);
-    } else if (prob.topo == ND_CUBE3D || prob.topo == ND_BALL3D) {
+    } else if (prob.topo == ND_CUBE3D || prob.topo == ND_BALL3D || prob.topo == ND_DISK2D) {
         const int h = (int)prob.radius;
         if (prob.topo == ND_CUBE3D) cfg.block = cube_block(h, cfg.tile, cfg.tile_y);
         tmpl.cx = cfg.tile;
@@ -425,6 +446,7 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         tmpl.cz = cfg.tile_z;
         tmpl.gx = (int32_t)((prob.n1 + cfg.tile - 1) / cfg.tile);
         tmpl.gy = (int32_t)((prob.n2 + cfg.tile_y - 1) / cfg.tile_y);
+        tmpl.pz = ball_pz(prob.topo, prob.radius);
         const int32_t gz = (int32_t)((prob.n3 + cfg.tile_z - 1) / cfg.tile_z);
         tmpl.G = tmpl.gx * tmpl.gy * gz;
     } else {
@@ -571,11 +593,11 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
                     return hip_fail(e, "cube stage");
         if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "cube final");
-    } else if (g.topo == ND_BALL3D) {
+    } else if (g.topo == ND_BALL3D || g.topo == ND_DISK2D) {
         CubeLaunch L;
         if (!ball_select(g.model, g.prec, g.block, &L))
             return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d, block %d", g.model, g.block);
-        const size_t smem = ball_smem_bytes(g.h, g.tile, g.tile_y);
+        const size_t smem = ball_smem_bytes(g.h, ball_pz(g.topo, g.h), g.tile, g.tile_y);
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
                 if ((e = cube_launch_stage(L, grid, g.block, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
@@ -647,8 +669,9 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
     for (int i = 0; i < count; ++i) {
         if (steps[i] == 0) continue;
         const Net* n = nets[i];
-        const int h = (n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D) ? (int)n->prob.radius : 0;
-        const int bs = n->prob.topo == ND_BALL3D ? n->cfg.block : 0;
+        const int h = n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D
+                          ? (int)n->prob.radius : 0;
+        const int bs = (n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D) ? n->cfg.block : 0;
         groups[std::make_tuple(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h, bs)]
             .push_back(i);
     }
@@ -845,8 +868,8 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
         if ((c.tile + 2 * h) * (c.tile_y + 2 * h) > 1024)
             return fail(ND_ERR_INVALID_ARG, "cube tile: (tile+2h)*(tile_y+2h) must be <= 1024");
-    } else if (p.topo == ND_BALL3D) {
-        const int P = (int)p.radius;
+    } else if (p.topo == ND_BALL3D || p.topo == ND_DISK2D) {
+        const int P = (int)p.radius, pz = ball_pz(p.topo, p.radius);
         if (c.tile < 1 || c.tile_y < 1 || c.tile_z < 1)
             return fail(ND_ERR_INVALID_ARG, "ball tile extents must be >= 1");
         c.tile = (int32_t)std::min<int64_t>(c.tile, p.n1);
@@ -855,7 +878,7 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         if (c.block != 256 && c.block != 1024) c.block = 1024;
         const int rows = 4 * (c.block / 64);
         if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > rows || c.tile * c.tile_y > c.block ||
-            ball_smem_bytes(P, c.tile, c.tile_y) > kBallSmemMax)
+            ball_smem_bytes(P, pz, c.tile, c.tile_y) > kBallSmemMax)
             return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 4*block/64, "
                                             "tile*tile_y <= block and the prefix ring within LDS");
     } else {

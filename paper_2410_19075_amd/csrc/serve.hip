@@ -37,8 +37,9 @@ namespace nd {
 using ClassKey = std::tuple<int, int, int, int, int, int, int>;
 
 static ClassKey class_key(const Net* n) {
-    const int h = (n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D) ? (int)n->prob.radius : 0;
-    const int bs = n->prob.topo == ND_BALL3D ? n->cfg.block : 0;
+    const int h = n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D
+                      ? (int)n->prob.radius : 0;
+    const int bs = (n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D) ? n->cfg.block : 0;
     return ClassKey(n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y, h, bs);
 }
 

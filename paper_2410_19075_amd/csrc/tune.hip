@@ -49,7 +49,7 @@ static int log2_bucket(int64_t v) {
 static TuneKey tune_key(const nd_problem* p, const std::string& arch) {
     // ring: width bucket = floor(8 P / n) (P/n in eighths); cube: half-width h
     const int wb = p->topo == ND_RING ? (int)(8 * p->radius / p->n) : 0;
-    const int h = (p->topo == ND_CUBE3D || p->topo == ND_BALL3D) ? (int)p->radius : 0;
+    const int h = p->topo == ND_CUBE3D || p->topo == ND_BALL3D || p->topo == ND_DISK2D ? (int)p->radius : 0;
     return TuneKey(arch, p->model, p->topo, p->precision, log2_bucket(p->n), wb, h);
 }
 
@@ -85,7 +85,7 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
                 v.push_back(c);
             }
         }
-    } else if (p->topo == ND_BALL3D) {
+    } else if (p->topo == ND_BALL3D || p->topo == ND_DISK2D) {
         v.push_back(base);  // the cost-model tiling
         for (int cz : {base.tile_z * 2, (base.tile_z + 1) / 2}) {
             nd_kernel_config c = base;

@@ -18,7 +18,7 @@ ND_ERR_NUMERIC = -5
 ND_ERR_UNSUPPORTED = -6
 
 ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA = 0, 1, 2, 3
-ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D = 0, 1, 2, 3
+ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D = 0, 1, 2, 3, 4
 ND_FP64, ND_FP32_BULK = 0, 1
 ND_MAX_PARAMS = 12
 NVARS = {ND_KURAMOTO: 1, ND_FHN: 2, ND_HH: 4, ND_KURAMOTO_INERTIA: 2}

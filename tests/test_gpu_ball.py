@@ -112,3 +112,51 @@ def test_ball_paper_performance_shapes(nd, n1, P, steps):
     y, _, _ = nd.simulate(p, y0, 0.05, steps)
     ref, _, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, steps)
     assert normwise(y, ref, 2) < 1e-12
+
+
+def case2d(nd, model, n1, n2, P, seed, steps, prec=0, cfg=None, record_every=0):
+    n = n1 * n2
+    phases = inputs.kuramoto_phases(seed, n)
+    if model == "inertia":
+        y0 = np.concatenate([phases, inputs.uniform_range(seed, inputs.TAG_MISC, n, -0.5, 0.5)])
+        code, ocode, prm, nv = nd.ND_KURAMOTO_INERTIA, O.INERTIA, INERT, 2
+    else:
+        y0, code, ocode, prm, nv = phases, nd.ND_KURAMOTO, O.KURAMOTO, KUR, 1
+    p = nd.problem(code, nd.ND_DISK2D, n, prm, precision=prec, radius=P, dims=(n1, n2, 1))
+    h = nd.nd_create(p)
+    try:
+        if cfg:
+            c = nd.nd_get_config(h)
+            for k, v in cfg.items():
+                setattr(c, k, v)
+            nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, 0.05, steps, nd.observe(record_every, -1))
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+        R = None
+        if record_every:
+            R = np.empty(steps // record_every + 1)
+            nd.nd_get_observables(h, R=R, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    ref, Rref, _ = O.run(O.disk(n1, P, prm, n2=n2, model=ocode), y0, 0.05, steps, record_every=record_every)
+    return y, ref, R, Rref, nv
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "inertia"])
+@pytest.mark.parametrize("n1,n2,P,cfg", [(40, 36, 2, None), (17, 19, 6, None), (64, 64, 1, None),
+                                         (30, 25, 3, dict(tile=7, tile_y=5, tile_z=1)),
+                                         (50, 40, 4, dict(tile=32, tile_y=8, tile_z=1, block=256))])
+def test_disk_fp64_parity(nd, model, n1, n2, P, cfg):
+    print(f"case disk {model} {n1}x{n2} P={P} cfg={cfg}", flush=True)
+    y, ref, R, Rref, nv = case2d(nd, model, n1, n2, P, n1 + P, 40, cfg=cfg, record_every=4)
+    assert normwise(y, ref, nv) < 1e-12
+    assert np.max(np.abs(R - Rref)) < 1e-12
+
+
+def test_disk_fp32_bulk(nd):
+    y, ref, _, _, nv = case2d(nd, "inertia", 48, 48, 3, 9, 200, prec=1)
+    e = normwise(y, ref, nv)
+    print(f"disk fp32-bulk error {e:.3e}")
+    assert e < 1e-4
