@@ -446,3 +446,104 @@ int orc_run(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t 
 
 /* Order parameter of a state, exposed for the observable pins. */
 double orc_order_parameter(int model, int64_t n, const double* y) { return order_parameter(model, n, y); }
+
+/* ------------------------------------------------- Dormand-Prince 5(4) stepping
+ * The embedded explicit Runge-Kutta pair of Dormand & Prince (1980), the
+ * paper's default solver (Sec. III.A), with the usual step-size control
+ * (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4):
+ *   err = sqrt(mean_i ((y5_i - y4_i) / (atol + rtol * max(|y_i|, |y5_i|)))^2),
+ *   accept when err <= 1; new h = h * min(facmax, max(0.2, 0.9 * err^(-1/5))),
+ *   facmax = 10, and 1 right after a rejection; the step that reaches t_end
+ *   (to within a relative 1e-12 of h) is shortened to end exactly on it.
+ * The fifth-order solution propagates and the last stage is the first stage of
+ * the next step (first same as last).  rtol <= 0 selects fixed steps of dt0
+ * with no control (used by the order pin).
+ * stats[4] = {t reached, accepted steps, rejected steps, last proposed h}. */
+static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+/* fifth minus fourth order weights */
+static const double DP_E[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
+
+int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t n2, int64_t n3,
+                  const int64_t* row_ptr, const int32_t* col, const double* w, const double* prm,
+                  const double* per_elem, double* y, double t_end, double rtol, double atol, double dt0,
+                  int64_t max_steps, double* stats) {
+    orc_net m = make_net(model, topo, n, radius, n1, n2, n3, row_ptr, col, w, prm, per_elem, 0);
+    int rc = validate(&m);
+    if (rc) return rc;
+    if (!(dt0 > 0.0) || !(t_end >= 0.0) || max_steps < 0) return ORC_EINVAL;
+    const int64_t len = (int64_t)nvars(model) * n;
+    double* k[7];
+    double* z = (double*)malloc(sizeof(double) * len);
+    int ok = z != NULL;
+    for (int s = 0; s < 7; ++s) {
+        k[s] = (double*)malloc(sizeof(double) * len);
+        ok = ok && k[s];
+    }
+    if (!ok) {
+        free(z);
+        for (int s = 0; s < 7; ++s) free(k[s]);
+        return ORC_ENOMEM;
+    }
+    (void)DP_C;
+    double t = 0.0, h = dt0, facmax = 10.0;
+    int64_t acc = 0, rej = 0;
+    rhs(&m, y, k[0]);
+    while (t < t_end && acc + rej < max_steps) {
+        /* the step that reaches t_end (within a relative 1e-12 of h) ends on it */
+        const int last = t_end - t <= h * (1.0 + 1e-12);
+        const double hs = last ? t_end - t : h;
+        for (int s = 1; s < 7; ++s) {
+            for (int64_t i = 0; i < len; ++i) {
+                double a = 0.0;
+                for (int q = 0; q < s; ++q) a += DP_A[s][q] * k[q][i];
+                z[i] = y[i] + hs * a;
+            }
+            rhs(&m, z, k[s]);
+        }
+        /* z now holds the fifth-order solution (stage 7 uses the weights b) */
+        if (rtol <= 0.0) {
+            memcpy(y, z, sizeof(double) * len);
+            memcpy(k[0], k[6], sizeof(double) * len);
+            t = last ? t_end : t + hs;
+            ++acc;
+            continue;
+        }
+        double sum = 0.0;
+        for (int64_t i = 0; i < len; ++i) {
+            double e = 0.0;
+            for (int q = 0; q < 7; ++q) e += DP_E[q] * k[q][i];
+            e *= hs;
+            const double sc = atol + rtol * fmax(fabs(y[i]), fabs(z[i]));
+            sum += (e / sc) * (e / sc);
+        }
+        const double err = sqrt(sum / (double)len);
+        const double f = 0.9 * pow(err, -0.2);
+        if (err <= 1.0) {
+            memcpy(y, z, sizeof(double) * len);
+            memcpy(k[0], k[6], sizeof(double) * len);
+            t = last ? t_end : t + hs;
+            ++acc;
+            h = hs * fmin(facmax, fmax(0.2, f));
+            facmax = 10.0;
+        } else {
+            ++rej;
+            h = hs * fmax(0.2, fmin(1.0, f));
+            facmax = 1.0;
+        }
+    }
+    stats[0] = t;
+    stats[1] = (double)acc;
+    stats[2] = (double)rej;
+    stats[3] = h;
+    free(z);
+    for (int s = 0; s < 7; ++s) free(k[s]);
+    return ORC_OK;
+}

@@ -36,6 +36,9 @@ def lib():
         L.orc_run.restype = i32
         L.orc_run.argtypes = [i32, i32, i64, i64, i64, i64, i64, dp, dp, dp, dp, dp, i32,
                               dp, ctypes.c_double, i64, dp, i64, dp, i64]
+        L.orc_run_dopri.restype = i32
+        L.orc_run_dopri.argtypes = [i32, i32, i64, i64, i64, i64, i64, dp, dp, dp, dp, dp, dp,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
         L.orc_order_parameter.restype = ctypes.c_double
         L.orc_order_parameter.argtypes = [i32, i64, dp]
         _LIB = L
@@ -122,3 +125,18 @@ def run(net, y0, dt, steps, record_every=0, mv_start=None, reverse=False):
 def order_parameter(model, n, y):
     y = np.ascontiguousarray(y, dtype=np.float64)
     return lib().orc_order_parameter(int(model), int(n), _p(y))
+
+
+def run_dopri(net, y0, t_end, rtol, atol, dt0, max_steps=10 ** 7):
+    """Dormand-Prince 5(4) with step-size control (rtol <= 0: fixed steps of dt0);
+    returns (y, t reached, accepted steps, rejected steps, last proposed step)."""
+    y = np.array(y0, dtype=np.float64, copy=True).ravel()
+    assert y.size == net.nvars * net.n
+    st = np.zeros(4)
+    n1, n2, n3 = net.dims
+    rc = lib().orc_run_dopri(net.model, net.topo, net.n, net.radius, n1, n2, n3, _p(net.row_ptr), _p(net.col),
+                             _p(net.w), _p(net.params), _p(net.per_elem), _p(y), float(t_end), float(rtol),
+                             float(atol), float(dt0), int(max_steps), _p(st))
+    if rc != 0:
+        raise ValueError(f"oracle dopri run failed ({rc})")
+    return y, st[0], int(st[1]), int(st[2]), st[3]

@@ -785,3 +785,50 @@ def test_disk_dense_brute_force_inertia():
     ref = dense_rk4(inertia_dense(A, *prm), y0, 0.05, 30)
     yy, _, _ = O.run(O.disk(n1, P, prm, n2=n2, model=O.INERTIA), y0, 0.05, 30)
     assert np.max(np.abs(yy - ref)) / np.max(np.abs(ref)) < 1e-13
+
+
+# ------------------------------------------------ Dormand-Prince 5(4) stepping
+def test_dopri_fixed_step_is_fifth_order():
+    """Fixed steps (no control): the error of the inertia zero-coupling closed
+    form falls by ~2^5 per halving of the step."""
+    n, P = 20, 3
+    omega, m, eps = 0.7, 0.5, 0.9
+    phi0 = inputs.kuramoto_phases(31, n)
+    psi0 = inputs.uniform_range(32, inputs.TAG_MISC, n, -1.0, 1.0)
+    t = 4.0
+    w = omega / eps
+    decay = math.exp(-eps * t / m)
+    exact = np.concatenate([phi0 + w * t + (psi0 - w) * (m / eps) * (1 - decay), w + (psi0 - w) * decay])
+    errs = []
+    for steps in (20, 40, 80):
+        y, tr, acc, rej, _ = O.run_dopri(O.ring(O.INERTIA, n, P, inert(omega, 0.0, 1.0, m, eps)),
+                                         np.concatenate([phi0, psi0]), t, -1.0, 0.0, t / steps)
+        assert acc == steps and rej == 0 and tr == pytest.approx(t, abs=1e-12)
+        errs.append(np.max(np.abs(y - exact)))
+    assert 28 < errs[0] / errs[1] < 50 and 28 < errs[1] / errs[2] < 50
+
+
+def test_dopri_constant_field_is_exact():
+    """With zero coupling the Kuramoto field is the constant omega: every stage
+    and both embedded solutions are exact, so the error estimate is 0 and each
+    step is accepted with the largest growth factor."""
+    n, P = 30, 4
+    y0 = inputs.kuramoto_phases(33, n)
+    y, t, acc, rej, hlast = O.run_dopri(O.ring(O.KURAMOTO, n, P, kur(0.37, 0.0, 1.0)), y0, 10.0, 1e-9, 1e-12, 0.01)
+    assert np.max(np.abs(y - (y0 + 0.37 * 10.0))) < 1e-12
+    assert rej == 0 and t == pytest.approx(10.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("rtol", [1e-6, 1e-9])
+def test_dopri_tolerance_proportionality_against_library(rtol):
+    """Adaptive runs of a coupled FHN ring agree with scipy's DOP853 at a tight
+    tolerance to within a small multiple of the requested rtol."""
+    n, P = 40, 6
+    prm = np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
+    y0 = inputs.fhn_circle(34, n)
+    net = O.ring(O.FHN, n, P, prm)
+    y, t, acc, rej, _ = O.run_dopri(net, y0, 2.0, rtol, rtol * 1e-3, 1e-3)
+    sol = solve_ivp(lambda _t, yy: O.rhs(net, yy), (0.0, 2.0), y0, method="DOP853", rtol=1e-13, atol=1e-13)
+    ref = sol.y[:, -1]
+    assert t == pytest.approx(2.0, abs=1e-12) and acc > 0
+    assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 100 * rtol
