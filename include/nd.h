@@ -187,6 +187,30 @@ typedef struct nd_kernel_config {
     int32_t tile_z; /* cube: planes per work item */
 } nd_kernel_config;
 
+/* Adaptive stepping: Dormand-Prince 5(4), the paper's default solver (Sec. III.A), with the
+ * usual step-size control (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4):
+ *   err = sqrt(mean_i ((y5_i - y4_i) / (atol + rtol max(|y_i|, |y5_i|)))^2), accept when
+ *   err <= 1, new h = h min(facmax, max(0.2, 0.9 err^(-1/5))), facmax = 10 (1 right after a
+ *   rejection); the step that reaches t_end (within a relative 1e-12 of h) ends on it.
+ * rtol <= 0 takes fixed steps of dt0 (no control).  The fifth-order solution propagates.
+ * Each of the `count` networks is integrated from its current state over [0, t_end[i]]
+ * starting with step dt0[i], entirely on the device, one workgroup per network: each
+ * network controls its own step.  Supported: FP64 rings (ND_RING) of at most 1024
+ * elements of the Kuramoto, Kuramoto-with-inertia or FHN model, one model per call
+ * (ND_ERR_UNSUPPORTED otherwise).  At most max_steps step attempts per network.  The state
+ * is advanced in place (read it with nd_get_state); no observables are recorded.  Blocks
+ * until done; stats[i] receives the time reached, the accepted and rejected steps and the
+ * step proposed next. */
+typedef struct nd_adaptive_stats {
+    double t;          /* time reached (t_end unless max_steps ran out) */
+    int64_t accepted;  /* accepted steps */
+    int64_t rejected;  /* rejected step attempts */
+    double h_next;     /* step size proposed for a continuation */
+} nd_adaptive_stats;
+
+nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end, const double* dt0, double rtol,
+                          double atol, int64_t max_steps, nd_adaptive_stats* stats, void* hip_stream);
+
 nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
 nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);
 

@@ -1,0 +1,249 @@
+// Dormand-Prince 5(4) with step-size control for rings held by one workgroup,
+// entirely on the device.
+//
+// The paper's default solver is the adaptive embedded pair of Dormand and
+// Prince (Sec. III.A).  Here every ring of up to 1024 elements is integrated
+// by one workgroup from t = 0 to its own t_end: the state and the seven stage
+// slopes stay in registers, each stage's window sums come from LDS prefix sums
+// of the mapped stage values (as in the resident RK4 kernel), and the step
+// control is the usual one (Hairer, Norsett & Wanner, Solving ODEs I, II.4):
+//   err = sqrt(mean_i ((y5_i - y4_i) / (atol + rtol max(|y_i|, |y5_i|)))^2),
+//   accept when err <= 1, new h = h min(facmax, max(0.2, 0.9 err^(-1/5))),
+//   facmax = 10, or 1 right after a rejection; the step that reaches t_end
+//   (to within a relative 1e-12 of h) ends on it; rtol <= 0 means fixed steps.
+// The fifth-order solution propagates, and the last stage is the first stage
+// of the next step.  The error norm is one fixed-order block reduction, so the
+// accept/reject decisions are the same in every run.  Each ring decides for
+// itself: a batch of rings with different parameters and horizons runs in one
+// launch without host round trips.
+#include <cmath>
+
+#include "models.h"
+#include "runtime.h"
+
+namespace nd {
+
+namespace {
+constexpr int kDpBS = 512, kDpEPT = 2, kDpCap = kDpBS * kDpEPT;  // ring capacity 1024
+
+__device__ __constant__ double kDpA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+// fifth- minus fourth-order weights
+__device__ __constant__ double kDpE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
+                                           22.0 / 525, -1.0 / 40};
+}  // namespace
+
+template <int MODEL>
+__global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict__ D,
+                                                      const double* __restrict__ t_end, double rtol, double atol,
+                                                      int64_t max_steps, double* __restrict__ stats) {
+    using M = RingModel<MODEL, double>;
+    constexpr int V = M::V, T = kDpCap, EPT = kDpEPT, NW = kDpBS / kWave;
+    __shared__ double pf[2 * T];  // inclusive prefix sums of the two map components
+    __shared__ double lds[8 * NW];
+    const int tid = threadIdx.x;
+    const NetDesc& d = D[blockIdx.x];
+    const int n = (int)d.n, P = (int)d.P;
+    ND_GLOBAL double* y_g = gp(d.y[d.ypar]);
+    double y[EPT][V], k[7][EPT][V];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = tid * EPT + e;
+#pragma unroll
+        for (int v = 0; v < V; ++v) y[e][v] = i < n ? y_g[(int64_t)v * n + i] : 0.0;
+    }
+    // slopes of stage value z: map, block prefix sums, window sums, RHS
+    auto slopes = [&](const double (&z)[EPT][V], double (&kout)[EPT][V]) {
+        double2 x[EPT];
+        double tot[2] = {0.0, 0.0}, none[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid * EPT + e;
+            x[e] = M::map(z[e]);
+            if (i >= n) x[e] = make_double2(0.0, 0.0);
+            tot[0] += x[e].x;
+            tot[1] += x[e].y;
+            pf[tid * EPT + e] = tot[0];
+            pf[T + tid * EPT + e] = tot[1];
+        }
+        block_sum_and_exscan<kDpBS, 2, 2>(none, tot, lds);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            pf[tid * EPT + e] += tot[0];
+            pf[T + tid * EPT + e] += tot[1];
+        }
+        lds_barrier();
+        const double t0 = pf[n - 1], t1 = pf[T + n - 1];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid * EPT + e;
+#pragma unroll
+            for (int v = 0; v < V; ++v) kout[e][v] = 0.0;
+            if (i < n) {
+                const int lo = i - P, hi = i + P + 1;
+                auto pre = [&](int q, int c) { return q == 0 ? 0.0 : pf[c * T + q - 1]; };
+                double w0, w1;
+                if (lo < 0) {
+                    w0 = pre(hi, 0) + (t0 - pre(lo + n, 0));
+                    w1 = pre(hi, 1) + (t1 - pre(lo + n, 1));
+                } else if (hi > n) {
+                    w0 = (t0 - pre(lo, 0)) + pre(hi - n, 0);
+                    w1 = (t1 - pre(lo, 1)) + pre(hi - n, 1);
+                } else {
+                    w0 = pre(hi, 0) - pre(lo, 0);
+                    w1 = pre(hi, 1) - pre(lo, 1);
+                }
+                const double2 W = make_double2(w0 - x[e].x, w1 - x[e].y);
+                M::rhs(d, z[e], x[e], W, kout[e]);
+            }
+        }
+        lds_barrier();  // pf is rewritten by the next stage
+    };
+    slopes(y, k[0]);
+    const double tend = t_end[blockIdx.x];
+    double t = 0.0, h = d.dt, facmax = 10.0;
+    int64_t acc = 0, rej = 0;
+    // every wave leaves the loop together: t, h and the counters are uniform
+    while (t < tend && acc + rej < max_steps) {
+        const bool last = tend - t <= h * (1.0 + 1e-12);
+        const double hs = last ? tend - t : h;
+        double z[EPT][V];
+#pragma unroll
+        for (int s = 1; s < 7; ++s) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int q = 0; q < s; ++q) a += kDpA[s][q] * k[q][e][v];
+                    z[e][v] = y[e][v] + hs * a;
+                }
+            slopes(z, k[s]);
+        }
+        // z is the fifth-order solution (stage 7 uses the weights b)
+        bool accept = true;
+        double f = 1.0;
+        if (rtol > 0.0) {
+            double sum[1] = {0.0};
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                if (tid * EPT + e >= n) continue;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    double er = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) er += kDpE[q] * k[q][e][v];
+                    er *= hs;
+                    const double sc = atol + rtol * fmax(fabs(y[e][v]), fabs(z[e][v]));
+                    sum[0] += (er / sc) * (er / sc);
+                }
+            }
+            block_sum<kDpBS, 1>(sum, lds);
+            const double err = sqrt(sum[0] / (double)(V * n));
+            f = 0.9 * pow(err, -0.2);
+            accept = err <= 1.0;
+        }
+        if (accept) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    y[e][v] = z[e][v];
+                    k[0][e][v] = k[6][e][v];
+                }
+            t = last ? tend : t + hs;
+            ++acc;
+            if (rtol > 0.0) h = hs * fmin(facmax, fmax(0.2, f));
+            facmax = 10.0;
+        } else {
+            ++rej;
+            h = hs * fmax(0.2, fmin(1.0, f));
+            facmax = 1.0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = tid * EPT + e;
+        if (i < n) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) y_g[(int64_t)v * n + i] = y[e][v];
+        }
+    }
+    if (tid == 0) {
+        ND_GLOBAL double* st = gp(stats) + 4 * blockIdx.x;
+        st[0] = t;
+        st[1] = (double)acc;
+        st[2] = (double)rej;
+        st[3] = h;
+    }
+}
+
+}  // namespace nd
+
+using namespace nd;
+
+extern "C" nd_status nd_run_adaptive(const nd_handle* hs, int32_t count, const double* t_end, const double* dt0,
+                                     double rtol, double atol, int64_t max_steps, nd_adaptive_stats* stats,
+                                     void* stream) {
+    if (!hs || !t_end || !dt0 || !stats || count < 0) return fail(ND_ERR_INVALID_ARG, "bad adaptive-run arguments");
+    if (!std::isfinite(rtol) || !std::isfinite(atol) || atol < 0.0 || (rtol > 0.0 && atol == 0.0))
+        return fail(ND_ERR_INVALID_ARG, "rtol must be finite; atol finite, and > 0 when rtol > 0");
+    if (max_steps < 0) return fail(ND_ERR_INVALID_ARG, "max_steps must be >= 0");
+    if (count == 0) return ND_OK;
+    int model = -1;
+    std::vector<NetDesc> descs(count);
+    for (int i = 0; i < count; ++i) {
+        Net* n = reinterpret_cast<Net*>(hs[i]);
+        if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle at %d", i);
+        if (n->prob.topo != ND_RING || n->prob.n > kDpCap || n->prob.precision != ND_FP64 || n->prob.model == ND_HH)
+            return fail(ND_ERR_UNSUPPORTED, "adaptive stepping runs FP64 rings of at most %d elements", kDpCap);
+        if (model >= 0 && n->prob.model != model)
+            return fail(ND_ERR_INVALID_ARG, "one adaptive batch holds one model");
+        model = n->prob.model;
+        if (!(t_end[i] >= 0.0) || !std::isfinite(t_end[i]) || !(dt0[i] > 0.0) || !std::isfinite(dt0[i]))
+            return fail(ND_ERR_INVALID_ARG, "t_end must be finite and >= 0, dt0 finite and > 0 (network %d)", i);
+        descs[i] = n->run_desc(dt0[i], 0);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    void* buf = nullptr;
+    const size_t bd = (size_t)count * sizeof(NetDesc), bt = (size_t)count * 8, bs = (size_t)count * 32;
+    hipError_t e = hipMallocAsync(&buf, bd + bt + bs, st);
+    if (e != hipSuccess) return hip_fail(e, "adaptive scratch");
+    NetDesc* d_desc = (NetDesc*)buf;
+    double* d_tend = (double*)((char*)buf + bd);
+    double* d_stats = (double*)((char*)buf + bd + bt);
+    std::vector<double> h_stats((size_t)count * 4);
+    if ((e = hipMemcpyAsync(d_desc, descs.data(), bd, hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(d_tend, t_end, bt, hipMemcpyHostToDevice, st)) == hipSuccess) {
+        if (model == ND_KURAMOTO)
+            hipLaunchKernelGGL(k_ring_dopri<ND_KURAMOTO>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol,
+                               max_steps, d_stats);
+        else if (model == ND_FHN)
+            hipLaunchKernelGGL(k_ring_dopri<ND_FHN>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol,
+                               max_steps, d_stats);
+        else
+            hipLaunchKernelGGL(k_ring_dopri<ND_KURAMOTO_INERTIA>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend,
+                               rtol, atol, max_steps, d_stats);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h_stats.data(), d_stats, bs, hipMemcpyDeviceToHost, st);
+    }
+    const hipError_t ef = hipFreeAsync(buf, st);
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "adaptive run");
+    if (ef != hipSuccess) return hip_fail(ef, "adaptive scratch free");
+    if (es != hipSuccess) return hip_fail(es, "adaptive run");
+    for (int i = 0; i < count; ++i) {
+        stats[i].t = h_stats[4 * i];
+        stats[i].accepted = (int64_t)h_stats[4 * i + 1];
+        stats[i].rejected = (int64_t)h_stats[4 * i + 2];
+        stats[i].h_next = h_stats[4 * i + 3];
+    }
+    return ND_OK;
+}

@@ -42,6 +42,10 @@ class nd_kernel_config(ctypes.Structure):
                 ("tile_z", _c_i32)]
 
 
+class nd_adaptive_stats(ctypes.Structure):
+    _fields_ = [("t", _c_dbl), ("accepted", _c_i64), ("rejected", _c_i64), ("h_next", _c_dbl)]
+
+
 class nd_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _c_i64), ("max_slots", _c_i32), ("chunk_steps", _c_i32), ("grid", _c_i32),
                 ("reserved", _c_i32)]
@@ -80,6 +84,8 @@ _sig = {
     "nd_set_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_run": [_c_vp, _c_dbl, _c_i64, _P(nd_observe), _c_vp],
     "nd_run_batch": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_i64), _P(nd_observe), _c_vp],
+    "nd_run_adaptive": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _P(nd_adaptive_stats),
+                        _c_vp],
     "nd_get_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_get_observables": [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_destroy": [_c_vp],
@@ -206,6 +212,19 @@ def nd_run_batch(handles, dts, steps, obs=None, stream=None):
     ss = (_c_i64 * k)(*[int(x) for x in steps])
     oo = (nd_observe * k)(*obs) if obs is not None else None
     _check(_lib.nd_run_batch(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch")
+
+
+def nd_run_adaptive(handles, t_end, dt0, rtol, atol, max_steps=10 ** 7, stream=None):
+    """Dormand-Prince 5(4) with step-size control on each network (FP64 rings of at
+    most 1024 elements); returns one nd_adaptive_stats per network."""
+    k = len(handles)
+    hs = (_c_vp * k)(*handles)
+    te = (_c_dbl * k)(*[float(x) for x in t_end])
+    d0 = (_c_dbl * k)(*[float(x) for x in dt0])
+    st = (nd_adaptive_stats * k)()
+    _check(_lib.nd_run_adaptive(hs, k, te, d0, float(rtol), float(atol), int(max_steps), st, _stream(stream)),
+           "nd_run_adaptive")
+    return list(st)
 
 
 def nd_get_observables(h, R=None, mean_vel=None, on_device=None, stream=None):
