@@ -24,6 +24,11 @@ Other workloads (one JSON line each, same fields):
   --workload ball      the same state with the paper's ball neighbourhood of
                        radius --radius (2: 33 links, the default; 6: 925 links),
                        centre included
+  --workload adaptive  Dormand-Prince 5(4) with step-size control on the device:
+                       4096 Kuramoto rings N = 1024, P = 256, alpha = 1.46,
+                       omega = 0, integrated over t = 100 at rtol = 1e-8,
+                       atol = 1e-10, each ring controlling its own step from
+                       h0 = 1e-3; value counts accepted steps
   --workload serve     continuous-batching server fed by seeded Poisson arrivals of
                        Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
                        [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
@@ -66,6 +71,7 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "inertia": (1, 1000, 0.05, 100),
     "ball": (1, 1000, 0.05, 100),
     "serve": (24, 0, 0.01, 0),
+    "adaptive": (4096, 0, 0.0, 1024),
 }
 DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3,
               "ball": 100 ** 3}
@@ -436,6 +442,73 @@ def main_serve(nd, torch, args, stream):
     print(json.dumps(out), flush=True)
 
 
+def main_adaptive(nd, torch, args, stream):
+    """One launch integrates every ring to t_end with its own step control."""
+    from paper_2410_19075_amd import inputs
+    n, P, t_end, rtol, atol = args.n, args.n // 4, 100.0, 1e-8, 1e-10
+    hs = []
+    for b in range(args.batch):
+        h = nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, [0.0, 1.0, 1.46], radius=P))
+        hs.append(h)
+    y0s = [torch.from_numpy(inputs.kuramoto_phases(1000 + b, n)).cuda() for b in range(args.batch)]
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def one():
+        for h, y0 in zip(hs, y0s):
+            nd.nd_set_state(h, y0, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        st = nd.nd_run_adaptive(hs, [t_end] * len(hs), [1e-3] * len(hs), rtol, atol, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3, st
+
+    for _ in range(args.warmup):
+        one()
+    times, ev_total, acc, rej = [], 0.0, 0, 0
+    for _ in range(args.steps):
+        dt_s, ev_s, st = one()
+        times.append(dt_s)
+        ev_total += ev_s
+        acc += sum(s.accepted for s in st)
+        rej += sum(s.rejected for s in st)
+    wall = sum(times)
+    value = acc * n / wall
+    # algorithmic FP64 flops per element and accepted step: 7 stages of the resident
+    # kernel's per-stage work (KURAMOTO_RESIDENT_FLOPS / 4 each, sin/cos included)
+    # plus the stage combinations (2 flops per coefficient, 27 + 7 coefficients)
+    flops = acc * n * (7 * KURAMOTO_RESIDENT_FLOPS / 4 + 2 * 34)
+    achieved = flops / ev_total / 1e12
+    out = {"metric": "oscillator-steps/s", "value": value, "unit": "oscillator-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"Dormand-Prince 5(4), {args.batch} Kuramoto rings N={n} P={P} alpha=1.46, "
+                                  f"t=0..{t_end}, rtol={rtol} atol={atol}, per-ring step control",
+                      "global_batch": args.batch, "parallelism": "single-gpu"},
+           "accepted_steps": acc, "rejected_steps": rej,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_ring_dopri<Kuramoto>",
+                        "avg_launch_us": ev_total / args.steps * 1e6}}
+    for h in hs:
+        nd.nd_destroy(h)
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.lib()
+        y0 = inputs.kuramoto_phases(1000, n)
+        t0 = time.perf_counter()
+        _, _, oacc, orej, _ = O.run_dopri(O.ring(O.KURAMOTO, n, P, [0.0, 1.0, 1.46]), y0, t_end, rtol, atol, 1e-3)
+        sec = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": oacc * n / sec, "unit": "oscillator-steps/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"one Kuramoto ring N={n} P={P}, Dormand-Prince 5(4) to t={t_end}, "
+                                         f"{oacc} accepted / {orej} rejected steps, FP64, {sec:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -466,6 +539,9 @@ def main():
         return
     if args.workload == "serve":
         main_serve(nd, torch, args, stream)
+        return
+    if args.workload == "adaptive":
+        main_adaptive(nd, torch, args, stream)
         return
     wl = Workload(args, nd)
     osc_per_step = args.batch * wl.n * args.horizon
