@@ -41,6 +41,12 @@
  *       eps du_i/dt = u_i - u_i^3/3 - v_i + k * sum_j ( cos phi du_j + sin phi dv_j)
  *           dv_i/dt = u_i + a         + k * sum_j (-sin phi du_j + cos phi dv_j)
  *     with k = sigma / (2P).
+ *   The Kuramoto models and FitzHugh-Nagumo also run on an arbitrary binary
+ *     coupling matrix given by rows (topology LINKS: row i lists the
+ *     presynaptic elements j with L_ij = 1, Sec. III.B), each sum divided by
+ *     the row's own link count Omega_i as Alg. 1 divides by its link count; a
+ *     row without links contributes no coupling.  The links are taken in the
+ *     order the row lists them.
  *   Hodgkin-Huxley, Eq. (1) specialised to the squid axon (Na, K, leak) with
  *     an instantaneous sigmoidal synapse S(V) on a directed graph stored as
  *     CSR by target (sources ascending):
@@ -63,7 +69,7 @@
 #define ORC_ENOMEM -2
 
 enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2, ORC_INERTIA = 3 };
-enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3, ORC_DISK = 4 };
+enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3, ORC_DISK = 4, ORC_LINKS = 5 };
 
 typedef struct {
     int model, topo;
@@ -252,6 +258,62 @@ static void rhs_fhn_ring(const orc_net* m, const double* z, double* f) {
     }
 }
 
+/* ------------------------------------------------ binary coupling matrix rows */
+/* Kuramoto coupling of element i over the links of its row:
+ * (1/Omega_i) sum_{j in row i} sin(phi_j - phi_i - alpha), 0 for an empty row. */
+static double kuramoto_links_coupling(const orc_net* m, const double* z, int64_t i, double alpha) {
+    const int64_t b = m->row_ptr[i], e = m->row_ptr[i + 1];
+    if (e == b) return 0.0;
+    double s = 0.0;
+    for (int64_t t = 0; t < e - b; ++t) {
+        const int64_t q = m->reverse ? (e - 1 - t) : (b + t);
+        s += sin(z[m->col[q]] - z[i] - alpha);
+    }
+    return s * (1.0 / (double)(e - b));
+}
+
+static void rhs_kuramoto_links(const orc_net* m, const double* z, double* f) {
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m->n; ++i) f[i] = omega + mu * kuramoto_links_coupling(m, z, i, alpha);
+}
+
+static void rhs_inertia_links(const orc_net* m, const double* z, double* f) {
+    const int64_t n = m->n;
+    const double omega = m->prm[0], mu = m->prm[1], alpha = m->prm[2], mass = m->prm[3], eps = m->prm[4];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double psi = z[n + i];
+        f[i] = psi;
+        f[n + i] = (omega - eps * psi + mu * kuramoto_links_coupling(m, z, i, alpha)) / mass;
+    }
+}
+
+/* FitzHugh-Nagumo with the rotational coupling averaged over the row's links,
+ * k = sigma / Omega_i (no coupling for an empty row). */
+static void rhs_fhn_links(const orc_net* m, const double* z, double* f) {
+    const int64_t n = m->n;
+    const double eps = m->prm[0], a = m->prm[1], sigma = m->prm[2], phi = m->prm[3];
+    const double buu = cos(phi), buv = sin(phi), bvu = -sin(phi), bvv = cos(phi);
+    const double* u = z;
+    const double* v = z + n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t b = m->row_ptr[i], e = m->row_ptr[i + 1];
+        double cu = 0.0, cv = 0.0;
+        for (int64_t t = 0; t < e - b; ++t) {
+            const int64_t q = m->reverse ? (e - 1 - t) : (b + t);
+            const int64_t j = m->col[q];
+            double du = u[j] - u[i], dv = v[j] - v[i];
+            cu += buu * du + buv * dv;
+            cv += bvu * du + bvv * dv;
+        }
+        const double kappa = e > b ? sigma / (double)(e - b) : 0.0;
+        f[i] = (u[i] - u[i] * u[i] * u[i] / 3.0 - v[i] + kappa * cu) / eps;
+        f[n + i] = u[i] + a + kappa * cv;
+    }
+}
+
 /* ---------------------------------------------------------- Hodgkin-Huxley */
 /* x / (1 - exp(-x)), the removable singularity at x = 0 taken by its series */
 static double xoverexpm1(double x) {
@@ -304,6 +366,9 @@ static int rhs(const orc_net* m, const double* z, double* f) {
     else if (m->model == ORC_INERTIA && (m->topo == ORC_BALL || m->topo == ORC_DISK)) rhs_inertia_ball(m, z, f);
     else if (m->model == ORC_FHN && m->topo == ORC_RING) rhs_fhn_ring(m, z, f);
     else if (m->model == ORC_HH && m->topo == ORC_CSR) rhs_hh_csr(m, z, f);
+    else if (m->model == ORC_KURAMOTO && m->topo == ORC_LINKS) rhs_kuramoto_links(m, z, f);
+    else if (m->model == ORC_INERTIA && m->topo == ORC_LINKS) rhs_inertia_links(m, z, f);
+    else if (m->model == ORC_FHN && m->topo == ORC_LINKS) rhs_fhn_links(m, z, f);
     else return ORC_EINVAL;
     return ORC_OK;
 }
@@ -322,6 +387,13 @@ static int validate(const orc_net* m) {
         if (m->n1 * m->n2 * m->n3 != m->n) return ORC_EINVAL;
     } else if (m->topo == ORC_CSR) {
         if (!m->row_ptr || !m->col || !m->w || !m->per_elem) return ORC_EINVAL;
+    } else if (m->topo == ORC_LINKS) {
+        if (!m->row_ptr || m->row_ptr[0] != 0) return ORC_EINVAL;
+        for (int64_t i = 0; i < m->n; ++i) {
+            if (m->row_ptr[i + 1] < m->row_ptr[i]) return ORC_EINVAL;
+            for (int64_t q = m->row_ptr[i]; q < m->row_ptr[i + 1]; ++q)
+                if (m->col[q] < 0 || m->col[q] >= m->n) return ORC_EINVAL;
+        }
     }
     return ORC_OK;
 }

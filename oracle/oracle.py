@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 KURAMOTO, FHN, HH, INERTIA = 0, 1, 2, 3
-RING, CUBE, CSR, BALL, DISK = 0, 1, 2, 3, 4
+RING, CUBE, CSR, BALL, DISK, LINKS = 0, 1, 2, 3, 4, 5
 NVARS = {KURAMOTO: 1, FHN: 2, HH: 4, INERTIA: 2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -93,6 +93,12 @@ def disk(n1, P, params, n2=None, model=KURAMOTO):
     """Periodic n1 x n2 plane, neighbours = lattice points within distance P, centre included."""
     n2 = n1 if n2 is None else n2
     return Net(model, DISK, n1 * n2, params, radius=P, dims=(n1, n2, 1))
+
+
+def links(model, n, row_ptr, col, params):
+    """Arbitrary binary coupling matrix by rows: row i lists the j with L_ij = 1
+    (summed in the listed order, divided by the row's link count)."""
+    return Net(model, LINKS, n, params, row_ptr=row_ptr, col=col)
 
 
 def csr(n, row_ptr, col, w, params, i_app):

@@ -21,7 +21,7 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 # stream tags: one independent stream per quantity
-TAG_PHASE, TAG_FHN, TAG_PATCH, TAG_HH_STATE, TAG_HH_IAPP, TAG_GRAPH, TAG_WEIGHT, TAG_MISC = range(1, 9)
+TAG_PHASE, TAG_FHN, TAG_PATCH, TAG_HH_STATE, TAG_HH_IAPP, TAG_GRAPH, TAG_WEIGHT, TAG_MISC, TAG_LINKS = range(1, 10)
 
 
 def _mix(z):
@@ -143,3 +143,70 @@ def random_out_graph(seed, n, out_degree, wmax=0.1):
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
     return row_ptr, col, w
+
+
+# ------------------------------------------------- binary coupling matrices
+# Rows of a binary coupling matrix L (row i lists the j with L_ij = 1) as CSR:
+# row_ptr int64[n+1], col int32 ascending within each row.
+def _csr_from_mask(mask):
+    n = mask.shape[0]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=row_ptr[1:])
+    col = np.nonzero(mask)[1].astype(np.int32)
+    return row_ptr, col
+
+
+def random_links(seed, n, density):
+    """Every entry L_ij (self links included) set independently with
+    probability `density`; empty rows can occur.  For small n (n^2 draws)."""
+    mask = uniform(seed, TAG_LINKS, n * n).reshape(n, n) < density
+    return _csr_from_mask(mask)
+
+
+def ring_links(n, P):
+    """Ring: row i holds i-P..i-1 and i+1..i+P (mod n)."""
+    off = np.concatenate([np.arange(-P, 0), np.arange(1, P + 1)])
+    j = (np.arange(n)[:, None] + off[None, :]) % n
+    col = np.sort(j, axis=1).astype(np.int32).ravel()
+    return np.arange(0, n * 2 * P + 1, 2 * P, dtype=np.int64), col
+
+
+def small_world_links(seed, n, P, shortcuts):
+    """Ring of radius P plus `shortcuts` extra links placed on random rows to
+    random sources (a row may get several; duplicates of existing links and
+    self links are skipped), so most rows share the ring's structure and a few
+    differ."""
+    off = np.concatenate([np.arange(-P, 0), np.arange(1, P + 1)])
+    rows = [set(((i + off) % n).tolist()) for i in range(n)]
+    u = uniform(seed, TAG_LINKS, 2 * shortcuts)
+    for s_ in range(shortcuts):
+        i = int(u[2 * s_] * n)
+        j = int(u[2 * s_ + 1] * n)
+        if j != i:
+            rows[i].add(j)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([j for r in rows for j in sorted(r)], dtype=np.int32)
+    return row_ptr, col
+
+
+def lattice_ball_links(n1, n2, n3, P, include_self=True):
+    """Periodic n1 x n2 x n3 lattice (index x + n1*y + n1*n2*z), row i holding
+    every lattice point within Euclidean distance P of element i (the element
+    itself when include_self).  n3 = 1 gives the plane with the disk."""
+    r = np.arange(-P, P + 1)
+    dz_r = r if n3 > 1 else np.array([0])
+    DX, DY, DZ = np.meshgrid(r, r, dz_r, indexing="ij")
+    keep = DX ** 2 + DY ** 2 + DZ ** 2 <= P * P
+    if not include_self:
+        keep &= (DX != 0) | (DY != 0) | (DZ != 0)
+    dx, dy, dz = DX[keep], DY[keep], DZ[keep]
+    i = np.arange(n1 * n2 * n3, dtype=np.int64)
+    x, y, z = i % n1, (i // n1) % n2, i // (n1 * n2)
+    L = dx.size
+    col = np.empty((i.size, L), dtype=np.int64)
+    for q in range(L):
+        col[:, q] = (x + dx[q]) % n1 + n1 * ((y + dy[q]) % n2) + n1 * n2 * ((z + dz[q]) % n3)
+    col.sort(axis=1)
+    row_ptr = np.arange(0, i.size * L + 1, L, dtype=np.int64)
+    return row_ptr, col.astype(np.int32).ravel()

@@ -832,3 +832,158 @@ def test_dopri_tolerance_proportionality_against_library(rtol):
     ref = sol.y[:, -1]
     assert t == pytest.approx(2.0, abs=1e-12) and acc > 0
     assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 100 * rtol
+
+
+# ------------------------------------------- compressed coupling matrix (Alg. 2)
+from oracle import compress as CM  # noqa: E402
+
+
+def test_compress_full_mesh_is_all_ones_and_one_empty_entry():
+    """Sec. III.B: a full mesh compresses to a common vector with every bit set
+    and a single difference-table entry with no bit set."""
+    n = 12
+    rp = np.arange(0, n * n + 1, n, dtype=np.int64)
+    col = np.tile(np.arange(n, dtype=np.int32), n)
+    V, D, C = CM.compress(n, rp, col)
+    assert V == list(range(n)) and D == [[]] and np.all(C == 0)
+    # without self links every row shifts onto row 0 as well
+    col = np.array([j for i in range(n) for j in range(n) if j != i], dtype=np.int32)
+    rp = np.arange(0, n * (n - 1) + 1, n - 1, dtype=np.int64)
+    V, D, C = CM.compress(n, rp, col)
+    assert V == list(range(1, n)) and D == [[]] and np.all(C == 0)
+
+
+@pytest.mark.parametrize("n,P", [(10, 1), (33, 7), (64, 31)])
+def test_compress_ring_has_one_entry(n, P):
+    """A ring is translation invariant: one (empty) entry, V = row 0."""
+    V, D, C = CM.compress(n, *inputs.ring_links(n, P))
+    assert V == list(range(1, P + 1)) + list(range(n - P, n))
+    assert D == [[]] and np.all(C == 0)
+
+
+@pytest.mark.parametrize("density", [0.0, 0.05, 0.3, 0.9, 1.0])
+def test_compress_extract_round_trip_random(density):
+    """EXTRACT inverts COMPRESS on every row of arbitrary matrices (brute force
+    over all rows; self links and empty rows included)."""
+    n = 37
+    rp, col = inputs.random_links(int(100 * density) + 3, n, density)
+    V, D, C = CM.compress(n, rp, col)
+    rp2, col2 = CM.extract_all(n, V, D, C)
+    assert np.array_equal(rp, rp2) and np.array_equal(col, col2)
+    assert len(D) == len({tuple(d) for d in D}) <= n and D[0] == []
+
+
+def test_compress_small_world_round_trip_and_entries():
+    """A ring with a few shortcuts: the rows without a shortcut share the empty
+    entry, every row with shortcuts has an entry holding exactly its shortcuts
+    (shifted onto row 0's frame)."""
+    n, P = 200, 5
+    rp, col = inputs.small_world_links(11, n, P, 12)
+    V, D, C = CM.compress(n, rp, col)
+    rp2, col2 = CM.extract_all(n, V, D, C)
+    assert np.array_equal(rp, rp2) and np.array_equal(col, col2)
+    ring_rows = CM.rows_of(n, *inputs.ring_links(n, P))
+    rows = CM.rows_of(n, rp, col)
+    for i in range(n):
+        extra = rows[i] - ring_rows[i]
+        assert sorted((j - i) % n for j in extra) == D[C[i]]
+
+
+def boundary_pattern(i, n1, n2, n3, P):
+    """Which coordinates of element i lie within P of a lattice face; with a
+    periodic flattened index, a wrap in z shifts by n1*n2*n3 = n (a multiple of
+    n), a wrap in y (on a 3D lattice) or x does not."""
+    x, y = i % n1, (i // n1) % n2
+    px = x if x < P else (x - n1 if x >= n1 - P else None)
+    py = None if n3 == 1 else (y if y < P else (y - n2 if y >= n2 - P else None))
+    return px, py
+
+
+@pytest.mark.parametrize("dims,P", [((9, 8, 7), 2), ((11, 10, 5), 1), ((13, 9, 1), 3), ((7, 7, 7), 3)])
+def test_compress_lattice_entries_are_boundary_patterns(dims, P):
+    """On the flattened periodic lattice with the ball (disk) neighbourhood two
+    rows share an entry exactly when they share a boundary pattern: (2P+1)^2
+    entries in 3D, 2P+1 on the plane."""
+    n1, n2, n3 = dims
+    n = n1 * n2 * n3
+    V, D, C = CM.compress(n, *inputs.lattice_ball_links(n1, n2, n3, P))
+    pats = [boundary_pattern(i, n1, n2, n3, P) for i in range(n)]
+    assert len(D) == len(set(pats)) == ((2 * P + 1) ** 2 if n3 > 1 else 2 * P + 1)
+    first = {}
+    for i, p in enumerate(pats):
+        assert first.setdefault(p, C[i]) == C[i]
+
+
+def test_links_rhs_reduces_to_the_structured_topologies():
+    """Given the rows of a ring, a ball or a disk, the row-list RHS equals the
+    oracle's ring / ball / disk RHS (pinned above) up to summation order."""
+    prm = kur(0.2, 1.1, 0.9)
+    n, P = 57, 9
+    z = inputs.kuramoto_phases(5, n)
+    a = O.rhs(O.links(O.KURAMOTO, n, *inputs.ring_links(n, P), prm), z)
+    assert np.max(np.abs(a - O.rhs(O.ring(O.KURAMOTO, n, P, prm), z))) < 1e-14
+    dims, P = (9, 8, 7), 2
+    n = 9 * 8 * 7
+    z = inputs.kuramoto_phases(6, n)
+    a = O.rhs(O.links(O.KURAMOTO, n, *inputs.lattice_ball_links(*dims, P), prm), z)
+    assert np.max(np.abs(a - O.rhs(O.ball(9, P, prm, n2=8, n3=7), z))) < 1e-14
+    n = 13 * 11
+    z = inputs.kuramoto_phases(7, n)
+    a = O.rhs(O.links(O.KURAMOTO, n, *inputs.lattice_ball_links(13, 11, 1, 3), prm), z)
+    assert np.max(np.abs(a - O.rhs(O.disk(13, 3, prm, n2=11), z))) < 1e-14
+    fhn = np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
+    n, P = 40, 13
+    z = inputs.fhn_circle(8, n)
+    a = O.rhs(O.links(O.FHN, n, *inputs.ring_links(n, P), fhn), z)
+    b = O.rhs(O.ring(O.FHN, n, P, fhn), z)
+    assert np.max(np.abs(a - b)) / np.max(np.abs(b)) < 1e-14
+
+
+def links_dense(A, model, prm):
+    """Dense formulation with per-row link counts (an empty row: no coupling)."""
+    n = A.shape[0]
+    L = A.sum(axis=1)
+    Linv = np.where(L > 0, 1.0 / np.maximum(L, 1), 0.0)
+    if model == O.FHN:
+        eps, a, sigma, phi = prm
+        B = np.array([[math.cos(phi), math.sin(phi)], [-math.sin(phi), math.cos(phi)]])
+
+        def F(s):
+            u, v = s[:n], s[n:]
+            Du, Dv = A @ u - L * u, A @ v - L * v
+            cu = sigma * Linv * (B[0, 0] * Du + B[0, 1] * Dv)
+            cv = sigma * Linv * (B[1, 0] * Du + B[1, 1] * Dv)
+            return np.concatenate([(u - u ** 3 / 3 - v + cu) / eps, u + a + cv])
+        return F
+    omega, mu, alpha = prm[:3]
+
+    def coup(phi):
+        return np.imag(np.exp(-1j * (phi + alpha)) * (A @ np.exp(1j * phi))) * Linv
+    if model == O.KURAMOTO:
+        return lambda phi: omega + mu * coup(phi)
+    m, eps = prm[3], prm[4]
+    return lambda y: np.concatenate([y[n:], (omega - eps * y[n:] + mu * coup(y[:n])) / m])
+
+
+@pytest.mark.parametrize("model", [O.KURAMOTO, O.INERTIA, O.FHN])
+def test_links_dense_brute_force(model):
+    n = 45
+    rp, col = inputs.random_links(21, n, 0.15)
+    A = np.zeros((n, n))
+    for i in range(n):
+        if i % 11 != 3:  # rows 3, 14, 25, 36 are left empty
+            A[i, col[rp[i]:rp[i + 1]]] = 1.0
+    rp = np.concatenate([[0], np.cumsum(A.sum(axis=1))]).astype(np.int64)
+    col = np.nonzero(A)[1].astype(np.int32)
+    assert np.any(A.sum(axis=1) == 0) and np.any(np.diag(A) == 1)  # empty rows and self links occur
+    prm = {O.KURAMOTO: [0.3, 1.2, 1.1], O.INERTIA: [0.3, 1.2, 1.1, 0.8, 0.2],
+           O.FHN: [0.05, 0.5, 0.1, math.pi / 2 - 0.1]}[model]
+    if model == O.FHN:
+        y0 = inputs.fhn_circle(4, n)
+    elif model == O.INERTIA:
+        y0 = np.concatenate([inputs.kuramoto_phases(4, n), inputs.uniform_range(4, inputs.TAG_MISC, n, -0.5, 0.5)])
+    else:
+        y0 = inputs.kuramoto_phases(4, n)
+    ref = dense_rk4(links_dense(A, model, prm), y0, 0.01, 100)
+    y, _, _ = O.run(O.links(model, n, rp, col, np.array(prm)), y0, 0.01, 100)
+    assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-12
