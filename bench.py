@@ -24,6 +24,11 @@ Other workloads (one JSON line each, same fields):
   --workload ball      the same state with the paper's ball neighbourhood of
                        radius --radius (2: 33 links, the default; 6: 925 links),
                        centre included
+  --workload links     the same 100^3 inertia state with the ball of radius
+                       --radius given as an arbitrary binary coupling matrix
+                       (33 links per row at P = 2), held in the paper's
+                       differentially compressed form and extracted per row on
+                       the fly
   --workload adaptive  Dormand-Prince 5(4) with step-size control on the device:
                        4096 Kuramoto rings N = 1024, P = 256, alpha = 1.46,
                        omega = 0, integrated over t = 100 at rtol = 1e-8,
@@ -70,11 +75,12 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "hh": (1, 5000, 0.01, 1000000),
     "inertia": (1, 1000, 0.05, 100),
     "ball": (1, 1000, 0.05, 100),
+    "links": (1, 1000, 0.05, 100),
     "serve": (24, 0, 0.01, 0),
     "adaptive": (4096, 0, 0.0, 1024),
 }
 DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3,
-              "ball": 100 ** 3}
+              "ball": 100 ** 3, "links": 100 ** 3}
 INERTIA_PRM = [0.0, 0.01, 0.45, 1.0, 0.05]  # omega, mu, alpha, m, eps (Sec. V, Fig. 6c)
 
 
@@ -154,6 +160,18 @@ class Workload:
                          f"omega=0, RK4 dt=0.05, {args.horizon} steps, planted coherent ball, psi=0")
             self.kernel = "k_ball_stage<inertia>"
             self.prof = None
+        elif w == "links":
+            from paper_2410_19075_amd import inputs
+            self.n1 = args.n
+            self.n, self.P = args.n ** 3, args.radius
+            self.rows = inputs.lattice_ball_links(args.n, args.n, args.n, args.radius)
+            self.nvars, self.links = 2, int(self.rows[0][1])
+            self.name = (f"Kuramoto-Sakaguchi with inertia, 3D lattice {args.n}^3 periodic, ball of radius "
+                         f"{args.radius} ({self.links} links incl. the element) given as a binary coupling "
+                         f"matrix in compressed form (Alg. 2), m=1 eps=0.05 mu=0.01 alpha=0.45 omega=0, "
+                         f"RK4 dt=0.05, {args.horizon} steps, planted coherent ball, psi=0")
+            self.kernel = "k_links_stage<inertia>"
+            self.prof = None
         elif w == "cube":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, 4
@@ -188,6 +206,9 @@ class Workload:
         if w == "ball":
             return nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, self.n, INERTIA_PRM, precision=prec,
                               radius=self.P, dims=(self.n1,) * 3)
+        if w == "links":
+            return nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_LINKS, self.n, INERTIA_PRM, precision=prec,
+                              row_ptr=self.rows[0], col=self.rows[1])
         rp, col, wt = self.graph
         return nd.problem(nd.ND_HH, nd.ND_CSR, self.n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=wt,
                           per_elem=self.iapp)
@@ -201,7 +222,7 @@ class Workload:
             return inputs.kuramoto_phases(1000 + b, self.n)
         if w == "cube":
             return inputs.cube_phases_with_patch(1000 + b, self.n1)
-        if w in ("inertia", "ball"):
+        if w in ("inertia", "ball", "links"):
             return np.concatenate([inputs.cube_phases_with_patch(1000 + b, self.n1), np.zeros(self.n)])
         return inputs.hh_state(1000 + b, self.n)
 
@@ -214,6 +235,10 @@ class Workload:
         b = self.nvars * (7 * 8 + 6 * kb)
         if self.a.workload == "hh":
             b += 4 * self.links * (4 + kb)
+        if self.a.workload == "links":
+            # per stage: the row's table index, and the exchanged map (cos, sin)
+            # written once and read once (its gathers by the neighbours hit cache)
+            b += 4 * (4 + 2 * (16 if prec == 0 else 8))
         return b
 
 
@@ -287,6 +312,9 @@ def cpu_baseline(wl, args):
     elif w == "ball":
         net, steps, what = (O.ball(wl.n1, wl.P, INERTIA_PRM, model=O.INERTIA), 1,
                             f"the {wl.n1}^3 lattice with inertia, ball radius {wl.P}")
+    elif w == "links":
+        net, steps, what = (O.links(O.INERTIA, wl.n, wl.rows[0], wl.rows[1], np.array(INERTIA_PRM)), 20,
+                            f"the {wl.n1}^3 lattice with inertia, ball radius {wl.P} as row lists")
     else:
         rp, col, wt = wl.graph
         net, steps, what = O.csr(wl.n, rp, col, wt, HH_PRM, wl.iapp), args.cpu_sample_steps, f"HH N={wl.n} deg 100"

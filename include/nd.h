@@ -16,17 +16,19 @@
  *   ND_KURAMOTO  Eq. (3) with m = 0, eps = 1 and a natural frequency:
  *                dphi_i/dt = omega + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha),
  *                L = number of neighbours (the paper's Alg. 1 divides by the link count).
- *                params = {omega, mu, alpha}.  Topology ND_RING, ND_CUBE3D, ND_BALL3D or ND_DISK2D.
+ *                params = {omega, mu, alpha}.  Topology ND_RING, ND_CUBE3D, ND_BALL3D, ND_DISK2D or
+ *                ND_LINKS.
  *   ND_KURAMOTO_INERTIA  Eq. (3) with inertia (m != 0) as a first-order system in
  *                (phi, psi = dphi/dt), plus a natural frequency:
  *                dphi_i/dt = psi_i,
  *                m dpsi_i/dt = omega - eps psi_i + (mu/L) sum_{j in nbr(i)} sin(phi_j - phi_i - alpha).
- *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING, ND_CUBE3D, ND_BALL3D or
- *                ND_DISK2D.
+ *                params = {omega, mu, alpha, m, eps}; m != 0.  ND_RING, ND_CUBE3D, ND_BALL3D,
+ *                ND_DISK2D or ND_LINKS.
  *   ND_FHN       Eq. (2) with tau = 0, D = 0, I_app = 0 and a rotational coupling
  *                matrix B(phi) = [[cos phi, sin phi], [-sin phi, cos phi]] applied to
  *                (u_j - u_i, v_j - v_i), averaged over the 2P ring neighbours, inside the
- *                eps-scaled fast equation.  params = {eps, a, sigma, phi}.  ND_RING only.
+ *                eps-scaled fast equation.  params = {eps, a, sigma, phi}.  ND_RING, or ND_LINKS
+ *                (then averaged over the row's links).
  *   ND_HH        Eq. (1) for the squid axon (Na, K, leak; textbook rate functions, rest
  *                -65 mV) with an instantaneous sigmoidal synapse:
  *                C dV_i/dt = I_i - I_ion + (Esyn - V_i) sum_{e in in(i)} w_e S(V_src(e)),
@@ -34,7 +36,7 @@
  *                params = {C, gNa, gK, gL, ENa, EK, EL, Esyn, theta_s, k_s}; per_elem = I_i.
  *                ND_CSR only.
  *
- * Topologies (Sec. IV; Sec. III.C for general coupling matrices):
+ * Topologies (Sec. IV; Sec. III.C for general coupling matrices and their compression):
  *   ND_RING      element i couples to i +- 1 .. i +- P (periodic), requires 1 <= P, 2P+1 <= n
  *                and n < 2^29.
  *   ND_CUBE3D    periodic n1 x n2 x n3 lattice, index x + n1*y + n1*n2*z (the paper's 3D index
@@ -49,6 +51,13 @@
  *                n1, n2 >= 2P+1.  Kuramoto models only.
  *   ND_CSR       directed graph stored by target: in-edges of i are row_ptr[i] .. row_ptr[i+1]-1,
  *                col[e] = source, weight[e] = synaptic weight (the paper's L_ik with weights).
+ *   ND_LINKS     an arbitrary binary coupling matrix L (Sec. III.C: L_ij = 1 when element j
+ *                influences element i), given by rows in row_ptr / col as for ND_CSR (weight
+ *                ignored): row i lists its sources j, each at most once, self links allowed.
+ *                L = the row's own link count; a row without links has no coupling.  nd_create
+ *                compresses the matrix with the paper's differential compression (Alg. 2, see
+ *                nd_compress_links) and the kernels extract every row on the fly; the cost per
+ *                element is the row's link count.  n < 2^29.  Kuramoto models and FHN.
  *
  * State layout: variable-major FP64, length nvars * n: Kuramoto phi[n] (unwrapped, never reduced
  * mod 2 pi); Kuramoto with inertia phi[n] then psi[n]; FHN u[n] then v[n]; HH V[n], m[n], h[n],
@@ -101,6 +110,7 @@ typedef int32_t nd_status;
 #define ND_CSR 2
 #define ND_BALL3D 3
 #define ND_DISK2D 4
+#define ND_LINKS 5
 
 #define ND_FP64 0
 #define ND_FP32_BULK 1
@@ -110,14 +120,14 @@ typedef int32_t nd_status;
 /* A network: model, parameters, topology, precision.  All pointers are host pointers. */
 typedef struct nd_problem {
     int32_t model;      /* ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA */
-    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D */
+    int32_t topo;       /* ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D, ND_LINKS */
     int32_t precision;  /* ND_FP64, ND_FP32_BULK */
     int32_t reserved;   /* must be 0 */
     int64_t n;          /* number of elements */
     int64_t radius;     /* ring: P; cube: half-width h */
     int64_t n1, n2, n3; /* cube extents, n = n1*n2*n3 */
-    const int64_t* row_ptr; /* CSR: n+1 offsets, row_ptr[0] = 0, non-decreasing */
-    const int32_t* col;     /* CSR: nnz sources in [0, n) */
+    const int64_t* row_ptr; /* CSR, LINKS: n+1 offsets, row_ptr[0] = 0, non-decreasing */
+    const int32_t* col;     /* CSR, LINKS: nnz sources in [0, n) */
     const double* weight;   /* CSR: nnz weights */
     int64_t nnz;            /* CSR: number of edges = row_ptr[n] */
     const double* per_elem; /* HH: applied current per neuron (n values); else NULL */
@@ -210,6 +220,30 @@ typedef struct nd_adaptive_stats {
 
 nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end, const double* dt0, double rtol,
                           double atol, int64_t max_steps, nd_adaptive_stats* stats, void* hip_stream);
+
+/* Differential compression of a binary coupling matrix (Sec. III.C, Alg. 2), as nd_create
+ * applies it to ND_LINKS problems; exposed so a caller can inspect the compressed size.
+ * Rows are given as for ND_LINKS (row_ptr: n+1 offsets, col: sources).  A circular shift of
+ * row i left by i moves position p to (p - i) mod n; the common vector V is row 0; the
+ * difference vector of row i is (row i shifted left by i) XOR V; the difference table keeps
+ * each distinct difference vector once, in order of first appearance as i increases; C[i] is
+ * the entry of row i, so row i = (V XOR D[C[i]]) shifted right by i.  Host-only: no device
+ * work.  info receives the sizes (always); V (sorted positions, v_cap >= info.v_bits),
+ * d_ptr (entry k holds d_pos[d_ptr[k] .. d_ptr[k+1]-1], sorted; d_ptr_cap >= entries + 1),
+ * d_pos (d_pos_cap >= info.d_bits) and C (c_cap >= n) are written when non-NULL, so a first
+ * call with NULL arrays sizes them.  ND_ERR_INVALID_ARG for malformed rows (a source out of
+ * range or listed twice) or short arrays; n < 2^29. */
+typedef struct nd_links_info {
+    int64_t v_bits;   /* set bits of the common vector V (the links of row 0) */
+    int64_t entries;  /* difference-table entries */
+    int64_t d_bits;   /* set bits over all entries */
+    int64_t runs;     /* maximal runs of consecutive positions in V */
+    int64_t bytes;    /* device bytes of the compressed matrix as the kernels hold it */
+} nd_links_info;
+
+nd_status nd_compress_links(int64_t n, const int64_t* row_ptr, const int32_t* col, int32_t* V, int64_t v_cap,
+                            int64_t* d_ptr, int64_t d_ptr_cap, int32_t* d_pos, int64_t d_pos_cap, int32_t* C,
+                            int64_t c_cap, nd_links_info* info);
 
 nd_status nd_get_config(nd_handle h, nd_kernel_config* cfg);
 nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg);

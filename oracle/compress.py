@@ -1,4 +1,4 @@
-"""Differential compression of a binary coupling matrix (Sec. III.B, Alg. 2),
+"""Differential compression of a binary coupling matrix (Sec. III.C, Alg. 2),
 written out plainly with Python sets.
 
 TEST INFRASTRUCTURE ONLY: imported by tests/ and the benchmark's CPU-baseline

@@ -43,7 +43,7 @@
  *     with k = sigma / (2P).
  *   The Kuramoto models and FitzHugh-Nagumo also run on an arbitrary binary
  *     coupling matrix given by rows (topology LINKS: row i lists the
- *     presynaptic elements j with L_ij = 1, Sec. III.B), each sum divided by
+ *     presynaptic elements j with L_ij = 1, Sec. III.C), each sum divided by
  *     the row's own link count Omega_i as Alg. 1 divides by its link count; a
  *     row without links contributes no coupling.  The links are taken in the
  *     order the row lists them.

@@ -11,6 +11,8 @@ namespace nd {
 
 constexpr int kWave = 64;
 constexpr int kCsrSourceBlocks = 8;  // CSR in-edges split by source range, one block per XCD
+constexpr int kLinksRows = 256;          // compressed coupling matrix: rows per work item
+constexpr int32_t kLinksRemove = 1 << 30;  // entry position flag: the entry removes a link of V
 
 // Per-network descriptor, one per network of a batch, resident in device memory.
 // The chunk-position fields (g0, nsteps, ypar) advance on the device at the end
@@ -38,6 +40,12 @@ struct NetDesc {
     const void* w;           // CSR: weights in the bulk type, same order
     double* acc_part;        // CSR: per source block synaptic partial sums [blocks][n]
     const double* iapp;
+    const int32_t* lrow;     // links: difference-table entry of every row
+    const int2* lruns;       // links: runs (first position, length) of the common vector
+    const int32_t* ldptr;    // links: entry k's positions at [ldptr[k], ldptr[k+1])
+    const int32_t* ldpos;    // links: position, | kLinksRemove when V holds it
+    const double* linv;      // links: 1 / link count of the rows of entry k (0: no links)
+    int32_t lnruns;          // links: number of runs
     double* R;          // order parameter per recorded step
     int64_t r_every;
     double* mv;         // mean phase velocity accumulator / result

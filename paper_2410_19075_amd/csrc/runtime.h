@@ -132,4 +132,32 @@ hipError_t csr_launch_prologue(const CsrLaunch& L, int grid, hipStream_t s, NetD
 hipError_t csr_launch_stage(const CsrLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
                             const int* nwork, int stage, int j);
 
+// Binary coupling matrices in the paper's compressed form (links.hip)
+struct LinksCompressed {
+    int64_t n = 0;
+    std::vector<int32_t> V;     // common vector: sorted positions of row 0
+    std::vector<int64_t> dptr;  // difference table: entry k at [dptr[k], dptr[k+1]) of dpos
+    std::vector<int32_t> dpos;  // sorted positions of every entry
+    std::vector<int32_t> C;     // entry of every row
+};
+struct LinksDeviceForm {
+    std::vector<int2> runs;     // maximal runs of consecutive positions of V
+    std::vector<int32_t> dptr;  // as LinksCompressed::dptr
+    std::vector<int32_t> dsig;  // positions, | kLinksRemove where V holds the position
+    std::vector<double> inv;    // 1 / link count per entry (0 for an empty row)
+};
+nd_status compress_links(int64_t n, const int64_t* row_ptr, const int32_t* col, LinksCompressed* out);
+void links_device_form(const LinksCompressed& c, LinksDeviceForm* f);
+int64_t links_device_bytes(const LinksCompressed& c);
+struct LinksLaunch {
+    void (*prologue)(const NetDesc*, const int2*, const int*);
+    void (*stage[4])(const NetDesc*, const int2*, const int*, int);
+    void (*stage_mv[4])(const NetDesc*, const int2*, const int*, int);
+    void (*final)(const NetDesc*, const int2*, const int*, int);
+};
+bool links_select(int model, int prec, LinksLaunch* out);
+size_t links_map_bytes(int model, int prec);
+hipError_t links_launch_chunk(const LinksLaunch& L, int grid, hipStream_t s, NetDesc* D, const int2* work,
+                              const int* nwork, int chunk, bool mv);
+
 }  // namespace nd

@@ -112,6 +112,17 @@ nd_status validate_problem(const nd_problem* p) {
                 return fail(ND_ERR_INVALID_ARG, "lattices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
             break;
         }
+        case ND_LINKS: {
+            if (p->model == ND_HH) return fail(ND_ERR_INVALID_ARG, "HH needs the CSR topology (weighted links)");
+            if (!p->row_ptr || (p->nnz > 0 && !p->col))
+                return fail(ND_ERR_INVALID_ARG, "the links topology needs row_ptr and col");
+            if (p->row_ptr[0] != 0 || p->row_ptr[p->n] != p->nnz)
+                return fail(ND_ERR_INVALID_ARG, "row_ptr must start at 0 and end at nnz");
+            if (p->n >= (int64_t(1) << 29))
+                return fail(ND_ERR_INVALID_ARG, "link matrices hold at most 2^29 - 1 elements (n=%lld)", (long long)p->n);
+            // row order and ranges are checked while compressing
+            break;
+        }
         case ND_CSR: {
             if (p->model != ND_HH) return fail(ND_ERR_INVALID_ARG, "the CSR topology is for HH");
             if (!p->row_ptr || (p->nnz > 0 && (!p->col || !p->weight)) || !p->per_elem)
@@ -269,6 +280,9 @@ nd_kernel_config default_config(const nd_problem* p) {
         c.tile_y = cy;
         c.tile_z = cz;
         c.block = bs;
+    } else if (p->topo == ND_LINKS) {
+        c.tile = kLinksRows;  // rows per work item
+        c.block = 256;
     } else {
         c.tile = 256;    // target rows per work item
         c.tile_y = 8;    // edges per thread per chunk
@@ -295,6 +309,13 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
              ((p->n3 + c.tile_z - 1) / c.tile_z);
     if (p->topo == ND_CSR)
         b += kCsrSourceBlocks * (n + 1) * 8 + p->nnz * (4 + kb) + n * 8 + 2 * n * kb + kCsrSourceBlocks * n * 8;
+    if (p->topo == ND_LINKS) {
+        // the compressed matrix (sized by compressing it), the two exchanged-map buffers and
+        // the per-work-item sums
+        LinksCompressed lc;
+        if (compress_links(n, p->row_ptr, p->col, &lc) == ND_OK) b += links_device_bytes(lc);
+        b += 2 * n * (int64_t)links_map_bytes(p->model, p->precision) + 3 * 2 * 8 * ((n + kLinksRows - 1) / kLinksRows);
+    }
     b += sizeof(NetDesc) + 64;
     return b;
 }
@@ -316,9 +337,11 @@ Net::~Net() {
 static void derive_params(const nd_problem* p, NetDesc& d) {
     std::memset(d.p, 0, sizeof d.p);
     if (p->model == ND_KURAMOTO || p->model == ND_KURAMOTO_INERTIA) {
+        // links: the kernels divide each row's sum by its own link count
         const double L = p->topo == ND_RING     ? 2.0 * (double)p->radius
                          : p->topo == ND_BALL3D ? (double)ball_points(p->radius)
                          : p->topo == ND_DISK2D ? (double)disk_points(p->radius)
+                         : p->topo == ND_LINKS  ? 1.0
                                                 : std::pow(2.0 * (double)p->radius + 1.0, 3.0) - 1.0;
         d.p[0] = p->params[0];
         d.p[1] = p->params[1] / L;
@@ -331,10 +354,12 @@ static void derive_params(const nd_problem* p, NetDesc& d) {
     } else if (p->model == ND_FHN) {
         d.p[0] = p->params[0];
         d.p[1] = p->params[1];
-        d.p[2] = p->params[2] / (2.0 * (double)p->radius);
+        // links: the kernels pass the row's mean, so kappa = sigma and the count is 1
+        const double L = p->topo == ND_LINKS ? 1.0 : 2.0 * (double)p->radius;
+        d.p[2] = p->params[2] / L;
         d.p[3] = std::cos(p->params[3]);
         d.p[4] = std::sin(p->params[3]);
-        d.p[5] = 2.0 * (double)p->radius;
+        d.p[5] = L;
         d.p[6] = 1.0 / p->params[0];
     } else {
         for (int i = 0; i < 10; ++i) d.p[i] = p->params[i];
@@ -413,6 +438,29 @@ nd_status Net::create(const nd_problem* pr) {
         }
         HIPC(hipMemcpy((void*)d.iapp, pr->per_elem, n * 8, hipMemcpyHostToDevice));
     }
+    if (pr->topo == ND_LINKS) {
+        LinksCompressed lc;
+        if ((s = compress_links(n, pr->row_ptr, pr->col, &lc))) return s;
+        if ((int64_t)lc.dpos.size() >= (int64_t(1) << 31))
+            return fail(ND_ERR_UNSUPPORTED, "links: the difference table holds 2^31 or more positions");
+        LinksDeviceForm f;
+        links_device_form(lc, &f);
+        const size_t K = f.inv.size();
+        if ((s = alloc((void**)&d.lrow, n * 4))) return s;
+        if ((s = alloc((void**)&d.lruns, f.runs.size() * sizeof(int2)))) return s;
+        if ((s = alloc((void**)&d.ldptr, (K + 1) * 4))) return s;
+        if ((s = alloc((void**)&d.ldpos, f.dsig.size() * 4))) return s;
+        if ((s = alloc((void**)&d.linv, K * 8))) return s;
+        for (int b = 0; b < 2; ++b)
+            if ((s = alloc(&d.sx[b], n * (int64_t)links_map_bytes(pr->model, pr->precision)))) return s;
+        d.lnruns = (int32_t)f.runs.size();
+        HIPC(hipMemcpy((void*)d.lrow, lc.C.data(), n * 4, hipMemcpyHostToDevice));
+        if (!f.runs.empty())
+            HIPC(hipMemcpy((void*)d.lruns, f.runs.data(), f.runs.size() * sizeof(int2), hipMemcpyHostToDevice));
+        HIPC(hipMemcpy((void*)d.ldptr, f.dptr.data(), (K + 1) * 4, hipMemcpyHostToDevice));
+        if (!f.dsig.empty()) HIPC(hipMemcpy((void*)d.ldpos, f.dsig.data(), f.dsig.size() * 4, hipMemcpyHostToDevice));
+        HIPC(hipMemcpy((void*)d.linv, f.inv.data(), K * 8, hipMemcpyHostToDevice));
+    }
     if ((s = alloc((void**)&solo_desc, sizeof(NetDesc)))) return s;
     if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
     return apply_config(cfg);
@@ -449,6 +497,11 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
         tmpl.pz = ball_pz(prob.topo, prob.radius);
         const int32_t gz = (int32_t)((prob.n3 + cfg.tile_z - 1) / cfg.tile_z);
         tmpl.G = tmpl.gx * tmpl.gy * gz;
+    } else if (prob.topo == ND_LINKS) {
+        cfg.block = 256;
+        cfg.tile = kLinksRows;  // rows per work item (fixed by the kernel)
+        tmpl.tile = kLinksRows;
+        tmpl.G = (int32_t)((n + kLinksRows - 1) / kLinksRows);
     } else {
         cfg.block = 256;
         cfg.tile = 256;  // rows per work item (fixed by the kernel)
@@ -604,6 +657,11 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
                     return hip_fail(e, "ball stage");
         if ((e = cube_launch_final(L, grid, st, g.desc, g.work, g.nwork, chunk)) != hipSuccess)
             return hip_fail(e, "ball final");
+    } else if (g.topo == ND_LINKS) {
+        LinksLaunch L;
+        if (!links_select(g.model, g.prec, &L)) return fail(ND_ERR_UNSUPPORTED, "no links kernel for model %d", g.model);
+        if ((e = links_launch_chunk(L, grid, st, g.desc, g.work, g.nwork, chunk, g.mv)) != hipSuccess)
+            return hip_fail(e, "links chunk");
     } else {
         CsrLaunch L;
         if (!csr_select(g.prec, g.tile_y, &L)) return fail(ND_ERR_UNSUPPORTED, "no CSR kernel for %d edges per thread", g.tile_y);
@@ -769,6 +827,10 @@ nd_status nd_footprint(const nd_problem* p, int64_t* bytes) {
     if (!bytes) return fail(ND_ERR_INVALID_ARG, "bytes is NULL");
     nd_status s = validate_problem(p);
     if (s) return s;
+    if (p->topo == ND_LINKS) {  // malformed rows show up while compressing
+        LinksCompressed lc;
+        if ((s = compress_links(p->n, p->row_ptr, p->col, &lc))) return s;
+    }
     *bytes = footprint_bytes(p, default_config(p));
     return ND_OK;
 }
@@ -881,6 +943,9 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
             ball_smem_bytes(P, pz, c.tile, c.tile_y) > kBallSmemMax)
             return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 4*block/64, "
                                             "tile*tile_y <= block and the prefix ring within LDS");
+    } else if (p.topo == ND_LINKS) {
+        if (c.tile != kLinksRows) return fail(ND_ERR_INVALID_ARG, "links work items hold %d rows (tile must be %d)",
+                                              kLinksRows, kLinksRows);
     } else {
         if (c.tile != 256) return fail(ND_ERR_INVALID_ARG, "CSR work items hold 256 rows (tile must be 256)");
         if (c.tile_y < 2 || c.tile_y > 16 || (c.tile_y & (c.tile_y - 1)))

@@ -369,13 +369,15 @@ nd_status nd_server_submit(nd_server_h h, const nd_problem* p, const double* y0,
                                                (long long)i);
     auto r = std::make_unique<Request>();
     r->prob = *p;
-    if (p->topo == ND_CSR) {
+    if (p->topo == ND_CSR || p->topo == ND_LINKS) {
         r->row_ptr.assign(p->row_ptr, p->row_ptr + p->n + 1);
         r->col.assign(p->col, p->col + p->nnz);
-        r->weight.assign(p->weight, p->weight + p->nnz);
         r->prob.row_ptr = r->row_ptr.data();
         r->prob.col = r->col.data();
-        r->prob.weight = r->weight.data();
+        if (p->topo == ND_CSR) {
+            r->weight.assign(p->weight, p->weight + p->nnz);
+            r->prob.weight = r->weight.data();
+        }
     }
     if (p->per_elem) {
         r->per_elem.assign(p->per_elem, p->per_elem + p->n);

@@ -92,6 +92,8 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
             c.tile_z = (int)std::max<int64_t>(1, std::min<int64_t>(cz, p->n3));
             v.push_back(c);
         }
+    } else if (p->topo == ND_LINKS) {
+        v.push_back(base);  // one kernel shape
     } else {
         for (int l : {4, 8, 16}) {
             nd_kernel_config c = base;

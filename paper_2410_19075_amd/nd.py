@@ -18,7 +18,7 @@ ND_ERR_NUMERIC = -5
 ND_ERR_UNSUPPORTED = -6
 
 ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA = 0, 1, 2, 3
-ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D = 0, 1, 2, 3, 4
+ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D, ND_LINKS = 0, 1, 2, 3, 4, 5
 ND_FP64, ND_FP32_BULK = 0, 1
 ND_MAX_PARAMS = 12
 NVARS = {ND_KURAMOTO: 1, ND_FHN: 2, ND_HH: 4, ND_KURAMOTO_INERTIA: 2}
@@ -44,6 +44,10 @@ class nd_kernel_config(ctypes.Structure):
 
 class nd_adaptive_stats(ctypes.Structure):
     _fields_ = [("t", _c_dbl), ("accepted", _c_i64), ("rejected", _c_i64), ("h_next", _c_dbl)]
+
+
+class nd_links_info(ctypes.Structure):
+    _fields_ = [("v_bits", _c_i64), ("entries", _c_i64), ("d_bits", _c_i64), ("runs", _c_i64), ("bytes", _c_i64)]
 
 
 class nd_server_config(ctypes.Structure):
@@ -87,6 +91,8 @@ _sig = {
     "nd_run_adaptive": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _P(nd_adaptive_stats),
                         _c_vp],
     "nd_get_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
+    "nd_compress_links": [_c_i64, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64,
+                          _P(nd_links_info)],
     "nd_get_observables": [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_destroy": [_c_vp],
     "nd_get_config": [_c_vp, _P(nd_kernel_config)],
@@ -225,6 +231,24 @@ def nd_run_adaptive(handles, t_end, dt0, rtol, atol, max_steps=10 ** 7, stream=N
     _check(_lib.nd_run_adaptive(hs, k, te, d0, float(rtol), float(atol), int(max_steps), st, _stream(stream)),
            "nd_run_adaptive")
     return list(st)
+
+
+def nd_compress_links(n, row_ptr, col):
+    """The library's compression of a binary coupling matrix given by rows:
+    returns (V, d_ptr, d_pos, C, info)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    info = nd_links_info()
+    _check(_lib.nd_compress_links(int(n), rp.ctypes.data, cl.ctypes.data if cl.size else None, None, 0, None, 0,
+                                  None, 0, None, 0, ctypes.byref(info)), "nd_compress_links")
+    V = np.empty(info.v_bits, dtype=np.int32)
+    dptr = np.empty(info.entries + 1, dtype=np.int64)
+    dpos = np.empty(info.d_bits, dtype=np.int32)
+    C = np.empty(int(n), dtype=np.int32)
+    _check(_lib.nd_compress_links(int(n), rp.ctypes.data, cl.ctypes.data if cl.size else None, V.ctypes.data, V.size,
+                                  dptr.ctypes.data, dptr.size, dpos.ctypes.data, dpos.size, C.ctypes.data, C.size,
+                                  ctypes.byref(info)), "nd_compress_links")
+    return V, dptr, dpos, C, info
 
 
 def nd_get_observables(h, R=None, mean_vel=None, on_device=None, stream=None):

@@ -155,3 +155,80 @@ def test_ball_link_counts_and_footprint():
     r = np.arange(-6, 7)
     X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
     assert int(np.sum(X ** 2 + Y ** 2 + Z ** 2 <= 36)) == 925
+
+
+# ------------------------------------------- compressed coupling matrix (host)
+def _oracle_compress(n, rp, col):
+    from oracle import compress as CM
+    return CM.compress(n, rp, col)
+
+
+@pytest.mark.parametrize("case", ["random", "ring", "small_world", "lattice", "disk", "empty_rows"])
+def test_links_compression_matches_the_oracle(case):
+    """The library's Alg. 2 (host C++) gives exactly the oracle's common vector,
+    difference table (same order) and row entries."""
+    from paper_2410_19075_amd import nd
+    if case == "random":
+        n, (rp, col) = 61, inputs.random_links(5, 61, 0.2)
+    elif case == "ring":
+        n, (rp, col) = 100, inputs.ring_links(100, 17)
+    elif case == "small_world":
+        n, (rp, col) = 500, inputs.small_world_links(9, 500, 6, 40)
+    elif case == "lattice":
+        n, (rp, col) = 9 * 10 * 11, inputs.lattice_ball_links(9, 10, 11, 3)
+    elif case == "disk":
+        n, (rp, col) = 15 * 13, inputs.lattice_ball_links(15, 13, 1, 4)
+    else:
+        n = 30
+        rp0, col0 = inputs.random_links(8, n, 0.3)
+        rows = [col0[rp0[i]:rp0[i + 1]] if i % 2 else col0[:0] for i in range(n)]  # even rows empty
+        rp = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64)
+        col = np.concatenate(rows).astype(np.int32)
+    V, dptr, dpos, C, info = nd.nd_compress_links(n, rp, col)
+    V2, D2, C2 = _oracle_compress(n, rp, col)
+    assert list(V) == V2 and np.array_equal(C, C2)
+    assert info.entries == len(D2) and [list(dpos[dptr[k]:dptr[k + 1]]) for k in range(info.entries)] == D2
+    assert info.v_bits == len(V2) and info.d_bits == sum(len(d) for d in D2)
+
+
+def test_links_unsorted_rows_compress_like_sorted_ones():
+    from paper_2410_19075_amd import nd
+    n, (rp, col) = 80, inputs.small_world_links(4, 80, 3, 10)
+    shuffled = col.copy()
+    for i in range(n):
+        shuffled[rp[i]:rp[i + 1]] = shuffled[rp[i]:rp[i + 1]][::-1]
+    a, b = nd.nd_compress_links(n, rp, col), nd.nd_compress_links(n, rp, shuffled)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+
+
+def test_links_paper_3d_radius_6_table_is_small():
+    """Ball of radius 6 (925 links) on a flattened periodic lattice: 13^2 = 169
+    entries, so the per-row index dominates the compressed size."""
+    from paper_2410_19075_amd import nd
+    n1 = 26
+    rp, col = inputs.lattice_ball_links(n1, n1, n1, 6)
+    _, _, _, _, info = nd.nd_compress_links(n1 ** 3, rp, col)
+    assert info.v_bits == 925 and info.entries == 169
+    assert info.bytes < 4 * n1 ** 3 + 169 * 8 + 4 * info.d_bits + 8 * info.runs + 4 * 170 + 1
+
+
+@pytest.mark.parametrize("bad", ["duplicate", "range", "decreasing"])
+def test_links_malformed_rows_are_rejected(bad):
+    from paper_2410_19075_amd import nd
+    n = 6
+    rp = np.array([0, 2, 4, 6, 8, 10, 12], dtype=np.int64)
+    col = np.array([1, 2, 0, 2, 0, 1, 4, 5, 3, 5, 3, 4], dtype=np.int32)
+    if bad == "duplicate":
+        col[3] = 0
+    elif bad == "range":
+        col[5] = 6
+    else:
+        rp[2] = 1
+    with pytest.raises(nd.NDError) as ei:
+        nd.nd_compress_links(n, rp, col)
+    assert ei.value.status == nd.ND_ERR_INVALID_ARG
+    if bad != "decreasing":
+        p = nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, [0, 1, 0.5], row_ptr=rp, col=col)
+        with pytest.raises(nd.NDError):
+            nd.nd_footprint(p)

@@ -1,0 +1,198 @@
+"""GPU parity of arbitrary binary coupling matrices held in the paper's
+compressed form (Alg. 2) against the FP64 CPU oracle's row-list topology,
+through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import compress as CM
+from oracle import oracle as O
+from paper_2410_19075_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KUR = [0.1, 1.0, 0.9]
+INERT = [0.1, 1.0, 0.45, 1.0, 0.05]
+FHN = [0.05, 0.5, 0.1, math.pi / 2 - 0.1]
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_19075_amd import nd as _nd
+    return _nd
+
+
+def normwise(a, ref, nvars):
+    a, ref = a.reshape(nvars, -1), ref.reshape(nvars, -1)
+    return max(np.max(np.abs(a[v] - ref[v])) / np.max(np.abs(ref[v])) for v in range(nvars))
+
+
+MODELS = {"kuramoto": (0, O.KURAMOTO, KUR, 1), "inertia": (3, O.INERTIA, INERT, 2), "fhn": (1, O.FHN, FHN, 2)}
+
+
+def state(model, seed, n):
+    if model == "fhn":
+        return inputs.fhn_circle(seed, n)
+    if model == "inertia":
+        return np.concatenate([inputs.kuramoto_phases(seed, n), inputs.uniform_range(seed, inputs.TAG_MISC, n, -0.5, 0.5)])
+    return inputs.kuramoto_phases(seed, n)
+
+
+def with_empty_rows(rp, col, every):
+    n = rp.size - 1
+    rows = [col[rp[i]:rp[i + 1]] if i % every else col[:0] for i in range(n)]
+    return (np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64),
+            np.concatenate(rows).astype(np.int32))
+
+
+def matrix(kind, seed):
+    if kind == "random":
+        n = 300
+        return n, with_empty_rows(*inputs.random_links(seed, n, 0.05), 7)
+    if kind == "small_world":
+        n = 2000
+        return n, inputs.small_world_links(seed, n, 25, 60)
+    if kind == "lattice":
+        return 12 * 11 * 10, inputs.lattice_ball_links(12, 11, 10, 2)
+    if kind == "disk":
+        return 23 * 19, inputs.lattice_ball_links(23, 19, 1, 3)
+    if kind == "full_mesh":
+        n = 257
+        return n, (np.arange(0, n * n + 1, n, dtype=np.int64), np.tile(np.arange(n, dtype=np.int32), n))
+    if kind == "tiny":
+        return 1, (np.array([0, 1], dtype=np.int64), np.array([0], dtype=np.int32))
+    raise ValueError(kind)
+
+
+def run_case(nd, model, n, rp, col, seed, steps, prec=0, dt=0.01, record_every=0, mv=-1):
+    code, ocode, prm, nv = MODELS[model]
+    y0 = state(model, seed, n)
+    p = nd.problem(code, nd.ND_LINKS, n, prm, precision=prec, row_ptr=rp, col=col)
+    y, R, mvel = nd.simulate(p, y0, dt, steps, record_every=record_every, mv_start_step=mv)
+    ref, Rref, mvref = O.run(O.links(ocode, n, rp, col, np.array(prm)), y0, dt, steps, record_every=record_every,
+                             mv_start=mv if mv >= 0 else None)
+    return y, ref, R, Rref, mvel, mvref, nv
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "inertia", "fhn"])
+@pytest.mark.parametrize("kind", ["random", "small_world", "lattice", "disk", "full_mesh", "tiny"])
+def test_links_fp64_parity(nd, model, kind):
+    print(f"case links {model} {kind}", flush=True)
+    n, (rp, col) = matrix(kind, 3)
+    y, ref, R, Rref, mv, mvref, nv = run_case(nd, model, n, rp, col, 17, 30, record_every=5, mv=10)
+    assert normwise(y, ref, nv) < 1e-12
+    assert np.max(np.abs(R - Rref)) < 1e-12
+    assert np.max(np.abs(mv - mvref)) < 1e-9
+
+
+@pytest.mark.parametrize("model", ["kuramoto", "fhn"])
+def test_links_fp32_bulk(nd, model):
+    n, (rp, col) = matrix("small_world", 5)
+    y, ref, _, _, _, _, nv = run_case(nd, model, n, rp, col, 4, 200, prec=1)
+    e = normwise(y, ref, nv)
+    print(f"links {model} fp32-bulk error {e:.3e}")
+    assert e < 1e-4
+
+
+def test_links_ring_matches_the_ring_kernel(nd):
+    """The ring given as a coupling matrix (one empty table entry) against the
+    window-sum ring kernel: the same trajectory within FP64 rounding."""
+    n, P = 4096, 700
+    rp, col = inputs.ring_links(n, P)
+    y0 = inputs.kuramoto_phases(8, n)
+    a, _, _ = nd.simulate(nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, KUR, row_ptr=rp, col=col), y0, 0.01, 50)
+    b, _, _ = nd.simulate(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, KUR, radius=P), y0, 0.01, 50)
+    assert np.max(np.abs(a - b)) / np.max(np.abs(b)) < 1e-12
+
+
+def test_links_ball_matches_the_ball_kernel(nd):
+    """The paper's 3D performance state (Kuramoto with inertia, ball of radius
+    2, 33 links) on 40^3 given as a compressed coupling matrix, against the
+    ball kernel and, on sampled elements, the oracle."""
+    n1, P = 40, 2
+    n = n1 ** 3
+    rp, col = inputs.lattice_ball_links(n1, n1, n1, P)
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(6, n1), np.zeros(n)])
+    a, _, _ = nd.simulate(nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_LINKS, n, prm, row_ptr=rp, col=col), y0, 0.05, 10)
+    b, _, _ = nd.simulate(nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, radius=P, dims=(n1,) * 3),
+                          y0, 0.05, 10)
+    assert normwise(a, b, 2) < 1e-12
+    ref, _, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, 10)
+    assert normwise(a, ref, 2) < 1e-12
+
+
+def test_links_restart_is_bitwise(nd):
+    n, (rp, col) = matrix("small_world", 9)
+    y0 = state("fhn", 2, n)
+    p = nd.problem(nd.ND_FHN, nd.ND_LINKS, n, FHN, row_ptr=rp, col=col)
+    a, _, _ = nd.simulate(p, y0, 0.01, 40)
+    b, _, _ = nd.simulate(p, y0, 0.01, 15)
+    c, _, _ = nd.simulate(p, b, 0.01, 25)
+    assert np.array_equal(a, c)
+
+
+def test_links_graph_chunks_and_persistent_grid(nd):
+    """Steps spread over replayed graph chunks (chunk not dividing the steps)
+    and a persistent grid smaller than the work give the eager result bitwise."""
+    n, (rp, col) = matrix("small_world", 12)
+    y0 = state("inertia", 3, n)
+    p = nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_LINKS, n, INERT, row_ptr=rp, col=col)
+    ref, _, _ = nd.simulate(p, y0, 0.01, 23)
+    h = nd.nd_create(p)
+    try:
+        c = nd.nd_get_config(h)
+        c.chunk, c.grid = 5, 3
+        nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, 0.01, 23)
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    assert np.array_equal(y, ref)
+
+
+def test_links_batch_with_other_topologies(nd):
+    """Links networks of different sizes batched with a ring in one call; each
+    matches its own oracle run."""
+    cases = [matrix("random", 1), matrix("small_world", 2), (777, inputs.small_world_links(3, 777, 4, 5))]
+    hs, y0s, refs = [], [], []
+    try:
+        for q, (n, (rp, col)) in enumerate(cases):
+            y0 = state("kuramoto", 30 + q, n)
+            hs.append(nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, KUR, row_ptr=rp, col=col)))
+            nd.nd_set_state(hs[-1], y0, on_device=0)
+            y0s.append(y0)
+            refs.append(O.run(O.links(O.KURAMOTO, n, rp, col, np.array(KUR)), y0, 0.01, 12 + q)[0])
+        ring_y0 = inputs.kuramoto_phases(40, 5000)
+        hs.append(nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 5000, KUR, radius=100)))
+        nd.nd_set_state(hs[-1], ring_y0, on_device=0)
+        refs.append(O.run(O.ring(O.KURAMOTO, 5000, 100, KUR), ring_y0, 0.01, 9)[0])
+        y0s.append(ring_y0)
+        nd.nd_run_batch(hs, [0.01] * 4, [12, 13, 14, 9])
+        for h, y0, ref in zip(hs, y0s, refs):
+            y = np.empty_like(y0)
+            nd.nd_get_state(h, y, on_device=0)
+            assert normwise(y, ref, 1) < 1e-12
+    finally:
+        for h in hs:
+            nd.nd_destroy(h)
+
+
+def test_links_compressed_by_oracle_and_extracted_gives_the_same_run(nd):
+    """The oracle's own EXTRACT of its compression as the oracle's input: the
+    GPU run from the original rows agrees with it (the compression is lossless
+    on both sides)."""
+    n, (rp, col) = matrix("small_world", 21)
+    V, D, C = CM.compress(n, rp, col)
+    rp2, col2 = CM.extract_all(n, V, D, C)
+    y0 = state("kuramoto", 5, n)
+    p = nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, KUR, row_ptr=rp, col=col)
+    y, _, _ = nd.simulate(p, y0, 0.01, 20)
+    ref, _, _ = O.run(O.links(O.KURAMOTO, n, rp2, col2, np.array(KUR)), y0, 0.01, 20)
+    assert normwise(y, ref, 1) < 1e-12
