@@ -148,7 +148,8 @@ class Workload:
                          f"(124 neighbours), m=1 eps=0.05 mu=0.01 alpha=0.45 omega=0, RK4 dt=0.05, "
                          f"{args.horizon} steps, planted coherent ball, psi=0")
             self.kernel = "k_cube_stage<inertia>"
-            self.prof = None
+            self.prof = (f"cube_stage_inertia_{args.n}cubed_h2.md", "k_cube_stage",
+                         ["cube.hip", "models.h", "nd_dev.h", "runtime.hip"])
         elif w == "ball":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, args.radius
@@ -159,7 +160,8 @@ class Workload:
                          f"{args.radius} ({self.links} links incl. the element), m=1 eps=0.05 mu=0.01 alpha=0.45 "
                          f"omega=0, RK4 dt=0.05, {args.horizon} steps, planted coherent ball, psi=0")
             self.kernel = "k_ball_stage<inertia>"
-            self.prof = None
+            self.prof = (f"ball_stage_inertia_{args.n}cubed_p{args.radius}.md", "k_ball_stage",
+                         ["cube.hip", "models.h", "nd_dev.h", "runtime.hip"])
         elif w == "links":
             from paper_2410_19075_amd import inputs
             self.n1 = args.n
@@ -171,7 +173,8 @@ class Workload:
                          f"matrix in compressed form (Alg. 2), m=1 eps=0.05 mu=0.01 alpha=0.45 omega=0, "
                          f"RK4 dt=0.05, {args.horizon} steps, planted coherent ball, psi=0")
             self.kernel = "k_links_stage<inertia>"
-            self.prof = None
+            self.prof = (f"links_stage_inertia_{args.n}cubed_ball{args.radius}.md", "k_links_stage",
+                         ["links.hip", "models.h", "nd_dev.h", "runtime.hip"])
         elif w == "cube":
             self.n1 = args.n
             self.n, self.P = args.n ** 3, 4
