@@ -839,7 +839,7 @@ from oracle import compress as CM  # noqa: E402
 
 
 def test_compress_full_mesh_is_all_ones_and_one_empty_entry():
-    """Sec. III.B: a full mesh compresses to a common vector with every bit set
+    """Sec. III.C: a full mesh compresses to a common vector with every bit set
     and a single difference-table entry with no bit set."""
     n = 12
     rp = np.arange(0, n * n + 1, n, dtype=np.int64)
