@@ -708,6 +708,9 @@ nd_status capture_chunk(const Group& g, int K, hipGraphExec_t* out) {
     return ND_OK;
 }
 
+// State values per launch from which a group runs without graph capture.
+constexpr int64_t kEagerValues = int64_t(1) << 20;
+
 // Run a set of networks (possibly of different classes) for their own step counts.
 nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t* steps, const nd_observe* obs,
                    hipStream_t st) {
@@ -777,7 +780,14 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         const int cfg_grid = n0->cfg.grid;
         g.grid = cfg_grid > 0 ? std::min<int>(cfg_grid, (int)work.size()) : (int)work.size();
         const int K = std::max(1, n0->cfg.chunk);
-        if (maxsteps <= K || !graphs_enabled()) {
+        // Replaying a captured chunk saves the host's per-launch cost, which matters
+        // for short kernels; groups whose stage kernels are long (many state values
+        // per launch) run eagerly, which measured a few percent faster per launch.
+        // Rings resident in one workgroup always take the chunked path.
+        int64_t values = 0;
+        for (int q : idx) values += nets[q]->prob.n * nvars_of(nets[q]->prob.model);
+        const bool eager = values >= kEagerValues && !(g.topo == ND_RING && g.tile < 0);
+        if (maxsteps <= K || !graphs_enabled() || eager) {
             // one eager chunk covering every network's steps
             if ((s = enqueue_chunk(g, (int)std::min<int64_t>(maxsteps, 1 << 30), st))) return s;
         } else {

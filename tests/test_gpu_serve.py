@@ -25,6 +25,7 @@ def nd():
 
 def cases(nd):
     rp, col, w = inputs.random_out_graph(9, 600, 12)
+    sw = inputs.small_world_links(5, 1500, 10, 30)
     return [
         (nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 1024, [0.0, 1.0, 1.46], radius=256),
          inputs.kuramoto_phases(1, 1024), 0.01, 150, 1),
@@ -38,6 +39,14 @@ def cases(nd):
                     per_elem=inputs.hh_iapp(9, 600)), inputs.hh_state(9, 600), 0.01, 80, 0),
         (nd.problem(nd.ND_FHN, nd.ND_RING, 20000, FHN_PRM, precision=nd.ND_FP32_BULK, radius=7000),
          inputs.fhn_circle(7, 20000), 0.01, 45, 3),
+        # the paper's 3D inertia model on a ball, its 2D disk, and a compressed coupling matrix
+        (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 12 ** 3, [0.0, 0.5, 0.45, 1.0, 0.05], radius=2,
+                    dims=(12, 12, 12)),
+         np.concatenate([inputs.kuramoto_phases(11, 12 ** 3), np.zeros(12 ** 3)]), 0.05, 40, 4),
+        (nd.problem(nd.ND_KURAMOTO, nd.ND_DISK2D, 20 * 18, [0.0, 1.0, 0.8], radius=3, dims=(20, 18, 1)),
+         inputs.kuramoto_phases(12, 20 * 18), 0.05, 33, 0),
+        (nd.problem(nd.ND_FHN, nd.ND_LINKS, 1500, FHN_PRM, row_ptr=sw[0], col=sw[1]), inputs.fhn_circle(13, 1500),
+         0.01, 55, 5),
     ]
 
 
