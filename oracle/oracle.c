@@ -542,11 +542,56 @@ static const double DP_A[7][6] = {
     {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
 /* fifth minus fourth order weights */
 static const double DP_E[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200, 22.0 / 525, -1.0 / 40};
+/* coefficients of the fourth-order continuous extension (dense output) */
+static const double DP_D[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                               -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                               -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
+
+/* Dense output of an accepted step from (t, y) with stages k[0..6] and size h
+ * (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.6, the continuous
+ * extension of order 4 of the Dormand-Prince pair):
+ *   y(t + theta h) = y + h sum_i b_i(theta) k_i,
+ *   b_i(theta) = theta (b_i + (1 - theta) (e1_i - b_i + theta (2 b_i - e1_i - e7_i + (1 - theta) d_i)))
+ * with b the fifth-order weights, e1 / e7 the first / last unit vectors and d
+ * the coefficients above; b_i(0) = 0 and b_i(1) = b_i. */
+void orc_dopri_dense_weights(double theta, double* wt) {
+    for (int i = 0; i < 7; ++i) {
+        const double b = i < 6 ? DP_A[6][i] : 0.0; /* the fifth-order weights are the last row of A */
+        const double e1 = i == 0 ? 1.0 : 0.0, e7 = i == 6 ? 1.0 : 0.0;
+        wt[i] = theta * (b + (1.0 - theta) * (e1 - b + theta * (2.0 * b - e1 - e7 + (1.0 - theta) * DP_D[i])));
+    }
+}
+
+static int dopri_core(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t n2, int64_t n3,
+                      const int64_t* row_ptr, const int32_t* col, const double* w, const double* prm,
+                      const double* per_elem, double* y, double t_end, double rtol, double atol, double dt0,
+                      int64_t max_steps, double* stats, double t_out, double* Rout, double* Yout);
 
 int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t n2, int64_t n3,
                   const int64_t* row_ptr, const int32_t* col, const double* w, const double* prm,
                   const double* per_elem, double* y, double t_end, double rtol, double atol, double dt0,
                   int64_t max_steps, double* stats) {
+    return dopri_core(model, topo, n, radius, n1, n2, n3, row_ptr, col, w, prm, per_elem, y, t_end, rtol, atol,
+                      dt0, max_steps, stats, 0.0, NULL, NULL);
+}
+
+/* As orc_run_dopri, and at the output times t_k = k t_out, k = 0 .. floor(t_end / t_out),
+ * the order parameter Rout[k] and (Yout non-NULL) the state Yout[k * nvars * n ..] from
+ * the dense output of the accepted step that contains t_k (t_0 = 0: the initial state).
+ * The step that ends on t_end provides every output left, theta clamped to 1. */
+int orc_run_dopri_dense(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t n2, int64_t n3,
+                        const int64_t* row_ptr, const int32_t* col, const double* w, const double* prm,
+                        const double* per_elem, double* y, double t_end, double rtol, double atol, double dt0,
+                        int64_t max_steps, double* stats, double t_out, double* Rout, double* Yout) {
+    if (!(t_out > 0.0) || !Rout) return ORC_EINVAL;
+    return dopri_core(model, topo, n, radius, n1, n2, n3, row_ptr, col, w, prm, per_elem, y, t_end, rtol, atol,
+                      dt0, max_steps, stats, t_out, Rout, Yout);
+}
+
+static int dopri_core(int model, int topo, int64_t n, int64_t radius, int64_t n1, int64_t n2, int64_t n3,
+                      const int64_t* row_ptr, const int32_t* col, const double* w, const double* prm,
+                      const double* per_elem, double* y, double t_end, double rtol, double atol, double dt0,
+                      int64_t max_steps, double* stats, double t_out, double* Rout, double* Yout) {
     orc_net m = make_net(model, topo, n, radius, n1, n2, n3, row_ptr, col, w, prm, per_elem, 0);
     int rc = validate(&m);
     if (rc) return rc;
@@ -567,6 +612,19 @@ int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, in
     (void)DP_C;
     double t = 0.0, h = dt0, facmax = 10.0;
     int64_t acc = 0, rej = 0;
+    const int64_t K = t_out > 0.0 ? (int64_t)floor(t_end / t_out) : -1;
+    int64_t next = 0;
+    double* yt = t_out > 0.0 ? (double*)malloc(sizeof(double) * len) : NULL;
+    if (t_out > 0.0 && !yt) {
+        free(z);
+        for (int s = 0; s < 7; ++s) free(k[s]);
+        return ORC_ENOMEM;
+    }
+    if (K >= 0) {
+        Rout[0] = order_parameter(model, n, y);
+        if (Yout) memcpy(Yout, y, sizeof(double) * len);
+        next = 1;
+    }
     rhs(&m, y, k[0]);
     while (t < t_end && acc + rej < max_steps) {
         /* the step that reaches t_end (within a relative 1e-12 of h) ends on it */
@@ -581,6 +639,39 @@ int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, in
             rhs(&m, z, k[s]);
         }
         /* z now holds the fifth-order solution (stage 7 uses the weights b) */
+        int accept = 1;
+        double f = 1.0;
+        if (rtol > 0.0) {
+            double sum = 0.0;
+            for (int64_t i = 0; i < len; ++i) {
+                double e = 0.0;
+                for (int q = 0; q < 7; ++q) e += DP_E[q] * k[q][i];
+                e *= hs;
+                const double sc = atol + rtol * fmax(fabs(y[i]), fabs(z[i]));
+                sum += (e / sc) * (e / sc);
+            }
+            const double err = sqrt(sum / (double)len);
+            f = 0.9 * pow(err, -0.2);
+            accept = err <= 1.0;
+        }
+        if (accept) {
+            /* outputs inside (t, t + hs]; the last step takes every one left */
+            const double tn = last ? t_end : t + hs;
+            for (; next <= K; ++next) {
+                const double tk = (double)next * t_out;
+                if (tk > tn && !last) break;
+                double theta = (tk - t) / hs, wt[7];
+                if (theta > 1.0) theta = 1.0;
+                orc_dopri_dense_weights(theta, wt);
+                for (int64_t i = 0; i < len; ++i) {
+                    double a = 0.0;
+                    for (int q = 0; q < 7; ++q) a += wt[q] * k[q][i];
+                    yt[i] = y[i] + hs * a;
+                }
+                Rout[next] = order_parameter(model, n, yt);
+                if (Yout) memcpy(Yout + next * len, yt, sizeof(double) * len);
+            }
+        }
         if (rtol <= 0.0) {
             memcpy(y, z, sizeof(double) * len);
             memcpy(k[0], k[6], sizeof(double) * len);
@@ -588,17 +679,7 @@ int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, in
             ++acc;
             continue;
         }
-        double sum = 0.0;
-        for (int64_t i = 0; i < len; ++i) {
-            double e = 0.0;
-            for (int q = 0; q < 7; ++q) e += DP_E[q] * k[q][i];
-            e *= hs;
-            const double sc = atol + rtol * fmax(fabs(y[i]), fabs(z[i]));
-            sum += (e / sc) * (e / sc);
-        }
-        const double err = sqrt(sum / (double)len);
-        const double f = 0.9 * pow(err, -0.2);
-        if (err <= 1.0) {
+        if (accept) {
             memcpy(y, z, sizeof(double) * len);
             memcpy(k[0], k[6], sizeof(double) * len);
             t = last ? t_end : t + hs;
@@ -616,6 +697,7 @@ int orc_run_dopri(int model, int topo, int64_t n, int64_t radius, int64_t n1, in
     stats[2] = (double)rej;
     stats[3] = h;
     free(z);
+    free(yt);
     for (int s = 0; s < 7; ++s) free(k[s]);
     return ORC_OK;
 }

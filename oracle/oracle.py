@@ -39,6 +39,12 @@ def lib():
         L.orc_run_dopri.restype = i32
         L.orc_run_dopri.argtypes = [i32, i32, i64, i64, i64, i64, i64, dp, dp, dp, dp, dp, dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64, dp]
+        L.orc_run_dopri_dense.restype = i32
+        L.orc_run_dopri_dense.argtypes = [i32, i32, i64, i64, i64, i64, i64, dp, dp, dp, dp, dp, dp,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, i64,
+                                          dp, ctypes.c_double, dp, dp]
+        L.orc_dopri_dense_weights.restype = None
+        L.orc_dopri_dense_weights.argtypes = [ctypes.c_double, dp]
         L.orc_order_parameter.restype = ctypes.c_double
         L.orc_order_parameter.argtypes = [i32, i64, dp]
         _LIB = L
@@ -146,3 +152,28 @@ def run_dopri(net, y0, t_end, rtol, atol, dt0, max_steps=10 ** 7):
     if rc != 0:
         raise ValueError(f"oracle dopri run failed ({rc})")
     return y, st[0], int(st[1]), int(st[2]), st[3]
+
+
+def run_dopri_dense(net, y0, t_end, rtol, atol, dt0, t_out, states=False, max_steps=10 ** 7):
+    """Dormand-Prince as run_dopri, plus R (and, with states=True, the state) at the
+    output times k * t_out from the dense output; returns
+    (y, t, accepted, rejected, h_next, R, Y or None)."""
+    y = np.array(y0, dtype=np.float64, copy=True).ravel()
+    K = int(np.floor(t_end / t_out))
+    R = np.full(K + 1, np.nan)
+    Y = np.full((K + 1, y.size), np.nan) if states else None
+    st = np.zeros(4)
+    n1, n2, n3 = net.dims
+    rc = lib().orc_run_dopri_dense(net.model, net.topo, net.n, net.radius, n1, n2, n3, _p(net.row_ptr),
+                                   _p(net.col), _p(net.w), _p(net.params), _p(net.per_elem), _p(y), float(t_end),
+                                   float(rtol), float(atol), float(dt0), int(max_steps), _p(st), float(t_out),
+                                   _p(R), _p(Y))
+    if rc != 0:
+        raise ValueError(f"oracle dense dopri run failed ({rc})")
+    return y, st[0], int(st[1]), int(st[2]), st[3], R, Y
+
+
+def dopri_dense_weights(theta):
+    w = np.empty(7)
+    lib().orc_dopri_dense_weights(float(theta), _p(w))
+    return w

@@ -987,3 +987,57 @@ def test_links_dense_brute_force(model):
     ref = dense_rk4(links_dense(A, model, prm), y0, 0.01, 100)
     y, _, _ = O.run(O.links(model, n, rp, col, np.array(prm)), y0, 0.01, 100)
     assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-12
+
+
+# ------------------------------------------------ Dormand-Prince dense output
+def test_dopri_dense_weights_match_the_library_interpolant():
+    """The fourth-order continuous extension equals scipy's RK45 interpolant
+    (its P matrix) at every theta, vanishes at theta = 0 and gives the
+    fifth-order weights at theta = 1."""
+    from scipy.integrate._ivp.rk import RK45
+    for th in np.linspace(0.0, 1.0, 41):
+        ref = RK45.P @ np.array([th, th ** 2, th ** 3, th ** 4])
+        assert np.max(np.abs(O.dopri_dense_weights(th) - ref)) < 2e-15
+    b = np.array([35 / 384, 0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84, 0])
+    assert np.max(np.abs(O.dopri_dense_weights(1.0) - b)) < 1e-15
+    assert np.all(O.dopri_dense_weights(0.0) == 0.0)
+
+
+def test_dopri_dense_output_follows_the_inertia_closed_form():
+    """mu = 0: the dense outputs between accepted steps follow the damped-rotor
+    closed form to the tolerance's order, and R is the order parameter of the
+    interpolated state."""
+    n, P = 30, 3
+    omega, m, eps = 0.7, 2.5, 0.4
+    phi0 = inputs.kuramoto_phases(15, n)
+    psi0 = inputs.uniform_range(16, inputs.TAG_MISC, n, -1.0, 1.0)
+    net = O.ring(O.INERTIA, n, P, inert(omega, 0.0, 1.0, m, eps))
+    t_end, t_out = 7.3, 0.25
+    y, t, acc, rej, _, R, Y = O.run_dopri_dense(net, np.concatenate([phi0, psi0]), t_end, 1e-10, 1e-12, 1e-3,
+                                                t_out, states=True)
+    K = int(t_end / t_out)
+    assert t == t_end and acc < 3 * K  # steps are longer than the output spacing
+    w = omega / eps
+    for k in range(K + 1):
+        tk = k * t_out
+        decay = math.exp(-eps * tk / m)
+        psi = w + (psi0 - w) * decay
+        phi = phi0 + w * tk + (psi0 - w) * (m / eps) * (1.0 - decay)
+        assert np.max(np.abs(Y[k, n:] - psi)) < 1e-8
+        assert np.max(np.abs(Y[k, :n] - phi)) < 1e-8
+        assert R[k] == pytest.approx(O.order_parameter(O.INERTIA, n, Y[k]), abs=1e-15)
+
+
+def test_dopri_dense_output_at_step_ends_is_the_step_state():
+    """Fixed steps (rtol <= 0) with outputs on step ends: theta = 1 gives the
+    state the solver reached there (a separate run to that time)."""
+    n, P = 40, 9
+    fhn = np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
+    net = O.ring(O.FHN, n, P, fhn)
+    y0 = inputs.fhn_circle(17, n)
+    _, _, acc, _, _, R, Y = O.run_dopri_dense(net, y0, 1.0, -1.0, 0.0, 0.02, 0.1, states=True)
+    assert acc == 50
+    for k in (1, 4, 10):
+        ref, _, _, _, _ = O.run_dopri(net, y0, 0.1 * k, -1.0, 0.0, 0.02)
+        assert np.max(np.abs(Y[k] - ref)) < 1e-12
+    assert np.array_equal(Y[0], y0)
