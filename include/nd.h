@@ -221,6 +221,24 @@ typedef struct nd_adaptive_stats {
 nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end, const double* dt0, double rtol,
                           double atol, int64_t max_steps, nd_adaptive_stats* stats, void* hip_stream);
 
+/* As nd_run_adaptive, with dense output: the trajectory at the output times t_k = k t_out,
+ * k = 0 .. floor(t_end[i] / t_out), taken from the solver's continuous extension of order 4
+ * inside the accepted step that contains t_k (Hairer, Norsett & Wanner, Solving ODEs I,
+ * Sec. II.6), so the outputs do not shorten the steps; t_0 gives the initial state and the
+ * step that ends on t_end provides every output left.  The paper returns trajectories at
+ * specified times and analyses synchronisation at each output (Sec. II, Sec. V; its
+ * Dormand-Prince solvers interpolate between steps, Sec. III.A).
+ * R (host, count * r_stride doubles): R[i * r_stride + k] = order parameter of network i at t_k
+ * (as nd_observe defines it); r_stride >= floor(t_end[i] / t_out) + 1 for every i.
+ * Y (host, may be NULL; count * y_stride doubles): Y[i * y_stride + k * nvars * n + v * n + j]
+ * = variable v of element j at t_k; y_stride >= (outputs of i) * nvars * n_i.
+ * Outputs a network does not reach (max_steps) read NaN.  The device holds R and Y in a
+ * scratch buffer for the call.  Otherwise as nd_run_adaptive. */
+nd_status nd_run_adaptive_dense(const nd_handle* h, int32_t count, const double* t_end, const double* dt0,
+                                double rtol, double atol, int64_t max_steps, double t_out, double* R,
+                                int64_t r_stride, double* Y, int64_t y_stride, nd_adaptive_stats* stats,
+                                void* hip_stream);
+
 /* Differential compression of a binary coupling matrix (Sec. III.C, Alg. 2), as nd_create
  * applies it to ND_LINKS problems; exposed so a caller can inspect the compressed size.
  * Rows are given as for ND_LINKS (row_ptr: n+1 offsets, col: sources).  A circular shift of

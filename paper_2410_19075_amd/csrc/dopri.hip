@@ -37,12 +37,26 @@ __device__ __constant__ double kDpA[7][6] = {
 // fifth- minus fourth-order weights
 __device__ __constant__ double kDpE[7] = {71.0 / 57600, 0, -71.0 / 16695, 71.0 / 1920, -17253.0 / 339200,
                                            22.0 / 525, -1.0 / 40};
+// continuous extension of order 4 (dense output; Hairer, Norsett & Wanner, Solving ODEs I, II.6)
+__device__ __constant__ double kDpD[7] = {-12715105075.0 / 11282082432.0, 0.0, 87487479700.0 / 32700410799.0,
+                                           -10690763975.0 / 1880347072.0, 701980252875.0 / 199316789632.0,
+                                           -1453857185.0 / 822651844.0, 69997945.0 / 29380423.0};
 }  // namespace
 
-template <int MODEL>
+// Where the dense output goes: R (and optionally the state) of network b at
+// output k is R[b * r_stride + k] (Y[b * y_stride + k * V * n + v * n + i]).
+struct DenseOut {
+    double t_out;  // output spacing (> 0: outputs at k * t_out, k = 0 .. floor(t_end / t_out))
+    double* R;
+    int64_t r_stride;
+    double* Y;     // may be NULL
+    int64_t y_stride;
+};
+
+template <int MODEL, bool DENSE>
 __global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict__ D,
                                                       const double* __restrict__ t_end, double rtol, double atol,
-                                                      int64_t max_steps, double* __restrict__ stats) {
+                                                      int64_t max_steps, double* __restrict__ stats, DenseOut out) {
     using M = RingModel<MODEL, double>;
     constexpr int V = M::V, T = kDpCap, EPT = kDpEPT, NW = kDpBS / kWave;
     __shared__ double pf[2 * T];  // inclusive prefix sums of the two map components
@@ -105,10 +119,52 @@ __global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict_
         }
         lds_barrier();  // pf is rewritten by the next stage
     };
+    // dense output k: the state y + hs sum_q w_q(theta) k_q (theta = 0: y itself), its
+    // order parameter by a fixed-order block reduction
+    auto emit = [&](int64_t kout, double theta, double hs) {
+        double wt[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double b = q < 6 ? kDpA[6][q] : 0.0, e1 = q == 0 ? 1.0 : 0.0, e7 = q == 6 ? 1.0 : 0.0;
+            wt[q] = theta * (b + (1.0 - theta) * (e1 - b + theta * (2.0 * b - e1 - e7 + (1.0 - theta) * kDpD[q])));
+        }
+        double s2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid * EPT + e;
+            if (i >= n) continue;
+            double yt[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                double a = 0.0;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) a += wt[q] * k[q][e][v];
+                yt[v] = theta == 0.0 ? y[e][v] : y[e][v] + hs * a;
+                if (out.Y) gp(out.Y)[blockIdx.x * out.y_stride + kout * V * n + (int64_t)v * n + i] = yt[v];
+            }
+            if constexpr (MODEL == ND_FHN) {
+                const double r = sqrt(yt[0] * yt[0] + yt[1] * yt[1]);
+                s2[0] += yt[0] / r;
+                s2[1] += yt[1] / r;
+            } else {
+                const double2 x = M::map(yt);
+                s2[0] += x.x;
+                s2[1] += x.y;
+            }
+        }
+        block_sum<kDpBS, 2>(s2, lds);
+        if (tid == 0) gp(out.R)[blockIdx.x * out.r_stride + kout] = sqrt(s2[0] * s2[0] + s2[1] * s2[1]) / (double)n;
+    };
     slopes(y, k[0]);
     const double tend = t_end[blockIdx.x];
     double t = 0.0, h = d.dt, facmax = 10.0;
     int64_t acc = 0, rej = 0;
+    const int64_t K = DENSE ? (int64_t)floor(tend / out.t_out) : -1;
+    int64_t next = 0;
+    if (DENSE && K >= 0) {
+        emit(0, 0.0, 0.0);
+        next = 1;
+    }
     // every wave leaves the loop together: t, h and the counters are uniform
     while (t < tend && acc + rej < max_steps) {
         const bool last = tend - t <= h * (1.0 + 1e-12);
@@ -151,6 +207,15 @@ __global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict_
             accept = err <= 1.0;
         }
         if (accept) {
+            if constexpr (DENSE) {
+                // outputs inside (t, t + hs]; the last step takes every one left
+                const double tn = last ? tend : t + hs;
+                for (; next <= K; ++next) {
+                    const double tk = (double)next * out.t_out;
+                    if (tk > tn && !last) break;
+                    emit(next, fmin((tk - t) / hs, 1.0), hs);
+                }
+            }
 #pragma unroll
             for (int e = 0; e < EPT; ++e)
 #pragma unroll
@@ -189,13 +254,16 @@ __global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict_
 
 using namespace nd;
 
-extern "C" nd_status nd_run_adaptive(const nd_handle* hs, int32_t count, const double* t_end, const double* dt0,
-                                     double rtol, double atol, int64_t max_steps, nd_adaptive_stats* stats,
-                                     void* stream) {
+static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* t_end, const double* dt0,
+                              double rtol, double atol, int64_t max_steps, nd_adaptive_stats* stats, void* stream,
+                              double t_out, double* R, int64_t r_stride, double* Y, int64_t y_stride) {
     if (!hs || !t_end || !dt0 || !stats || count < 0) return fail(ND_ERR_INVALID_ARG, "bad adaptive-run arguments");
     if (!std::isfinite(rtol) || !std::isfinite(atol) || atol < 0.0 || (rtol > 0.0 && atol == 0.0))
         return fail(ND_ERR_INVALID_ARG, "rtol must be finite; atol finite, and > 0 when rtol > 0");
     if (max_steps < 0) return fail(ND_ERR_INVALID_ARG, "max_steps must be >= 0");
+    const bool dense = t_out != 0.0;
+    if (dense && (!(t_out > 0.0) || !std::isfinite(t_out) || !R || r_stride < 1))
+        return fail(ND_ERR_INVALID_ARG, "dense output needs t_out > 0, R and r_stride >= 1");
     if (count == 0) return ND_OK;
     int model = -1;
     std::vector<NetDesc> descs(count);
@@ -209,30 +277,46 @@ extern "C" nd_status nd_run_adaptive(const nd_handle* hs, int32_t count, const d
         model = n->prob.model;
         if (!(t_end[i] >= 0.0) || !std::isfinite(t_end[i]) || !(dt0[i] > 0.0) || !std::isfinite(dt0[i]))
             return fail(ND_ERR_INVALID_ARG, "t_end must be finite and >= 0, dt0 finite and > 0 (network %d)", i);
+        if (dense) {
+            const int64_t outs = (int64_t)std::floor(t_end[i] / t_out) + 1;
+            if (outs > r_stride)
+                return fail(ND_ERR_INVALID_ARG, "network %d has %lld outputs, r_stride is %lld", i, (long long)outs,
+                            (long long)r_stride);
+            if (Y && outs * nvars_of(n->prob.model) * n->prob.n > y_stride)
+                return fail(ND_ERR_INVALID_ARG, "network %d needs y_stride >= %lld", i,
+                            (long long)(outs * nvars_of(n->prob.model) * n->prob.n));
+        }
         descs[i] = n->run_desc(dt0[i], 0);
     }
     hipStream_t st = (hipStream_t)stream;
     void* buf = nullptr;
     const size_t bd = (size_t)count * sizeof(NetDesc), bt = (size_t)count * 8, bs = (size_t)count * 32;
-    hipError_t e = hipMallocAsync(&buf, bd + bt + bs, st);
+    const size_t br = dense ? (size_t)count * r_stride * 8 : 0, by = dense && Y ? (size_t)count * y_stride * 8 : 0;
+    hipError_t e = hipMallocAsync(&buf, bd + bt + bs + br + by, st);
     if (e != hipSuccess) return hip_fail(e, "adaptive scratch");
     NetDesc* d_desc = (NetDesc*)buf;
     double* d_tend = (double*)((char*)buf + bd);
     double* d_stats = (double*)((char*)buf + bd + bt);
+    DenseOut o{dense ? t_out : 0.0, dense ? (double*)((char*)buf + bd + bt + bs) : nullptr, r_stride,
+               by ? (double*)((char*)buf + bd + bt + bs + br) : nullptr, y_stride};
     std::vector<double> h_stats((size_t)count * 4);
-    if ((e = hipMemcpyAsync(d_desc, descs.data(), bd, hipMemcpyHostToDevice, st)) == hipSuccess &&
+    // outputs a run does not reach (max_steps) read as NaN (all bits set)
+    if (dense) e = hipMemsetAsync(o.R, 0xff, br + by, st);
+    if (e == hipSuccess && (e = hipMemcpyAsync(d_desc, descs.data(), bd, hipMemcpyHostToDevice, st)) == hipSuccess &&
         (e = hipMemcpyAsync(d_tend, t_end, bt, hipMemcpyHostToDevice, st)) == hipSuccess) {
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol, max_steps, d_stats, o);
+        };
         if (model == ND_KURAMOTO)
-            hipLaunchKernelGGL(k_ring_dopri<ND_KURAMOTO>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol,
-                               max_steps, d_stats);
+            dense ? launch(k_ring_dopri<ND_KURAMOTO, true>) : launch(k_ring_dopri<ND_KURAMOTO, false>);
         else if (model == ND_FHN)
-            hipLaunchKernelGGL(k_ring_dopri<ND_FHN>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol,
-                               max_steps, d_stats);
+            dense ? launch(k_ring_dopri<ND_FHN, true>) : launch(k_ring_dopri<ND_FHN, false>);
         else
-            hipLaunchKernelGGL(k_ring_dopri<ND_KURAMOTO_INERTIA>, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend,
-                               rtol, atol, max_steps, d_stats);
+            dense ? launch(k_ring_dopri<ND_KURAMOTO_INERTIA, true>) : launch(k_ring_dopri<ND_KURAMOTO_INERTIA, false>);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(h_stats.data(), d_stats, bs, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && dense) e = hipMemcpyAsync(R, o.R, br, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && by) e = hipMemcpyAsync(Y, o.Y, by, hipMemcpyDeviceToHost, st);
     }
     const hipError_t ef = hipFreeAsync(buf, st);
     const hipError_t es = hipStreamSynchronize(st);
@@ -246,4 +330,18 @@ extern "C" nd_status nd_run_adaptive(const nd_handle* hs, int32_t count, const d
         stats[i].h_next = h_stats[4 * i + 3];
     }
     return ND_OK;
+}
+
+extern "C" nd_status nd_run_adaptive(const nd_handle* hs, int32_t count, const double* t_end, const double* dt0,
+                                     double rtol, double atol, int64_t max_steps, nd_adaptive_stats* stats,
+                                     void* stream) {
+    return run_adaptive(hs, count, t_end, dt0, rtol, atol, max_steps, stats, stream, 0.0, nullptr, 0, nullptr, 0);
+}
+
+extern "C" nd_status nd_run_adaptive_dense(const nd_handle* hs, int32_t count, const double* t_end,
+                                           const double* dt0, double rtol, double atol, int64_t max_steps,
+                                           double t_out, double* R, int64_t r_stride, double* Y, int64_t y_stride,
+                                           nd_adaptive_stats* stats, void* stream) {
+    if (!(t_out > 0.0)) return fail(ND_ERR_INVALID_ARG, "t_out must be > 0");
+    return run_adaptive(hs, count, t_end, dt0, rtol, atol, max_steps, stats, stream, t_out, R, r_stride, Y, y_stride);
 }

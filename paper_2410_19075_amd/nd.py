@@ -90,6 +90,8 @@ _sig = {
     "nd_run_batch": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_i64), _P(nd_observe), _c_vp],
     "nd_run_adaptive": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _P(nd_adaptive_stats),
                         _c_vp],
+    "nd_run_adaptive_dense": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _c_dbl, _c_vp,
+                              _c_i64, _c_vp, _c_i64, _P(nd_adaptive_stats), _c_vp],
     "nd_get_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_compress_links": [_c_i64, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64,
                           _P(nd_links_info)],
@@ -249,6 +251,27 @@ def nd_compress_links(n, row_ptr, col):
                                   dptr.ctypes.data, dptr.size, dpos.ctypes.data, dpos.size, C.ctypes.data, C.size,
                                   ctypes.byref(info)), "nd_compress_links")
     return V, dptr, dpos, C, info
+
+
+def nd_run_adaptive_dense(handles, t_end, dt0, rtol, atol, t_out, state_len=0, max_steps=10 ** 7, stream=None):
+    """Dormand-Prince with dense output: returns (stats, R, Y) with R[i, k] the order
+    parameter of network i at k * t_out and, when state_len (the largest nvars * n of
+    the networks) is given, Y[i, k * nvars * n_i + v * n_i + j] its state there (NaN
+    where a network does not reach the output)."""
+    k = len(handles)
+    hs = (_c_vp * k)(*handles)
+    te = (_c_dbl * k)(*[float(x) for x in t_end])
+    d0 = (_c_dbl * k)(*[float(x) for x in dt0])
+    st = (nd_adaptive_stats * k)()
+    # (a t_out <= 0 is passed on for the library to reject)
+    outs = int(np.max(np.floor(np.asarray(t_end, dtype=np.float64) / t_out))) + 1 if k and t_out > 0 else 1
+    R = np.empty((k, outs))
+    ys = outs * int(state_len)
+    Y = np.empty((k, ys)) if state_len else None
+    _check(_lib.nd_run_adaptive_dense(hs, k, te, d0, float(rtol), float(atol), int(max_steps), float(t_out),
+                                      R.ctypes.data, outs, Y.ctypes.data if Y is not None else None, ys, st,
+                                      _stream(stream)), "nd_run_adaptive_dense")
+    return list(st), R, Y
 
 
 def nd_get_observables(h, R=None, mean_vel=None, on_device=None, stream=None):

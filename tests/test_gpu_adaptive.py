@@ -129,3 +129,89 @@ def test_adaptive_rejects_unsupported(nd):
             nd.nd_run_adaptive([h], [1.0], [1e-3], 1e-6, 0.0)  # atol must be > 0 with rtol > 0
     finally:
         nd.nd_destroy(h)
+
+
+# ---------------------------------------------------------------- dense output
+@pytest.mark.parametrize("model,n,P,t_end,rtol,t_out", [("kuramoto", 1000, 300, 5.0, 1e-8, 0.1),
+                                                        ("fhn", 512, 179, 2.0, 1e-7, 0.05),
+                                                        ("inertia", 777, 200, 4.0, 1e-9, 0.3)])
+def test_dense_output_matches_oracle(nd, model, n, P, t_end, rtol, t_out):
+    """R and the state at every output time from the continuous extension, and
+    the same steps as without outputs."""
+    print(f"case dense {model} n={n} t_out={t_out}", flush=True)
+    p, onet, y0, nv = net(nd, model, n, P, 5 * n + P)
+    h = nd.nd_create(p)
+    try:
+        nd.nd_set_state(h, y0, on_device=0)
+        (st,), R, Y = nd.nd_run_adaptive_dense([h], [t_end], [1e-3], rtol, rtol * 1e-2, t_out, state_len=nv * n)
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    ref, t, acc, rej, _, Rref, Yref = O.run_dopri_dense(onet, y0, t_end, rtol, rtol * 1e-2, 1e-3, t_out, states=True)
+    assert (st.accepted, st.rejected) == (acc, rej) and st.t == t
+    K = int(np.floor(t_end / t_out))
+    assert R.shape == (1, K + 1) and not np.any(np.isnan(R))
+    # the step sizes agree to the rounding of err^(-1/5), so the outputs, which
+    # interpolate inside those steps, are held to 1e-9 (the interpolant's own
+    # error at these tolerances is ~1e-8)
+    assert np.max(np.abs(R[0] - Rref)) < 1e-9
+    Yg = Y[0].reshape(K + 1, nv * n)
+    for k in range(K + 1):
+        assert normwise(Yg[k], Yref[k], nv) < 1e-9
+    assert normwise(y, ref, nv) < 1e-10
+
+
+def test_dense_output_batch_and_budget(nd):
+    """Rings with different horizons in one call: each gets its own number of
+    outputs (the rest of its row untouched by the run reads NaN); a ring whose
+    step budget runs out leaves its later outputs NaN."""
+    cases = [(600, 100, 3.0), (256, 40, 1.2), (1024, 300, 0.0)]
+    probs, onets, y0s = [], [], []
+    for i, (n, P, _) in enumerate(cases):
+        p, onet, y0, _ = net(nd, "kuramoto", n, P, 70 + i)
+        probs.append(p)
+        onets.append(onet)
+        y0s.append(y0)
+    hs = [nd.nd_create(p) for p in probs]
+    try:
+        for h, y0 in zip(hs, y0s):
+            nd.nd_set_state(h, y0, on_device=0)
+        st, R, _ = nd.nd_run_adaptive_dense(hs, [c[2] for c in cases], [1e-3] * 3, 1e-8, 1e-10, 0.2)
+    finally:
+        for h in hs:
+            nd.nd_destroy(h)
+    assert R.shape == (3, 16)
+    for i, (c, onet, y0) in enumerate(zip(cases, onets, y0s)):
+        _, _, acc, rej, _, Rref, _ = O.run_dopri_dense(onet, y0, c[2], 1e-8, 1e-10, 1e-3, 0.2)
+        K = int(np.floor(c[2] / 0.2))
+        assert (st[i].accepted, st[i].rejected) == (acc, rej)
+        assert np.max(np.abs(R[i, :K + 1] - Rref)) < 1e-9
+        assert np.all(np.isnan(R[i, K + 1:]))
+    p, onet, y0, _ = net(nd, "fhn", 300, 60, 9)
+    h = nd.nd_create(p)
+    try:
+        nd.nd_set_state(h, y0, on_device=0)
+        (s1,), R1, _ = nd.nd_run_adaptive_dense([h], [50.0], [1e-3], 1e-8, 1e-10, 0.5, max_steps=40)
+    finally:
+        nd.nd_destroy(h)
+    _, t, _, _, _, Rref, _ = O.run_dopri_dense(onet, y0, 50.0, 1e-8, 1e-10, 1e-3, 0.5, max_steps=40)
+    reached = ~np.isnan(Rref)
+    assert s1.t < 50.0 and np.array_equal(~np.isnan(R1[0]), reached)
+    assert np.max(np.abs(R1[0][reached] - Rref[reached])) < 1e-8
+
+
+def test_dense_output_rejects_bad_arguments(nd):
+    h = nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 100, KUR, radius=10))
+    try:
+        with pytest.raises(nd.NDError):
+            nd.nd_run_adaptive_dense([h], [1.0], [1e-3], 1e-6, 1e-9, 0.0)
+        hs = (nd._c_vp * 1)(h)
+        te = (nd._c_dbl * 1)(1.0)
+        d0 = (nd._c_dbl * 1)(1e-3)
+        st = (nd.nd_adaptive_stats * 1)()
+        R = np.empty(5)
+        rc = nd._lib.nd_run_adaptive_dense(hs, 1, te, d0, 1e-6, 1e-9, 1000, 0.1, R.ctypes.data, 5, None, 0, st, None)
+        assert rc == nd.ND_ERR_INVALID_ARG  # 11 outputs do not fit r_stride 5
+    finally:
+        nd.nd_destroy(h)
