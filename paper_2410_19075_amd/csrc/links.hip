@@ -17,14 +17,14 @@
 // of D_k that V holds, plus those it does not:
 //   sum_{j in row i} x_j = sum_{p in V} x_{i+p} + sum_{p in D_k} s_kp x_{i+p},
 //   s_kp = -1 if p in V else +1   (indices mod n).
-// V is stored as maximal runs of consecutive positions (uniform over a
-// workgroup: every lane walks the same runs over consecutive elements, so the
-// gathers of a wave are contiguous); each entry of the table as its signed
-// positions.  The exchanged values x_j = map(z_j) of the stage (Kuramoto:
+// V is stored as its positions (uniform over a workgroup: every lane walks
+// the same positions from consecutive elements, so the gathers of a wave are
+// contiguous, and several are in flight per lane); each entry of the table as
+// its signed positions.  The exchanged values x_j = map(z_j) of the stage (Kuramoto:
 // (cos z, sin z); FHN: (u, v)) are written once per element by the previous
 // stage, so every gather reads one vector and no sin/cos is evaluated per
-// link.  One thread per element adds its row's terms in a fixed order (the
-// runs in ascending order, then the entry's positions), evaluates the RHS with
+// link.  One thread per element adds its row's terms in a fixed order (V's
+// positions ascending, then the entry's positions), evaluates the RHS with
 // the sum divided by the row's link count, does the 13-access RK bookkeeping
 // and writes the map of its next stage value.
 #include <algorithm>
@@ -144,15 +144,8 @@ nd_status compress_links(int64_t n, const int64_t* row_ptr, const int32_t* col, 
     return ND_OK;
 }
 
-// Device form: runs of V, signed entry positions, 1 / link count per entry.
+// Device form of the table: signed entry positions, 1 / link count per entry.
 void links_device_form(const LinksCompressed& c, LinksDeviceForm* f) {
-    f->runs.clear();
-    for (size_t q = 0; q < c.V.size();) {
-        size_t e = q + 1;
-        while (e < c.V.size() && c.V[e] == c.V[e - 1] + 1) ++e;
-        f->runs.push_back(make_int2(c.V[q], (int)(e - q)));
-        q = e;
-    }
     const size_t K = c.dptr.size() - 1;
     f->dptr.assign(K + 1, 0);
     f->dsig.assign(c.dpos.size(), 0);
@@ -171,10 +164,8 @@ void links_device_form(const LinksCompressed& c, LinksDeviceForm* f) {
 }
 
 int64_t links_device_bytes(const LinksCompressed& c) {
-    int64_t runs = 0;
-    for (size_t q = 0; q < c.V.size(); ++q) runs += (q == 0 || c.V[q] != c.V[q - 1] + 1);
     const int64_t K = (int64_t)c.dptr.size() - 1;
-    return runs * 8 + (K + 1) * 4 + (int64_t)c.dpos.size() * 4 + K * 8 + c.n * 4;
+    return (int64_t)c.V.size() * 4 + (K + 1) * 4 + (int64_t)c.dpos.size() * 4 + K * 8 + c.n * 4;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -182,7 +173,6 @@ int64_t links_device_bytes(const LinksCompressed& c) {
 // directly (one 16- or 8-byte access).
 typedef double ldv2 __attribute__((ext_vector_type(2)));
 typedef float lfv2 __attribute__((ext_vector_type(2)));
-typedef int liv2 __attribute__((ext_vector_type(2)));
 
 template <int MODEL, class KT>
 struct LinksTypes {
@@ -288,19 +278,18 @@ __global__ __launch_bounds__(256) void k_links_stage(const NetDesc* __restrict__
         double wx = 0.0, wy = 0.0;
         double inv = 0.0;
         if (valid) {
-            const ND_GLOBAL liv2* __restrict__ runs = gp((const liv2*)d.lruns);
-            const int nruns = d.lnruns;
-            for (int r = 0; r < nruns; ++r) {
-                const liv2 run = runs[r];
-                uint32_t jj = ui + (uint32_t)run.x;
+            // the common vector's positions are uniform over the workgroup (scalar
+            // loads); the gathers of consecutive positions are independent, so
+            // several are in flight per lane
+            const ND_GLOBAL int32_t* __restrict__ vpos = gp(d.lvpos);
+            const int nv = d.lnv;
+#pragma unroll 8
+            for (int q = 0; q < nv; ++q) {
+                uint32_t jj = ui + (uint32_t)vpos[q];
                 if (jj >= un) jj -= un;
-#pragma unroll 4
-                for (int q = 0; q < run.y; ++q) {
-                    const MT2 x = ld32(mi, jj);
-                    wx += (double)x.x;
-                    wy += (double)x.y;
-                    jj = jj + 1 == un ? 0u : jj + 1;
-                }
+                const MT2 x = ld32(mi, jj);
+                wx += (double)x.x;
+                wy += (double)x.y;
             }
             const int k = ld32(gp(d.lrow), ui);
             const int e0 = ld32(gp(d.ldptr), (uint32_t)k), e1 = ld32(gp(d.ldptr), (uint32_t)k + 1);

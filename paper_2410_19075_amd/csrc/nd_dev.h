@@ -41,11 +41,11 @@ struct NetDesc {
     double* acc_part;        // CSR: per source block synaptic partial sums [blocks][n]
     const double* iapp;
     const int32_t* lrow;     // links: difference-table entry of every row
-    const int2* lruns;       // links: runs (first position, length) of the common vector
     const int32_t* ldptr;    // links: entry k's positions at [ldptr[k], ldptr[k+1])
     const int32_t* ldpos;    // links: position, | kLinksRemove when V holds it
     const double* linv;      // links: 1 / link count of the rows of entry k (0: no links)
-    int32_t lnruns;          // links: number of runs
+    const int32_t* lvpos;    // links: positions of the common vector, ascending
+    int32_t lnv;             // links: number of positions of the common vector
     double* R;          // order parameter per recorded step
     int64_t r_every;
     double* mv;         // mean phase velocity accumulator / result

@@ -141,7 +141,6 @@ struct LinksCompressed {
     std::vector<int32_t> C;     // entry of every row
 };
 struct LinksDeviceForm {
-    std::vector<int2> runs;     // maximal runs of consecutive positions of V
     std::vector<int32_t> dptr;  // as LinksCompressed::dptr
     std::vector<int32_t> dsig;  // positions, | kLinksRemove where V holds the position
     std::vector<double> inv;    // 1 / link count per entry (0 for an empty row)

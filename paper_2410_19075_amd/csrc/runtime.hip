@@ -447,16 +447,15 @@ nd_status Net::create(const nd_problem* pr) {
         links_device_form(lc, &f);
         const size_t K = f.inv.size();
         if ((s = alloc((void**)&d.lrow, n * 4))) return s;
-        if ((s = alloc((void**)&d.lruns, f.runs.size() * sizeof(int2)))) return s;
+        if ((s = alloc((void**)&d.lvpos, lc.V.size() * 4))) return s;
         if ((s = alloc((void**)&d.ldptr, (K + 1) * 4))) return s;
         if ((s = alloc((void**)&d.ldpos, f.dsig.size() * 4))) return s;
         if ((s = alloc((void**)&d.linv, K * 8))) return s;
         for (int b = 0; b < 2; ++b)
             if ((s = alloc(&d.sx[b], n * (int64_t)links_map_bytes(pr->model, pr->precision)))) return s;
-        d.lnruns = (int32_t)f.runs.size();
+        d.lnv = (int32_t)lc.V.size();
         HIPC(hipMemcpy((void*)d.lrow, lc.C.data(), n * 4, hipMemcpyHostToDevice));
-        if (!f.runs.empty())
-            HIPC(hipMemcpy((void*)d.lruns, f.runs.data(), f.runs.size() * sizeof(int2), hipMemcpyHostToDevice));
+        if (!lc.V.empty()) HIPC(hipMemcpy((void*)d.lvpos, lc.V.data(), lc.V.size() * 4, hipMemcpyHostToDevice));
         HIPC(hipMemcpy((void*)d.ldptr, f.dptr.data(), (K + 1) * 4, hipMemcpyHostToDevice));
         if (!f.dsig.empty()) HIPC(hipMemcpy((void*)d.ldpos, f.dsig.data(), f.dsig.size() * 4, hipMemcpyHostToDevice));
         HIPC(hipMemcpy((void*)d.linv, f.inv.data(), K * 8, hipMemcpyHostToDevice));

@@ -210,7 +210,8 @@ def test_links_paper_3d_radius_6_table_is_small():
     rp, col = inputs.lattice_ball_links(n1, n1, n1, 6)
     _, _, _, _, info = nd.nd_compress_links(n1 ** 3, rp, col)
     assert info.v_bits == 925 and info.entries == 169
-    assert info.bytes < 4 * n1 ** 3 + 169 * 8 + 4 * info.d_bits + 8 * info.runs + 4 * 170 + 1
+    # V's positions, the table (offsets, positions, 1/links) and one entry index per row
+    assert info.bytes == 4 * 925 + 4 * 170 + 4 * info.d_bits + 8 * 169 + 4 * n1 ** 3
 
 
 @pytest.mark.parametrize("bad", ["duplicate", "range", "decreasing"])
