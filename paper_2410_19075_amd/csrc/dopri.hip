@@ -54,9 +54,9 @@ struct DenseOut {
 };
 
 template <int MODEL, bool DENSE>
-__global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict__ D,
-                                                      const double* __restrict__ t_end, double rtol, double atol,
-                                                      int64_t max_steps, double* __restrict__ stats, DenseOut out) {
+__device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const double* __restrict__ t_end,
+                                           double rtol, double atol, int64_t max_steps, double* __restrict__ stats,
+                                           DenseOut out) {
     using M = RingModel<MODEL, double>;
     constexpr int V = M::V, T = kDpCap, EPT = kDpEPT, NW = kDpBS / kWave;
     __shared__ double pf[2 * T];  // inclusive prefix sums of the two map components
@@ -250,6 +250,21 @@ __global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict_
     }
 }
 
+template <int MODEL, bool DENSE>
+__global__ __launch_bounds__(kDpBS) void k_ring_dopri(const NetDesc* __restrict__ D,
+                                                      const double* __restrict__ t_end, double rtol, double atol,
+                                                      int64_t max_steps, double* __restrict__ stats, DenseOut out) {
+    ring_dopri<MODEL, DENSE>(D, t_end, rtol, atol, max_steps, stats, out);
+}
+
+// The Kuramoto ring without dense output fits 128 registers per lane, so two
+// rings (workgroups of 8 waves) share a CU and hide each other's barriers.
+__global__ __launch_bounds__(kDpBS) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_dopri_kuramoto(
+    const NetDesc* __restrict__ D, const double* __restrict__ t_end, double rtol, double atol, int64_t max_steps,
+    double* __restrict__ stats, DenseOut out) {
+    ring_dopri<ND_KURAMOTO, false>(D, t_end, rtol, atol, max_steps, stats, out);
+}
+
 }  // namespace nd
 
 using namespace nd;
@@ -308,7 +323,7 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
             hipLaunchKernelGGL(kern, dim3(count), dim3(kDpBS), 0, st, d_desc, d_tend, rtol, atol, max_steps, d_stats, o);
         };
         if (model == ND_KURAMOTO)
-            dense ? launch(k_ring_dopri<ND_KURAMOTO, true>) : launch(k_ring_dopri<ND_KURAMOTO, false>);
+            dense ? launch(k_ring_dopri<ND_KURAMOTO, true>) : launch(k_ring_dopri_kuramoto);
         else if (model == ND_FHN)
             dense ? launch(k_ring_dopri<ND_FHN, true>) : launch(k_ring_dopri<ND_FHN, false>);
         else
