@@ -297,6 +297,16 @@ def run(nd, torch, wl, args, prec, stream):
     return wall, times, ev_total, finite, cfgd
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, args):
     """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
     from oracle import oracle as O
@@ -326,6 +336,7 @@ def cpu_baseline(wl, args):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": wl.n * steps / dt, "unit": "oscillator-steps/s", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{what}, {steps} RK4 step(s), FP64, direct neighbour sums, {dt:.2f} s"}
 
 
@@ -534,7 +545,7 @@ def main_adaptive(nd, torch, args, stream):
         sec = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {"value": oacc * n / sec, "unit": "oscillator-steps/s", "cores": cores,
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
                                "sample": f"one Kuramoto ring N={n} P={P}, Dormand-Prince 5(4) to t={t_end}, "
                                          f"{oacc} accepted / {orej} rejected steps, FP64, {sec:.2f} s"}
     print(json.dumps(out), flush=True)
