@@ -196,3 +196,21 @@ def test_links_compressed_by_oracle_and_extracted_gives_the_same_run(nd):
     y, _, _ = nd.simulate(p, y0, 0.01, 20)
     ref, _, _ = O.run(O.links(O.KURAMOTO, n, rp2, col2, np.array(KUR)), y0, 0.01, 20)
     assert normwise(y, ref, 1) < 1e-12
+
+
+def test_links_matrix_without_links(nd):
+    """No links at all (nnz = 0, no col array): every element rotates freely at
+    omega, and FHN elements follow their local dynamics."""
+    n = 300
+    rp = np.zeros(n + 1, dtype=np.int64)
+    y0 = inputs.kuramoto_phases(3, n)
+    p = nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, [0.3, 1.0, 0.9], row_ptr=rp)
+    y, R, _ = nd.simulate(p, y0, 0.01, 50, record_every=10)
+    assert np.max(np.abs(y - (y0 + 0.3 * 0.5))) < 1e-13
+    ref, Rref, _ = O.run(O.links(O.KURAMOTO, n, rp, np.zeros(0, dtype=np.int32), np.array([0.3, 1.0, 0.9])), y0,
+                         0.01, 50, record_every=10)
+    assert np.max(np.abs(R - Rref)) < 1e-13
+    f0 = state("fhn", 4, n)
+    a, _, _ = nd.simulate(nd.problem(nd.ND_FHN, nd.ND_LINKS, n, FHN, row_ptr=rp), f0, 0.01, 40)
+    b, _, _ = O.run(O.links(O.FHN, n, rp, np.zeros(0, dtype=np.int32), np.array(FHN)), f0, 0.01, 40)
+    assert normwise(a, b, 2) < 1e-12
