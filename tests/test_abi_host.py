@@ -185,10 +185,10 @@ def test_links_compression_matches_the_oracle(case):
         rp = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64)
         col = np.concatenate(rows).astype(np.int32)
     V, dptr, dpos, C, info = nd.nd_compress_links(n, rp, col)
-    V2, D2, C2 = _oracle_compress(n, rp, col)
-    assert list(V) == V2 and np.array_equal(C, C2)
-    assert info.entries == len(D2) and [list(dpos[dptr[k]:dptr[k + 1]]) for k in range(info.entries)] == D2
-    assert info.v_bits == len(V2) and info.d_bits == sum(len(d) for d in D2)
+    Vo, Do, Co = _oracle_compress(n, rp, col)
+    assert list(V) == Vo and np.array_equal(C, Co)
+    assert info.entries == len(Do) and [list(dpos[dptr[k]:dptr[k + 1]]) for k in range(info.entries)] == Do
+    assert info.v_bits == len(Vo) and info.d_bits == sum(len(d) for d in Do)
 
 
 def test_links_unsorted_rows_compress_like_sorted_ones():

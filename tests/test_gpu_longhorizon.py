@@ -47,10 +47,10 @@ def stats_gap(a, b, half):
     return dR, dmv, float(np.max(np.abs(Ra - Rb)))
 
 
-@pytest.mark.parametrize("case", ["kuramoto_c1", "fhn_c2"])
+@pytest.mark.parametrize("case", ["kuramoto_ring_1024", "fhn_ring_65536"])
 def test_fp32_bulk_long_horizon_statistics(nd, case):
     from paper_2410_19075_amd import inputs
-    if case == "kuramoto_c1":
+    if case == "kuramoto_ring_1024":
         n, P, steps = 1024, 256, 20000
         mk = lambda prec: nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, [0.0, 1.0, 1.46], precision=prec, radius=P)
         y0 = inputs.kuramoto_phases(1, n)

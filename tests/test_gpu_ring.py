@@ -59,7 +59,7 @@ def run_with_config(nd, p, y0, dt, steps, tile=None, grid=None, chunk=None, reco
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
-def test_c1_kuramoto_ring_fp64_parity(nd, seed):
+def test_kuramoto_ring_1024_fp64_parity(nd, seed):
     """Kuramoto ring N=1024, P=256, alpha=1.46, dt=0.01, 200 steps, FP64: final
     phases and R(t) at every step within 1e-12 of the oracle."""
     n, P, prm = 1024, 256, [0.0, 1.0, 1.46]
@@ -107,7 +107,7 @@ def test_twisted_state_rotates_rigidly_on_gpu(nd, q):
     assert np.max(np.abs(R - (1.0 if q == 0 else 0.0))) < 1e-12
 
 
-def test_fhn_ring_fp64_parity_c2_shape(nd):
+def test_fhn_ring_fp64_parity_65536(nd):
     """FitzHugh-Nagumo ring at the full width N=65536, P=floor(0.35N): a few
     steps against the oracle (the oracle's cost is O(N P) per stage)."""
     n = 65536

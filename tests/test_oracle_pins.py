@@ -14,7 +14,7 @@ from scipy.integrate import solve_ivp
 from oracle import oracle as O
 from paper_2410_19075_amd import inputs
 
-C1 = dict(n=1024, P=256, omega=0.0, mu=1.0, alpha=1.46)
+RING_1024 = dict(n=1024, P=256, omega=0.0, mu=1.0, alpha=1.46)
 
 
 def kur(omega, mu, alpha):
@@ -54,7 +54,7 @@ def cube_wave_frequency(dims, h, q, omega, mu, alpha):
     return omega - mu * math.sin(alpha) * (prod - 1.0) / L
 
 
-def test_closed_form_twist_c1_values():
+def test_closed_form_twist_values_ring_1024():
     # q = 0 is the synchronous state: Omega = -sin(alpha); q = 4 with P = n/4:
     # sin(257 * 2pi*4/1024 ...) makes the Dirichlet sum -1/2 - 1/2 + ... = 0
     assert ring_twist_frequency(1024, 256, 0, 0.0, 1.0, 1.46) == pytest.approx(-math.sin(1.46), abs=1e-15)
@@ -66,7 +66,7 @@ def test_closed_form_twist_c1_values():
 def test_ring_twisted_state_rotates_rigidly(q):
     """A q-twisted state is an exact solution rotating at Omega_q; RK4 keeps it
     exactly (all stage slopes equal), so phi(t) - phi(0) = Omega_q t."""
-    n, P = C1["n"], C1["P"]
+    n, P = RING_1024["n"], RING_1024["P"]
     net = O.ring(O.KURAMOTO, n, P, kur(0.0, 1.0, 1.46))
     y0 = inputs.twisted_state(n, q)
     dt, steps = 0.01, 200
@@ -240,7 +240,7 @@ def test_cube_plane_wave_closed_form(q):
     assert np.max(np.abs((yt - y0) - om * dt * steps)) < 1e-12
 
 
-def test_cube_c3_plane_wave_frequencies_h4():
+def test_cube_200_plane_wave_frequencies_h4():
     """The closed form for the 200^3, h = 4, alpha = 0.8 lattice at q = 0 is
     -sin(alpha); the oracle's RHS on a plane wave matches the closed form."""
     assert cube_wave_frequency((200,) * 3, 4, (0, 0, 0), 0, 1, 0.8) == pytest.approx(-math.sin(0.8), abs=1e-15)
@@ -276,7 +276,7 @@ def test_sphere_link_counts_of_the_paper(golden):
 
 
 # ---------------------------------------------------------- FitzHugh-Nagumo
-FHN_C2 = np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
+FHN_PRM = np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
 
 
 def fhn_local(u, v, eps, a):
@@ -287,7 +287,7 @@ def test_fhn_rest_point_is_fixed():
     """(u*, v*) = (-a, -a + a^3/3) is an equilibrium of the uncoupled and of the
     uniformly coupled network."""
     n, P = 128, 44
-    net = O.ring(O.FHN, n, P, FHN_C2)
+    net = O.ring(O.FHN, n, P, FHN_PRM)
     a = 0.5
     y0 = np.concatenate([np.full(n, -a), np.full(n, -a + a ** 3 / 3)])
     f = O.rhs(net, y0)
@@ -341,7 +341,7 @@ def test_fhn_coupling_sums_to_zero():
     elements it vanishes for any state."""
     n, P = 200, 70
     eps, a = 0.05, 0.5
-    net = O.ring(O.FHN, n, P, FHN_C2)
+    net = O.ring(O.FHN, n, P, FHN_PRM)
     y = inputs.fhn_circle(4, n)
     f = O.rhs(net, y)
     u, v = y[:n], y[n:]
@@ -357,7 +357,7 @@ def test_fhn_uniform_network_is_one_oscillator():
     FitzHugh-Nagumo oscillator; compare with scipy's DOP853 at tight tolerance."""
     n, P = 64, 20
     eps, a = 0.05, 0.5
-    net = O.ring(O.FHN, n, P, FHN_C2)
+    net = O.ring(O.FHN, n, P, FHN_PRM)
     u0, v0 = 1.3, -0.4
     y0 = np.concatenate([np.full(n, u0), np.full(n, v0)])
     dt, steps = 0.001, 2000
@@ -371,7 +371,7 @@ def test_fhn_uniform_network_is_one_oscillator():
 
 def test_fhn_dense_brute_force():
     n, P = 33, 11
-    eps, a, sigma, phi = FHN_C2
+    eps, a, sigma, phi = FHN_PRM
     A = ring_adjacency(n, P)
     L = 2 * P
     B = np.array([[math.cos(phi), math.sin(phi)], [-math.sin(phi), math.cos(phi)]])
@@ -386,7 +386,7 @@ def test_fhn_dense_brute_force():
 
     y0 = inputs.fhn_circle(9, n)
     ref = dense_rk4(F, y0, 0.01, 200)
-    y, _, _ = O.run(O.ring(O.FHN, n, P, FHN_C2), y0, 0.01, 200)
+    y, _, _ = O.run(O.ring(O.FHN, n, P, FHN_PRM), y0, 0.01, 200)
     assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-12
 
 
@@ -533,11 +533,11 @@ def test_hh_dense_brute_force():
 
 
 # ------------------------------------------------------------- self floor
-def test_fp64_self_floor_c1_small():
-    """Reversing the neighbour summation order changes C1's result only at the
+def test_fp64_self_floor_ring_1024():
+    """Reversing the neighbour summation order changes the N = 1024 ring's result only at the
     rounding level after 200 steps (the FP64 floor behind the 1e-12 gate)."""
-    net = O.ring(O.KURAMOTO, C1["n"], C1["P"], kur(0.0, 1.0, 1.46))
-    y0 = inputs.kuramoto_phases(1, C1["n"])
+    net = O.ring(O.KURAMOTO, RING_1024["n"], RING_1024["P"], kur(0.0, 1.0, 1.46))
+    y0 = inputs.kuramoto_phases(1, RING_1024["n"])
     a, Ra, _ = O.run(net, y0, 0.01, 200, record_every=1)
     b, Rb, _ = O.run(net, y0, 0.01, 200, record_every=1, reverse=True)
     e = np.max(np.abs(a - b)) / np.max(np.abs(a))
