@@ -71,3 +71,65 @@ def test_fp32_bulk_long_horizon_statistics(nd, case):
     # FP32-bulk cannot be closer to FP64 than FP64 is to itself
     assert err[0] <= max(1e-3, 2 * floor[0])
     assert err[1] <= max(1e-3, 2 * floor[1])
+
+
+def run_cfg(nd, p, y0, steps, dt, mv_start, cfg=None):
+    h = nd.nd_create(p)
+    try:
+        if cfg:
+            c = nd.nd_get_config(h)
+            for k, v in cfg.items():
+                setattr(c, k, v)
+            nd.nd_set_config(h, c)
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, dt, steps, nd.observe(1, mv_start))
+        R = np.empty(steps + 1)
+        mv = np.empty(p.n)
+        nd.nd_get_observables(h, R=R, mean_vel=mv, on_device=0)
+        return R, mv
+    finally:
+        nd.nd_destroy(h)
+
+
+def test_fp32_bulk_long_horizon_inertia_ball(nd):
+    """The paper's 3D inertia state (m = 1, eps = 0.05, mu = 0.01, alpha = 0.45,
+    ball of radius 2) on 60^3 over 100 time units: FP32-bulk statistics against
+    FP64, the FP64 floor from another tiling."""
+    from paper_2410_19075_amd import inputs
+    n1, steps = 60, 2000
+    n = n1 ** 3
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(21, n1), np.zeros(n)])
+    mk = lambda prec: nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, precision=prec, radius=2,
+                                 dims=(n1,) * 3)
+    half = steps // 2
+    a64 = run_cfg(nd, mk(0), y0, steps, 0.05, half)
+    b64 = run_cfg(nd, mk(0), y0, steps, 0.05, half, dict(tile=20, tile_y=12, tile_z=15))
+    a32 = run_cfg(nd, mk(1), y0, steps, 0.05, half)
+    floor, err = stats_gap(a64, b64, half), stats_gap(a64, a32, half)
+    print(f"inertia ball: fp64 floor {floor}; fp32-bulk {err}")
+    assert np.all(np.isfinite(a32[0])) and np.all(np.isfinite(a32[1]))
+    assert err[0] <= max(1e-3, 2 * floor[0])
+    assert err[1] <= max(1e-3, 2 * floor[1])
+
+
+def test_fp32_bulk_long_horizon_links_small_world(nd):
+    """FHN on a small-world coupling matrix (ring of radius 300 plus 2000
+    shortcuts, compressed) over 10^4 steps; the FP64 floor from a one-ulp
+    perturbation of one element."""
+    from paper_2410_19075_amd import inputs
+    n, steps = 8000, 10000
+    rp, col = inputs.small_world_links(5, n, 300, 2000)
+    mk = lambda prec: nd.problem(nd.ND_FHN, nd.ND_LINKS, n, FHN_PRM, precision=prec, row_ptr=rp, col=col)
+    y0 = inputs.fhn_circle(6, n)
+    y1 = y0.copy()
+    y1[17] = np.nextafter(y1[17], np.inf)
+    half = steps // 2
+    a64 = run_cfg(nd, mk(0), y0, steps, 0.01, half)
+    b64 = run_cfg(nd, mk(0), y1, steps, 0.01, half)
+    a32 = run_cfg(nd, mk(1), y0, steps, 0.01, half)
+    floor, err = stats_gap(a64, b64, half), stats_gap(a64, a32, half)
+    print(f"links small world: fp64 floor {floor}; fp32-bulk {err}")
+    assert np.all(np.isfinite(a32[0])) and np.all(np.isfinite(a32[1]))
+    assert err[0] <= max(1e-3, 2 * floor[0])
+    assert err[1] <= max(1e-3, 2 * floor[1])
