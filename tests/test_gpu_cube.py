@@ -151,3 +151,17 @@ def test_cube_batch_equals_solo(nd):
     finally:
         for hh in hs:
             nd.nd_destroy(hh)
+
+
+def test_cube_full_200_random_state_one_step(nd):
+    """The benchmark's workload at full size and in its launch configuration:
+    200^3, h = 4, uniform phases with a planted coherent ball, one step, every
+    element against the oracle (about half a minute of oracle time)."""
+    print("case full 200^3 cube, one step", flush=True)
+    n1 = 200
+    y0 = inputs.cube_phases_with_patch(1000, n1)
+    prm = [0.0, 1.0, 0.8]
+    y, R, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm), y0, 0.05, 1, record_every=1)
+    ref, Rref, _ = O.run(O.cube(n1, 4, prm), y0, 0.05, 1, record_every=1)
+    assert rel(y, ref) < 1e-12
+    assert np.max(np.abs(R - Rref)) < 1e-12

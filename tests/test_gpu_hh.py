@@ -131,3 +131,11 @@ def test_hh_fp32_bulk(nd):
     e = normwise(y, ref)
     print(f"hh fp32 error {e:.3e}")
     assert e < 1e-4
+
+
+def test_hh_full_size_two_steps(nd):
+    """The benchmark's workload at full size and in its launch configuration:
+    10^6 neurons, out-degree 100 (10^8 synapses), two steps against the oracle."""
+    print("case full HH 1e6 x 100, two steps", flush=True)
+    y, ref = hh_case(nd, 1000000, 100, 1, 2)
+    assert normwise(y, ref) < 1e-12

@@ -214,3 +214,17 @@ def test_links_matrix_without_links(nd):
     a, _, _ = nd.simulate(nd.problem(nd.ND_FHN, nd.ND_LINKS, n, FHN, row_ptr=rp), f0, 0.01, 40)
     b, _, _ = O.run(O.links(O.FHN, n, rp, np.zeros(0, dtype=np.int32), np.array(FHN)), f0, 0.01, 40)
     assert normwise(a, b, 2) < 1e-12
+
+
+def test_links_full_100_ball_one_step(nd):
+    """The links benchmark at full size: the 100^3 inertia state with the
+    radius-2 ball as a compressed matrix, one step against the oracle."""
+    print("case full links 100^3 ball 2, one step", flush=True)
+    n1 = 100
+    n = n1 ** 3
+    rp, col = inputs.lattice_ball_links(n1, n1, n1, 2)
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(1000, n1), np.zeros(n)])
+    y, _, _ = nd.simulate(nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_LINKS, n, prm, row_ptr=rp, col=col), y0, 0.05, 1)
+    ref, _, _ = O.run(O.links(O.INERTIA, n, rp, col, np.array(prm)), y0, 0.05, 1)
+    assert normwise(y, ref, 2) < 1e-12
