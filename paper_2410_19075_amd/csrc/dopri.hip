@@ -265,9 +265,348 @@ __global__ __launch_bounds__(kDpBS) __attribute__((amdgpu_waves_per_eu(4))) void
     ring_dopri<ND_KURAMOTO, false>(D, t_end, rtol, atol, max_steps, stats, out);
 }
 
+
+// ------------------------------------------------------------ tiled rings
+// Rings larger than one workgroup: the same method and step control, with
+// every stage spread over tiles of 512 elements in three launches (stage value,
+// its map and the tile's prefix sums; the tiles' offsets; window sums, RHS and,
+// at the last stage, the error terms), and one controller launch per step
+// attempt that takes the accept / reject decision on the device.  The host
+// replays attempts in groups and only reads back whether every ring is done.
+// Window sums come from global prefix sums of the map: the prefix of element k
+// is its tile's offset (fixed-order scan of the tile totals) plus its
+// in-tile inclusive prefix.
+constexpr int kDtBS = 256, kDtEPT = 2, kDtT = kDtBS * kDtEPT;
+
+// Per-ring control block, advanced by the controller on the device.
+struct DtCtl {
+    double t, h, hs, facmax;
+    int64_t acc, rej;
+    int32_t done, last, f, ypar;  // f: physical buffer of k1 (k_q lives at (f + q - 1) mod 7)
+};
+
+// Per-ring buffers of one call.
+struct DtNet {
+    int32_t n, P, G, V;
+    double tend;
+    double* y[2];     // state, and the fifth-order solution of the attempt
+    double* k[7];     // stage slopes (physical buffers)
+    double* M;        // [2][n] map of the current stage value
+    double* pre;      // [2][n] in-tile inclusive prefix of M
+    double* tot;      // [2][G] tile totals, then (after the offsets launch) exclusive offsets
+    double* errp;     // [G] error partial sums of the attempt
+    DtCtl* ctl;
+};
+
+template <int MODEL>
+__device__ __forceinline__ void dt_stage_value(const DtNet& r, const DtCtl& c, int s, int i, double* z) {
+    using M = RingModel<MODEL, double>;
+    constexpr int V = M::V;
+    const double* y = r.y[c.ypar];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        double a = 0.0;
+        for (int q = 0; q < s; ++q) a += kDpA[s][q] * r.k[(c.f + q) % 7][(int64_t)v * r.n + i];
+        z[v] = s == 0 ? y[(int64_t)v * r.n + i] : y[(int64_t)v * r.n + i] + c.hs * a;
+    }
+}
+
+// Stage value z of stage s (s = 0: the state; s = 6: the fifth-order
+// solution, kept in y[ypar ^ 1]), its map and the tile's inclusive prefix.
+template <int MODEL>
+__global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, const int2* __restrict__ work, int s) {
+    using M = RingModel<MODEL, double>;
+    constexpr int V = M::V, NW = kDtBS / kWave;
+    __shared__ double lds[4 * NW];
+    const int2 wk = work[blockIdx.x];
+    const DtNet& r = R[wk.x];
+    const DtCtl c = *r.ctl;
+    if (c.done) return;
+    const int n = r.n, t0 = wk.y * kDtT, tid = threadIdx.x;
+    double tot[2] = {0.0, 0.0}, none[1] = {0.0};
+    double pv[kDtEPT][2];
+#pragma unroll
+    for (int e = 0; e < kDtEPT; ++e) {
+        const int i = t0 + tid * kDtEPT + e;
+        double2 x = make_double2(0.0, 0.0);
+        if (i < n) {
+            double z[V];
+            dt_stage_value<MODEL>(r, c, s, i, z);
+            x = M::map(z);
+            if (s == 6) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) r.y[c.ypar ^ 1][(int64_t)v * n + i] = z[v];
+            }
+            r.M[i] = x.x;
+            r.M[n + i] = x.y;
+        }
+        tot[0] += x.x;
+        tot[1] += x.y;
+        pv[e][0] = tot[0];
+        pv[e][1] = tot[1];
+    }
+    const double own0 = tot[0], own1 = tot[1];
+    block_sum_and_exscan<kDtBS, 1, 2>(none, tot, lds);
+#pragma unroll
+    for (int e = 0; e < kDtEPT; ++e) {
+        const int i = t0 + tid * kDtEPT + e;
+        if (i < n) {
+            r.pre[i] = tot[0] + pv[e][0];
+            r.pre[n + i] = tot[1] + pv[e][1];
+        }
+    }
+    if (tid == kDtBS - 1) {
+        r.tot[wk.y] = tot[0] + own0;
+        r.tot[r.G + wk.y] = tot[1] + own1;
+    }
+}
+
+// Exclusive offsets of the tiles (one workgroup per ring, fixed order).
+__global__ __launch_bounds__(kDtBS) void k_dt_offsets(const DtNet* __restrict__ R) {
+    const DtNet& r = R[blockIdx.x];
+    if (r.ctl->done) return;
+    __shared__ double lds[4 * (kDtBS / kWave)];
+    __shared__ double chunk[2];
+    double carry0 = 0.0, carry1 = 0.0;
+    for (int b0 = 0; b0 < r.G; b0 += kDtBS) {
+        const int q = b0 + (int)threadIdx.x;
+        const double own0 = q < r.G ? r.tot[q] : 0.0, own1 = q < r.G ? r.tot[r.G + q] : 0.0;
+        double v[2] = {own0, own1}, none[1] = {0.0};
+        block_sum_and_exscan<kDtBS, 1, 2>(none, v, lds);  // v: exclusive prefix in this chunk
+        if (threadIdx.x == kDtBS - 1) {
+            chunk[0] = v[0] + own0;
+            chunk[1] = v[1] + own1;
+        }
+        if (q < r.G) {
+            r.tot[q] = carry0 + v[0];
+            r.tot[r.G + q] = carry1 + v[1];
+        }
+        __syncthreads();
+        carry0 += chunk[0];
+        carry1 += chunk[1];
+        __syncthreads();
+    }
+}
+
+// Window sums from the global prefix, the RHS of stage s into k_{s+1} and, at
+// the last stage, the error terms of the attempt.
+template <int MODEL>
+__global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, const NetDesc* __restrict__ D,
+                                                  const int2* __restrict__ work, int s, double rtol, double atol) {
+    using M = RingModel<MODEL, double>;
+    constexpr int V = M::V, NW = kDtBS / kWave;
+    __shared__ double lds[NW];
+    const int2 wk = work[blockIdx.x];
+    const DtNet& r = R[wk.x];
+    const NetDesc& d = D[wk.x];
+    const DtCtl c = *r.ctl;
+    if (c.done) return;
+    const int n = r.n, P = r.P, t0 = wk.y * kDtT, tid = threadIdx.x;
+    auto S = [&](int k, int comp) {  // inclusive global prefix of element k (k = -1: 0)
+        return k < 0 ? 0.0 : r.tot[comp * r.G + k / kDtT] + r.pre[comp * n + k];
+    };
+    double es[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < kDtEPT; ++e) {
+        const int i = t0 + tid * kDtEPT + e;
+        if (i >= n) continue;
+        double z[V];
+        dt_stage_value<MODEL>(r, c, s, i, z);
+        const double2 x = make_double2(r.M[i], r.M[n + i]);
+        const int lo = i - P, hi = i + P;
+        double w0, w1;
+        if (lo < 0) {
+            w0 = S(hi, 0) + (S(n - 1, 0) - S(lo + n - 1, 0));
+            w1 = S(hi, 1) + (S(n - 1, 1) - S(lo + n - 1, 1));
+        } else if (hi >= n) {
+            w0 = (S(n - 1, 0) - S(lo - 1, 0)) + S(hi - n, 0);
+            w1 = (S(n - 1, 1) - S(lo - 1, 1)) + S(hi - n, 1);
+        } else {
+            w0 = S(hi, 0) - S(lo - 1, 0);
+            w1 = S(hi, 1) - S(lo - 1, 1);
+        }
+        double k[V];
+        M::rhs(d, z, x, make_double2(w0 - x.x, w1 - x.y), k);
+        double* ko = r.k[(c.f + s) % 7];
+#pragma unroll
+        for (int v = 0; v < V; ++v) ko[(int64_t)v * n + i] = k[v];
+        if (s == 6 && rtol > 0.0) {
+            const double* y = r.y[c.ypar];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                double er = 0.0;
+                for (int q = 0; q < 7; ++q) er += kDpE[q] * r.k[(c.f + q) % 7][(int64_t)v * n + i];
+                er *= c.hs;
+                const double sc = atol + rtol * fmax(fabs(y[(int64_t)v * n + i]), fabs(z[v]));
+                es[0] += (er / sc) * (er / sc);
+            }
+        }
+    }
+    if (s == 6) {
+        block_sum<kDtBS, 1>(es, lds);
+        if (tid == 0) r.errp[wk.y] = es[0];
+    }
+}
+
+// The accept / reject decision of the attempt and the next step (one thread
+// per ring; the error partials are added in tile order).
+__global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol, int64_t max_steps) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const DtNet& r = R[b];
+    DtCtl c = *r.ctl;
+    if (c.done) return;
+    bool accept = true;
+    double f = 1.0;
+    if (rtol > 0.0) {
+        double sum = 0.0;
+        for (int q = 0; q < r.G; ++q) sum += r.errp[q];
+        const double err = sqrt(sum / ((double)r.V * (double)r.n));
+        f = 0.9 * pow(err, -0.2);
+        accept = err <= 1.0;
+    }
+    if (accept) {
+        c.t = c.last ? r.tend : c.t + c.hs;
+        ++c.acc;
+        if (rtol > 0.0) c.h = c.hs * fmin(c.facmax, fmax(0.2, f));
+        c.facmax = 10.0;
+        c.ypar ^= 1;
+        c.f = (c.f + 6) % 7;  // k1 of the next step is this step's k7
+    } else {
+        ++c.rej;
+        c.h = c.hs * fmax(0.2, fmin(1.0, f));
+        c.facmax = 1.0;
+    }
+    c.done = !(c.t < r.tend && c.acc + c.rej < max_steps);
+    if (!c.done) {
+        c.last = r.tend - c.t <= c.h * (1.0 + 1e-12);
+        c.hs = c.last ? r.tend - c.t : c.h;
+    }
+    *r.ctl = c;
+}
 }  // namespace nd
 
 using namespace nd;
+
+// Rings beyond one workgroup: buffers per ring, the stage / controller launches
+// replayed in groups of attempts until every ring is done.
+static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, const double* t_end,
+                                    const double* dt0, double rtol, double atol, int64_t max_steps,
+                                    nd_adaptive_stats* stats, hipStream_t st) {
+    const int count = (int)nets.size();
+    std::vector<DtNet> rs(count);
+    std::vector<DtCtl> cs(count);
+    std::vector<NetDesc> descs(count);
+    std::vector<int2> work;
+    size_t bytes = 0;
+    for (int b = 0; b < count; ++b) {
+        const Net* nt = nets[b];
+        const int64_t n = nt->prob.n, len = nvars_of(nt->prob.model) * n, G = (n + kDtT - 1) / kDtT;
+        bytes += (size_t)(8 * len + 4 * n + 3 * G) * 8 + sizeof(DtCtl);
+        for (int64_t t = 0; t < G; ++t) work.push_back(make_int2(b, (int)t));
+    }
+    const size_t bd = (size_t)count * sizeof(DtNet), bn = (size_t)count * sizeof(NetDesc),
+                 bw = work.size() * sizeof(int2);
+    char* buf = nullptr;
+    hipError_t e = hipMallocAsync((void**)&buf, bd + bn + bw + bytes + 256, st);
+    if (e != hipSuccess) return hip_fail(e, "adaptive scratch");
+    DtNet* d_r = (DtNet*)buf;
+    NetDesc* d_desc = (NetDesc*)(buf + bd);
+    int2* d_work = (int2*)(buf + bd + bn);
+    char* p = buf + ((bd + bn + bw + 255) / 256) * 256;
+    auto take = [&](size_t nbytes) {
+        char* q = p;
+        p += (nbytes + 7) / 8 * 8;
+        return q;
+    };
+    for (int b = 0; b < count; ++b) {
+        const Net* nt = nets[b];
+        const int64_t n = nt->prob.n, len = nvars_of(nt->prob.model) * n;
+        DtNet& r = rs[b];
+        r.n = (int32_t)n;
+        r.P = (int32_t)nt->prob.radius;
+        r.G = (int32_t)((n + kDtT - 1) / kDtT);
+        r.V = nvars_of(nt->prob.model);
+        r.tend = t_end[b];
+        descs[b] = nt->run_desc(dt0[b], 0);
+        r.y[0] = descs[b].y[descs[b].ypar];
+        r.y[1] = (double*)take(len * 8);
+        for (int q = 0; q < 7; ++q) r.k[q] = (double*)take(len * 8);
+        r.M = (double*)take(2 * n * 8);
+        r.pre = (double*)take(2 * n * 8);
+        r.tot = (double*)take(2 * r.G * 8);
+        r.errp = (double*)take(r.G * 8);
+        r.ctl = (DtCtl*)take(sizeof(DtCtl));
+        DtCtl& c = cs[b];
+        c = DtCtl{};
+        c.h = dt0[b];
+        c.facmax = 10.0;
+        c.done = !(0.0 < t_end[b] && max_steps > 0);
+        c.last = t_end[b] <= c.h * (1.0 + 1e-12);
+        c.hs = c.last ? t_end[b] : c.h;
+    }
+    const int tiles = (int)work.size();
+    auto stage = [&](int s) {
+        if (model == ND_KURAMOTO) {
+            hipLaunchKernelGGL(k_dt_map<ND_KURAMOTO>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
+        } else if (model == ND_FHN) {
+            hipLaunchKernelGGL(k_dt_map<ND_FHN>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
+        } else {
+            hipLaunchKernelGGL(k_dt_map<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
+        }
+        hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
+        if (model == ND_KURAMOTO) {
+            hipLaunchKernelGGL(k_dt_rhs<ND_KURAMOTO>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol,
+                               atol);
+        } else if (model == ND_FHN) {
+            hipLaunchKernelGGL(k_dt_rhs<ND_FHN>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol, atol);
+        } else {
+            hipLaunchKernelGGL(k_dt_rhs<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s,
+                               rtol, atol);
+        }
+        return hipGetLastError();
+    };
+    // the control blocks live inside the scratch: write them with the descriptors
+    for (int b = 0; b < count && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(rs[b].ctl, &cs[b], sizeof(DtCtl), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_r, rs.data(), bd, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_desc, descs.data(), bn, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_work, work.data(), bw, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = stage(0);  // k1 = f(y)
+    constexpr int kAttempts = 8;        // attempts launched between checks of the done flags
+    while (e == hipSuccess) {
+        for (int a = 0; a < kAttempts && e == hipSuccess; ++a) {
+            for (int s = 1; s <= 6 && e == hipSuccess; ++s) e = stage(s);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_dt_control, dim3((count + 63) / 64), dim3(64), 0, st, d_r, count, rtol, max_steps);
+                e = hipGetLastError();
+            }
+        }
+        for (int b = 0; b < count && e == hipSuccess; ++b)
+            e = hipMemcpyAsync(&cs[b], rs[b].ctl, sizeof(DtCtl), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        bool all = true;
+        for (const DtCtl& c : cs) all = all && c.done;
+        if (all) break;
+    }
+    // a state that ended in the scratch buffer goes back to the network
+    for (int b = 0; b < count && e == hipSuccess; ++b)
+        if (cs[b].ypar)
+            e = hipMemcpyAsync(rs[b].y[0], rs[b].y[1], (size_t)rs[b].V * rs[b].n * 8, hipMemcpyDeviceToDevice, st);
+    const hipError_t ef = hipFreeAsync(buf, st);
+    const hipError_t es = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "adaptive run (tiled)");
+    if (ef != hipSuccess) return hip_fail(ef, "adaptive scratch free");
+    if (es != hipSuccess) return hip_fail(es, "adaptive run (tiled)");
+    for (int b = 0; b < count; ++b) {
+        stats[b].t = cs[b].t;
+        stats[b].accepted = cs[b].acc;
+        stats[b].rejected = cs[b].rej;
+        stats[b].h_next = cs[b].h;
+    }
+    return ND_OK;
+}
 
 static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* t_end, const double* dt0,
                               double rtol, double atol, int64_t max_steps, nd_adaptive_stats* stats, void* stream,
@@ -281,12 +620,16 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
         return fail(ND_ERR_INVALID_ARG, "dense output needs t_out > 0, R and r_stride >= 1");
     if (count == 0) return ND_OK;
     int model = -1;
+    bool tiled = false;
     std::vector<NetDesc> descs(count);
+    std::vector<Net*> nets(count);
     for (int i = 0; i < count; ++i) {
         Net* n = reinterpret_cast<Net*>(hs[i]);
         if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle at %d", i);
-        if (n->prob.topo != ND_RING || n->prob.n > kDpCap || n->prob.precision != ND_FP64 || n->prob.model == ND_HH)
-            return fail(ND_ERR_UNSUPPORTED, "adaptive stepping runs FP64 rings of at most %d elements", kDpCap);
+        nets[i] = n;
+        if (n->prob.topo != ND_RING || n->prob.precision != ND_FP64 || n->prob.model == ND_HH)
+            return fail(ND_ERR_UNSUPPORTED, "adaptive stepping runs FP64 rings");
+        tiled = tiled || n->prob.n > kDpCap;
         if (model >= 0 && n->prob.model != model)
             return fail(ND_ERR_INVALID_ARG, "one adaptive batch holds one model");
         model = n->prob.model;
@@ -302,6 +645,10 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
                             (long long)(outs * nvars_of(n->prob.model) * n->prob.n));
         }
         descs[i] = n->run_desc(dt0[i], 0);
+    }
+    if (tiled) {
+        if (dense) return fail(ND_ERR_UNSUPPORTED, "dense output is for rings of at most %d elements", kDpCap);
+        return run_adaptive_tiled(nets, model, t_end, dt0, rtol, atol, max_steps, stats, (hipStream_t)stream);
     }
     hipStream_t st = (hipStream_t)stream;
     void* buf = nullptr;

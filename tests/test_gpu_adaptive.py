@@ -113,9 +113,9 @@ def test_adaptive_step_budget(nd):
 
 
 def test_adaptive_rejects_unsupported(nd):
-    big = nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 2000, KUR, radius=10)
     f32 = nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 500, KUR, precision=nd.ND_FP32_BULK, radius=10)
-    for p in (big, f32):
+    cube = nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, 9 ** 3, KUR, radius=1, dims=(9, 9, 9))
+    for p in (f32, cube):
         h = nd.nd_create(p)
         try:
             with pytest.raises(nd.NDError) as ei:
@@ -213,5 +213,58 @@ def test_dense_output_rejects_bad_arguments(nd):
         R = np.empty(5)
         rc = nd._lib.nd_run_adaptive_dense(hs, 1, te, d0, 1e-6, 1e-9, 1000, 0.1, R.ctypes.data, 5, None, 0, st, None)
         assert rc == nd.ND_ERR_INVALID_ARG  # 11 outputs do not fit r_stride 5
+    finally:
+        nd.nd_destroy(h)
+
+
+# ------------------------------------------------- rings beyond one workgroup
+@pytest.mark.parametrize("model,n,P,t_end,rtol", [("kuramoto", 5000, 1000, 2.0, 1e-8), ("fhn", 2049, 700, 1.0, 1e-7),
+                                                  ("inertia", 3000, 500, 3.0, 1e-9), ("kuramoto", 1025, 3, 1.5, 1e-6)])
+def test_tiled_adaptive_matches_oracle(nd, model, n, P, t_end, rtol):
+    """Rings larger than one workgroup take the tiled path: the same accepted and
+    rejected steps as the oracle's controller and the same state."""
+    print(f"case tiled adaptive {model} n={n}", flush=True)
+    p, onet, y0, nv = net(nd, model, n, P, n + 3 * P)
+    (y,), (st,) = run_gpu(nd, [p], [y0], [t_end], [1e-3], rtol, rtol * 1e-2)
+    ref, t, acc, rej, hnext = O.run_dopri(onet, y0, t_end, rtol, rtol * 1e-2, 1e-3)
+    print(f"  gpu {st.accepted}/{st.rejected}  oracle {acc}/{rej}", flush=True)
+    assert st.accepted == acc and st.rejected == rej
+    assert st.t == t
+    assert normwise(y, ref, nv) < 1e-10
+    assert st.h_next == pytest.approx(hnext, rel=1e-4)
+
+
+def test_tiled_adaptive_batch_fixed_steps_and_budget(nd):
+    """A batch with a small and two large rings (all on the tiled path), one of
+    them with t_end = 0; then fixed steps, and a step budget."""
+    cases = [(700, 100, 2.0, 1e-3), (4000, 1300, 1.0, 1e-2), (2500, 30, 0.0, 1e-3)]
+    probs, onets, y0s = [], [], []
+    for i, (n, P, _, _) in enumerate(cases):
+        p, onet, y0, _ = net(nd, "kuramoto", n, P, 90 + i)
+        probs.append(p)
+        onets.append(onet)
+        y0s.append(y0)
+    ys, st = run_gpu(nd, probs, y0s, [c[2] for c in cases], [c[3] for c in cases], 1e-8, 1e-10)
+    for y, s, onet, y0, c in zip(ys, st, onets, y0s, cases):
+        ref, t, acc, rej, _ = O.run_dopri(onet, y0, c[2], 1e-8, 1e-10, c[3])
+        assert (s.accepted, s.rejected) == (acc, rej) and s.t == t
+        assert np.max(np.abs(y - ref)) / max(1.0, np.max(np.abs(ref))) < 1e-10
+    p, onet, y0, nv = net(nd, "fhn", 3000, 900, 4)
+    (y,), (s,) = run_gpu(nd, [p], [y0], [0.5], [0.01], -1.0, 0.0)
+    ref, t, acc, rej, _ = O.run_dopri(onet, y0, 0.5, -1.0, 0.0, 0.01)
+    assert s.accepted == acc == 50 and s.rejected == 0
+    assert normwise(y, ref, nv) < 1e-12
+    (y,), (s,) = run_gpu(nd, [p], [y0], [100.0], [1e-3], 1e-8, 1e-10, max_steps=21)
+    ref, t, acc, rej, _ = O.run_dopri(onet, y0, 100.0, 1e-8, 1e-10, 1e-3, max_steps=21)
+    assert s.accepted + s.rejected == 21 == acc + rej
+    assert s.t == pytest.approx(t, rel=1e-6) and normwise(y, ref, nv) < 1e-6
+
+
+def test_tiled_adaptive_rejects_dense_output(nd):
+    h = nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 3000, KUR, radius=100))
+    try:
+        with pytest.raises(nd.NDError) as ei:
+            nd.nd_run_adaptive_dense([h], [1.0], [1e-3], 1e-6, 1e-9, 0.1)
+        assert ei.value.status == nd.ND_ERR_UNSUPPORTED
     finally:
         nd.nd_destroy(h)
