@@ -33,7 +33,10 @@ Other workloads (one JSON line each, same fields):
                        4096 Kuramoto rings N = 1024, P = 256, alpha = 1.46,
                        omega = 0, integrated over t = 100 at rtol = 1e-8,
                        atol = 1e-10, each ring controlling its own step from
-                       h0 = 1e-3; value counts accepted steps
+                       h0 = 1e-3; value counts accepted steps.  With --n above
+                       1024: FHN rings of that size (P = floor(0.35 N), the
+                       default workload's parameters and inputs) integrated over
+                       t = 10, 16 rings, on the tiled path
   --workload serve     continuous-batching server fed by seeded Poisson arrivals of
                        Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
                        [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
@@ -111,6 +114,8 @@ def parse():
                     help="only run a plain device-to-device copy of BYTES bytes (for scaling HBM counters)")
     a = ap.parse_args()
     b, hz, dt, n = DEFAULTS[a.workload]
+    if a.workload == "adaptive" and a.n > 1024:
+        b = 16  # rings beyond one workgroup (the FHN ring of the default workload)
     a.batch = a.batch or b
     a.horizon = a.horizon or hz
     a.n = a.n or n
@@ -485,14 +490,20 @@ def main_serve(nd, torch, args, stream):
 
 
 def main_adaptive(nd, torch, args, stream):
-    """One launch integrates every ring to t_end with its own step control."""
+    """One call integrates every ring to t_end with its own step control."""
     from paper_2410_19075_amd import inputs
-    n, P, t_end, rtol, atol = args.n, args.n // 4, 100.0, 1e-8, 1e-10
-    hs = []
-    for b in range(args.batch):
-        h = nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, [0.0, 1.0, 1.46], radius=P))
-        hs.append(h)
-    y0s = [torch.from_numpy(inputs.kuramoto_phases(1000 + b, n)).cuda() for b in range(args.batch)]
+    n, rtol, atol = args.n, 1e-8, 1e-10
+    tiled = n > 1024
+    if tiled:  # the FHN ring of the default workload, on the tiled path
+        P, t_end, prm, model = int(0.35 * n), 10.0, FHN_PRM, nd.ND_FHN
+        state = lambda b: inputs.fhn_circle(1000 + b, n)
+        nv = 2
+    else:
+        P, t_end, prm, model = n // 4, 100.0, [0.0, 1.0, 1.46], nd.ND_KURAMOTO
+        state = lambda b: inputs.kuramoto_phases(1000 + b, n)
+        nv = 1
+    hs = [nd.nd_create(nd.problem(model, nd.ND_RING, n, prm, radius=P)) for _ in range(args.batch)]
+    y0s = [torch.from_numpy(state(b)).cuda() for b in range(args.batch)]
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -519,34 +530,48 @@ def main_adaptive(nd, torch, args, stream):
         rej += sum(s.rejected for s in st)
     wall = sum(times)
     value = acc * n / wall
-    # algorithmic FP64 flops per element and accepted step: 7 stages of the resident
-    # kernel's per-stage work (KURAMOTO_RESIDENT_FLOPS / 4 each, sin/cos included)
-    # plus the stage combinations (2 flops per coefficient, 27 + 7 coefficients)
-    flops = acc * n * (7 * KURAMOTO_RESIDENT_FLOPS / 4 + 2 * 34)
-    achieved = flops / ev_total / 1e12
+    if tiled:
+        # algorithmic bytes per element and accepted step: stage s (1..6) reads y and
+        # k_1..k_s and writes k_{s+1}; the fifth-order solution is written once
+        bpe = (sum(s + 2 for s in range(1, 7)) + 1) * 8 * nv
+        achieved = acc * n * bpe / ev_total / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_dt_map + k_dt_offsets + k_dt_rhs + k_dt_control", "bytes_per_element_step": bpe}
+        what = f"{args.batch} FitzHugh-Nagumo rings N={n} P={P} (0.35N), eps=0.05 a=0.5 sigma=0.1 phi=pi/2-0.1"
+    else:
+        # algorithmic FP64 flops per element and accepted step: 7 stages of the resident
+        # kernel's per-stage work (KURAMOTO_RESIDENT_FLOPS / 4 each, sin/cos included)
+        # plus the stage combinations (2 flops per coefficient, 27 + 7 coefficients)
+        flops = acc * n * (7 * KURAMOTO_RESIDENT_FLOPS / 4 + 2 * 34)
+        achieved = flops / ev_total / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_ring_dopri<Kuramoto>"}
+        what = f"{args.batch} Kuramoto rings N={n} P={P} alpha=1.46"
+    roof["avg_launch_us"] = ev_total / args.steps * 1e6
     out = {"metric": "oscillator-steps/s", "value": value, "unit": "oscillator-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"Dormand-Prince 5(4), {args.batch} Kuramoto rings N={n} P={P} alpha=1.46, "
-                                  f"t=0..{t_end}, rtol={rtol} atol={atol}, per-ring step control",
+           "config": {"workload": f"Dormand-Prince 5(4), {what}, t=0..{t_end}, rtol={rtol} atol={atol}, "
+                                  f"per-ring step control",
                       "global_batch": args.batch, "parallelism": "single-gpu"},
-           "accepted_steps": acc, "rejected_steps": rej,
-           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_ring_dopri<Kuramoto>",
-                        "avg_launch_us": ev_total / args.steps * 1e6}}
+           "accepted_steps": acc, "rejected_steps": rej, "roofline": roof}
     for h in hs:
         nd.nd_destroy(h)
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         O.lib()
-        y0 = inputs.kuramoto_phases(1000, n)
+        y0 = state(0)
+        # a bounded sample: the Kuramoto ring to t_end, the large FHN ring to t = 0.01
+        ts = t_end if not tiled else 0.01
+        net = O.ring(O.FHN if tiled else O.KURAMOTO, n, P, prm)
         t0 = time.perf_counter()
-        _, _, oacc, orej, _ = O.run_dopri(O.ring(O.KURAMOTO, n, P, [0.0, 1.0, 1.46]), y0, t_end, rtol, atol, 1e-3)
+        _, _, oacc, orej, _ = O.run_dopri(net, y0, ts, rtol, atol, 1e-3)
         sec = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {"value": oacc * n / sec, "unit": "oscillator-steps/s", "cores": cores,
                                "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
-                               "sample": f"one Kuramoto ring N={n} P={P}, Dormand-Prince 5(4) to t={t_end}, "
+                               "sample": f"one ring N={n} P={P}, Dormand-Prince 5(4) to t={ts}, "
                                          f"{oacc} accepted / {orej} rejected steps, FP64, {sec:.2f} s"}
     print(json.dumps(out), flush=True)
 
