@@ -204,10 +204,12 @@ typedef struct nd_kernel_config {
  *   rejection); the step that reaches t_end (within a relative 1e-12 of h) ends on it.
  * rtol <= 0 takes fixed steps of dt0 (no control).  The fifth-order solution propagates.
  * Each of the `count` networks is integrated from its current state over [0, t_end[i]]
- * starting with step dt0[i], entirely on the device, one workgroup per network: each
- * network controls its own step.  Supported: FP64 rings (ND_RING) of at most 1024
- * elements of the Kuramoto, Kuramoto-with-inertia or FHN model, one model per call
- * (ND_ERR_UNSUPPORTED otherwise).  At most max_steps step attempts per network.  The state
+ * starting with step dt0[i] on the device; each network controls its own step.  Supported:
+ * FP64 rings (ND_RING) of the Kuramoto, Kuramoto-with-inertia or FHN model, one model per call
+ * (ND_ERR_UNSUPPORTED otherwise).  When every ring holds at most 1024 elements, one workgroup
+ * integrates each ring in a single launch; otherwise the batch is tiled over workgroups, with
+ * the accept / reject decisions taken on the device and only the rings' completion read back
+ * every few attempts.  At most max_steps step attempts per network.  The state
  * is advanced in place (read it with nd_get_state); no observables are recorded.  Blocks
  * until done; stats[i] receives the time reached, the accepted and rejected steps and the
  * step proposed next. */
@@ -233,7 +235,8 @@ nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end
  * Y (host, may be NULL; count * y_stride doubles): Y[i * y_stride + k * nvars * n + v * n + j]
  * = variable v of element j at t_k; y_stride >= (outputs of i) * nvars * n_i.
  * Outputs a network does not reach (max_steps) read NaN.  The device holds R and Y in a
- * scratch buffer for the call.  Otherwise as nd_run_adaptive. */
+ * scratch buffer for the call.  Rings of at most 1024 elements only (ND_ERR_UNSUPPORTED
+ * otherwise).  Otherwise as nd_run_adaptive. */
 nd_status nd_run_adaptive_dense(const nd_handle* h, int32_t count, const double* t_end, const double* dt0,
                                 double rtol, double atol, int64_t max_steps, double t_out, double* R,
                                 int64_t r_stride, double* Y, int64_t y_stride, nd_adaptive_stats* stats,
