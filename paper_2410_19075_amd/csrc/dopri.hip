@@ -388,9 +388,11 @@ __global__ __launch_bounds__(kDtBS) void k_dt_offsets(const DtNet* __restrict__ 
     }
 }
 
-// Window sums from the global prefix, the RHS of stage s into k_{s+1} and, at
-// the last stage, the error terms of the attempt.
-template <int MODEL>
+// Neighbour sums (ring: windows from the global prefix; links: the compressed
+// coupling matrix's rows, extracted as in the stage kernels of that topology),
+// the RHS of stage s into k_{s+1} and, at the last stage, the error terms of
+// the attempt.
+template <int MODEL, int TOPO>
 __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, const NetDesc* __restrict__ D,
                                                   const int2* __restrict__ work, int s, double rtol, double atol) {
     using M = RingModel<MODEL, double>;
@@ -413,20 +415,46 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
         double z[V];
         dt_stage_value<MODEL>(r, c, s, i, z);
         const double2 x = make_double2(r.M[i], r.M[n + i]);
-        const int lo = i - P, hi = i + P;
-        double w0, w1;
-        if (lo < 0) {
-            w0 = S(hi, 0) + (S(n - 1, 0) - S(lo + n - 1, 0));
-            w1 = S(hi, 1) + (S(n - 1, 1) - S(lo + n - 1, 1));
-        } else if (hi >= n) {
-            w0 = (S(n - 1, 0) - S(lo - 1, 0)) + S(hi - n, 0);
-            w1 = (S(n - 1, 1) - S(lo - 1, 1)) + S(hi - n, 1);
+        double2 W;
+        if constexpr (TOPO == ND_RING) {
+            const int lo = i - P, hi = i + P;
+            double w0, w1;
+            if (lo < 0) {
+                w0 = S(hi, 0) + (S(n - 1, 0) - S(lo + n - 1, 0));
+                w1 = S(hi, 1) + (S(n - 1, 1) - S(lo + n - 1, 1));
+            } else if (hi >= n) {
+                w0 = (S(n - 1, 0) - S(lo - 1, 0)) + S(hi - n, 0);
+                w1 = (S(n - 1, 1) - S(lo - 1, 1)) + S(hi - n, 1);
+            } else {
+                w0 = S(hi, 0) - S(lo - 1, 0);
+                w1 = S(hi, 1) - S(lo - 1, 1);
+            }
+            W = make_double2(w0 - x.x, w1 - x.y);
         } else {
-            w0 = S(hi, 0) - S(lo - 1, 0);
-            w1 = S(hi, 1) - S(lo - 1, 1);
+            // row i = (V XOR D[C_i]) shifted by i: V's positions, then the entry's
+            // signed positions, divided by the row's link count
+            double w0 = 0.0, w1 = 0.0;
+            for (int q = 0; q < d.lnv; ++q) {
+                int j = i + d.lvpos[q];
+                j -= j >= n ? n : 0;
+                w0 += r.M[j];
+                w1 += r.M[n + j];
+            }
+            const int ke = d.lrow[i];
+            for (int e2 = d.ldptr[ke]; e2 < d.ldptr[ke + 1]; ++e2) {
+                const int32_t v = d.ldpos[e2];
+                int j = i + (v & ~kLinksRemove);
+                j -= j >= n ? n : 0;
+                const double sg = (v & kLinksRemove) ? -1.0 : 1.0;
+                w0 += sg * r.M[j];
+                w1 += sg * r.M[n + j];
+            }
+            const double inv = d.linv[ke];
+            W = inv != 0.0 ? make_double2(w0 * inv, w1 * inv)
+                           : (MODEL == ND_FHN ? make_double2(z[0], z[V - 1]) : make_double2(0.0, 0.0));
         }
         double k[V];
-        M::rhs(d, z, x, make_double2(w0 - x.x, w1 - x.y), k);
+        M::rhs(d, z, x, W, k);
         double* ko = r.k[(c.f + s) % 7];
 #pragma unroll
         for (int v = 0; v < V; ++v) ko[(int64_t)v * n + i] = k[v];
@@ -490,7 +518,7 @@ using namespace nd;
 
 // Rings beyond one workgroup: buffers per ring, the stage / controller launches
 // replayed in groups of attempts until every ring is done.
-static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, const double* t_end,
+static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, int topo, const double* t_end,
                                     const double* dt0, double rtol, double atol, int64_t max_steps,
                                     nd_adaptive_stats* stats, hipStream_t st) {
     const int count = (int)nets.size();
@@ -554,15 +582,18 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, co
         } else {
             hipLaunchKernelGGL(k_dt_map<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
         }
-        hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
-        if (model == ND_KURAMOTO) {
-            hipLaunchKernelGGL(k_dt_rhs<ND_KURAMOTO>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol,
-                               atol);
-        } else if (model == ND_FHN) {
-            hipLaunchKernelGGL(k_dt_rhs<ND_FHN>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol, atol);
+        if (topo == ND_RING) hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
+        auto rhs = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol, atol);
+        };
+        if (topo == ND_RING) {
+            if (model == ND_KURAMOTO) rhs(k_dt_rhs<ND_KURAMOTO, ND_RING>);
+            else if (model == ND_FHN) rhs(k_dt_rhs<ND_FHN, ND_RING>);
+            else rhs(k_dt_rhs<ND_KURAMOTO_INERTIA, ND_RING>);
         } else {
-            hipLaunchKernelGGL(k_dt_rhs<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s,
-                               rtol, atol);
+            if (model == ND_KURAMOTO) rhs(k_dt_rhs<ND_KURAMOTO, ND_LINKS>);
+            else if (model == ND_FHN) rhs(k_dt_rhs<ND_FHN, ND_LINKS>);
+            else rhs(k_dt_rhs<ND_KURAMOTO_INERTIA, ND_LINKS>);
         }
         return hipGetLastError();
     };
@@ -619,7 +650,7 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
     if (dense && (!(t_out > 0.0) || !std::isfinite(t_out) || !R || r_stride < 1))
         return fail(ND_ERR_INVALID_ARG, "dense output needs t_out > 0, R and r_stride >= 1");
     if (count == 0) return ND_OK;
-    int model = -1;
+    int model = -1, topo = -1;
     bool tiled = false;
     std::vector<NetDesc> descs(count);
     std::vector<Net*> nets(count);
@@ -627,9 +658,12 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
         Net* n = reinterpret_cast<Net*>(hs[i]);
         if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle at %d", i);
         nets[i] = n;
-        if (n->prob.topo != ND_RING || n->prob.precision != ND_FP64 || n->prob.model == ND_HH)
-            return fail(ND_ERR_UNSUPPORTED, "adaptive stepping runs FP64 rings");
-        tiled = tiled || n->prob.n > kDpCap;
+        if ((n->prob.topo != ND_RING && n->prob.topo != ND_LINKS) || n->prob.precision != ND_FP64 ||
+            n->prob.model == ND_HH)
+            return fail(ND_ERR_UNSUPPORTED, "adaptive stepping runs FP64 rings and compressed coupling matrices");
+        if (topo >= 0 && n->prob.topo != topo) return fail(ND_ERR_INVALID_ARG, "one adaptive batch holds one topology");
+        topo = n->prob.topo;
+        tiled = tiled || n->prob.n > kDpCap || topo == ND_LINKS;
         if (model >= 0 && n->prob.model != model)
             return fail(ND_ERR_INVALID_ARG, "one adaptive batch holds one model");
         model = n->prob.model;
@@ -648,7 +682,7 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
     }
     if (tiled) {
         if (dense) return fail(ND_ERR_UNSUPPORTED, "dense output is for rings of at most %d elements", kDpCap);
-        return run_adaptive_tiled(nets, model, t_end, dt0, rtol, atol, max_steps, stats, (hipStream_t)stream);
+        return run_adaptive_tiled(nets, model, topo, t_end, dt0, rtol, atol, max_steps, stats, (hipStream_t)stream);
     }
     hipStream_t st = (hipStream_t)stream;
     void* buf = nullptr;

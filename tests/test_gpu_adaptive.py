@@ -268,3 +268,41 @@ def test_tiled_adaptive_rejects_dense_output(nd):
         assert ei.value.status == nd.ND_ERR_UNSUPPORTED
     finally:
         nd.nd_destroy(h)
+
+
+def links_net(nd, model, kind, seed):
+    if kind == "small_world":
+        n = 2000
+        rp, col = inputs.small_world_links(seed, n, 25, 60)
+    elif kind == "random":
+        n = 300
+        rp0, col0 = inputs.random_links(seed, n, 0.05)
+        rows = [col0[rp0[i]:rp0[i + 1]] if i % 7 else col0[:0] for i in range(n)]  # some rows empty
+        rp = np.concatenate([[0], np.cumsum([r.size for r in rows])]).astype(np.int64)
+        col = np.concatenate(rows).astype(np.int32)
+    else:
+        n = 12 * 11 * 10
+        rp, col = inputs.lattice_ball_links(12, 11, 10, 2)
+    if model == "kuramoto":
+        code, ocode, prm, y0, nv = nd.ND_KURAMOTO, O.KURAMOTO, KUR, inputs.kuramoto_phases(seed, n), 1
+    elif model == "fhn":
+        code, ocode, prm, y0, nv = nd.ND_FHN, O.FHN, FHN, inputs.fhn_circle(seed, n), 2
+    else:
+        code, ocode, prm, nv = nd.ND_KURAMOTO_INERTIA, O.INERTIA, INERT, 2
+        y0 = np.concatenate([inputs.kuramoto_phases(seed, n), inputs.uniform_range(seed, inputs.TAG_MISC, n, -0.5, 0.5)])
+    return (nd.problem(code, nd.ND_LINKS, n, prm, row_ptr=rp, col=col), O.links(ocode, n, rp, col, np.array(prm)),
+            y0, nv)
+
+
+@pytest.mark.parametrize("model,kind,t_end,rtol", [("fhn", "small_world", 1.0, 1e-7), ("kuramoto", "random", 3.0, 1e-8),
+                                                   ("inertia", "lattice", 2.0, 1e-9)])
+def test_adaptive_on_compressed_coupling_matrices(nd, model, kind, t_end, rtol):
+    """Dormand-Prince on arbitrary coupling matrices (the tiled path with the
+    compressed rows): the oracle's steps and state."""
+    print(f"case adaptive links {model} {kind}", flush=True)
+    p, onet, y0, nv = links_net(nd, model, kind, 13)
+    (y,), (st,) = run_gpu(nd, [p], [y0], [t_end], [1e-3], rtol, rtol * 1e-2)
+    ref, t, acc, rej, _ = O.run_dopri(onet, y0, t_end, rtol, rtol * 1e-2, 1e-3)
+    print(f"  gpu {st.accepted}/{st.rejected}  oracle {acc}/{rej}", flush=True)
+    assert (st.accepted, st.rejected) == (acc, rej) and st.t == t
+    assert normwise(y, ref, nv) < 1e-10
