@@ -205,9 +205,10 @@ typedef struct nd_kernel_config {
  * rtol <= 0 takes fixed steps of dt0 (no control).  The fifth-order solution propagates.
  * Each of the `count` networks is integrated from its current state over [0, t_end[i]]
  * starting with step dt0[i] on the device; each network controls its own step.  Supported:
- * FP64 rings (ND_RING) of the Kuramoto, Kuramoto-with-inertia or FHN model, one model per call
- * (ND_ERR_UNSUPPORTED otherwise).  When every ring holds at most 1024 elements, one workgroup
- * integrates each ring in a single launch; otherwise the batch is tiled over workgroups, with
+ * FP64 rings (ND_RING) or compressed coupling matrices (ND_LINKS) of the Kuramoto,
+ * Kuramoto-with-inertia or FHN model, one model and one topology per call (ND_ERR_UNSUPPORTED
+ * otherwise).  When every ring holds at most 1024 elements, one workgroup integrates each
+ * ring in a single launch; otherwise (and for ND_LINKS) the batch is tiled over workgroups, with
  * the accept / reject decisions taken on the device and only the rings' completion read back
  * every few attempts.  At most max_steps step attempts per network.  The state
  * is advanced in place (read it with nd_get_state); no observables are recorded.  Blocks
