@@ -37,6 +37,10 @@ Other workloads (one JSON line each, same fields):
                        1024: FHN rings of that size (P = floor(0.35 N), the
                        default workload's parameters and inputs) integrated over
                        t = 10, 16 rings, on the tiled path
+  --workload adaptive3d  the paper's 3D performance state (Kuramoto with inertia,
+                       100^3 lattice, ball of radius 2 as a compressed coupling
+                       matrix) integrated with Dormand-Prince over the paper's
+                       50 time units at rtol = 1e-6, atol = 1e-8
   --workload serve     continuous-batching server fed by seeded Poisson arrivals of
                        Kuramoto-ring and FHN-ring requests (50/50), N log-uniform in
                        [2^10, 2^22], P/N uniform in [0.05, 0.4], alpha uniform in
@@ -81,6 +85,7 @@ DEFAULTS = {  # workload: (batch, horizon, dt, n)
     "links": (1, 1000, 0.05, 100),
     "serve": (24, 0, 0.01, 0),
     "adaptive": (4096, 0, 0.0, 1024),
+    "adaptive3d": (1, 0, 0.0, 100),
 }
 DEFAULTS_N = {"fhn": 65536, "kuramoto": 1024, "cube": 200 ** 3, "hh": 1000000, "inertia": 100 ** 3,
               "ball": 100 ** 3, "links": 100 ** 3}
@@ -493,8 +498,15 @@ def main_adaptive(nd, torch, args, stream):
     """One call integrates every ring to t_end with its own step control."""
     from paper_2410_19075_amd import inputs
     n, rtol, atol = args.n, 1e-8, 1e-10
-    tiled = n > 1024
-    if tiled:  # the FHN ring of the default workload, on the tiled path
+    tiled = n > 1024 or args.workload == "adaptive3d"
+    if args.workload == "adaptive3d":  # the paper's 3D inertia state as a compressed coupling matrix
+        n1 = args.n
+        n = n1 ** 3
+        rows = inputs.lattice_ball_links(n1, n1, n1, 2)
+        P, t_end, prm, model, rtol, atol = 2, 50.0, INERTIA_PRM, nd.ND_KURAMOTO_INERTIA, 1e-6, 1e-8
+        state = lambda b: np.concatenate([inputs.cube_phases_with_patch(1000 + b, n1), np.zeros(n)])
+        nv = 2
+    elif tiled:  # the FHN ring of the default workload, on the tiled path
         P, t_end, prm, model = int(0.35 * n), 10.0, FHN_PRM, nd.ND_FHN
         state = lambda b: inputs.fhn_circle(1000 + b, n)
         nv = 2
@@ -502,7 +514,11 @@ def main_adaptive(nd, torch, args, stream):
         P, t_end, prm, model = n // 4, 100.0, [0.0, 1.0, 1.46], nd.ND_KURAMOTO
         state = lambda b: inputs.kuramoto_phases(1000 + b, n)
         nv = 1
-    hs = [nd.nd_create(nd.problem(model, nd.ND_RING, n, prm, radius=P)) for _ in range(args.batch)]
+    if args.workload == "adaptive3d":
+        hs = [nd.nd_create(nd.problem(model, nd.ND_LINKS, n, prm, row_ptr=rows[0], col=rows[1]))
+              for _ in range(args.batch)]
+    else:
+        hs = [nd.nd_create(nd.problem(model, nd.ND_RING, n, prm, radius=P)) for _ in range(args.batch)]
     y0s = [torch.from_numpy(state(b)).cuda() for b in range(args.batch)]
 
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -534,11 +550,16 @@ def main_adaptive(nd, torch, args, stream):
         # algorithmic bytes per element and accepted step: stage s (1..6) reads y and
         # k_1..k_s and writes k_{s+1}; the fifth-order solution is written once
         bpe = (sum(s + 2 for s in range(1, 7)) + 1) * 8 * nv
+        if args.workload == "adaptive3d":
+            bpe += 6 * (4 + 2 * 16)  # per stage: the row's table index, the exchanged map written and read
         achieved = acc * n * bpe / ev_total / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "kernel": "k_dt_map + k_dt_offsets + k_dt_rhs + k_dt_control", "bytes_per_element_step": bpe}
         what = f"{args.batch} FitzHugh-Nagumo rings N={n} P={P} (0.35N), eps=0.05 a=0.5 sigma=0.1 phi=pi/2-0.1"
+        if args.workload == "adaptive3d":
+            what = (f"Kuramoto-Sakaguchi with inertia, 3D lattice {args.n}^3 periodic, ball of radius 2 (33 links) "
+                    f"as a compressed coupling matrix, m=1 eps=0.05 mu=0.01 alpha=0.45, planted coherent ball, psi=0")
     else:
         # algorithmic FP64 flops per element and accepted step: 7 stages of the resident
         # kernel's per-stage work (KURAMOTO_RESIDENT_FLOPS / 4 each, sin/cos included)
@@ -553,7 +574,7 @@ def main_adaptive(nd, torch, args, stream):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"Dormand-Prince 5(4), {what}, t=0..{t_end}, rtol={rtol} atol={atol}, "
-                                  f"per-ring step control",
+                                  f"per-network step control",
                       "global_batch": args.batch, "parallelism": "single-gpu"},
            "accepted_steps": acc, "rejected_steps": rej, "roofline": roof}
     for h in hs:
@@ -562,16 +583,19 @@ def main_adaptive(nd, torch, args, stream):
         from oracle import oracle as O
         O.lib()
         y0 = state(0)
-        # a bounded sample: the Kuramoto ring to t_end, the large FHN ring to t = 0.01
+        # a bounded sample: the Kuramoto ring to t_end, the large FHN ring to t = 0.01,
+        # the lattice to t = 1
         ts = t_end if not tiled else 0.01
-        net = O.ring(O.FHN if tiled else O.KURAMOTO, n, P, prm)
+        net = O.ring(O.FHN if tiled else O.KURAMOTO, n, P, prm) if args.workload != "adaptive3d" else None
+        if args.workload == "adaptive3d":
+            ts, net = 1.0, O.links(O.INERTIA, n, rows[0], rows[1], np.array(prm))
         t0 = time.perf_counter()
         _, _, oacc, orej, _ = O.run_dopri(net, y0, ts, rtol, atol, 1e-3)
         sec = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {"value": oacc * n / sec, "unit": "oscillator-steps/s", "cores": cores,
                                "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
-                               "sample": f"one ring N={n} P={P}, Dormand-Prince 5(4) to t={ts}, "
+                               "sample": f"one network of {n} elements, Dormand-Prince 5(4) to t={ts}, "
                                          f"{oacc} accepted / {orej} rejected steps, FP64, {sec:.2f} s"}
     print(json.dumps(out), flush=True)
 
@@ -607,7 +631,7 @@ def main():
     if args.workload == "serve":
         main_serve(nd, torch, args, stream)
         return
-    if args.workload == "adaptive":
+    if args.workload in ("adaptive", "adaptive3d"):
         main_adaptive(nd, torch, args, stream)
         return
     wl = Workload(args, nd)
