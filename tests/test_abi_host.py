@@ -233,3 +233,42 @@ def test_links_malformed_rows_are_rejected(bad):
         p = nd.problem(nd.ND_KURAMOTO, nd.ND_LINKS, n, [0, 1, 0.5], row_ptr=rp, col=col)
         with pytest.raises(nd.NDError):
             nd.nd_footprint(p)
+
+
+def test_header_is_plain_c_and_host_calls_work_from_c(tmp_path):
+    """include/nd.h compiles as C99, and a C program linked against libnd.so
+    calls the host-only entry points (compression of a ring: one empty table
+    entry; error reporting) without a GPU."""
+    import subprocess
+    from paper_2410_19075_amd import nd
+    src = tmp_path / "use_nd.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <stdint.h>
+#include "nd.h"
+int main(void) {
+    enum { N = 40, P = 3 };
+    int64_t row_ptr[N + 1];
+    int32_t col[N * 2 * P];
+    for (int i = 0; i <= N; ++i) row_ptr[i] = (int64_t)i * 2 * P;
+    for (int i = 0; i < N; ++i) {
+        int c = 0;
+        for (int k = -P; k <= P; ++k)
+            if (k) col[i * 2 * P + c++] = (int32_t)((i + k + N) % N);
+    }
+    nd_links_info info;
+    nd_status s = nd_compress_links(N, row_ptr, col, NULL, 0, NULL, 0, NULL, 0, NULL, 0, &info);
+    printf("%d %lld %lld %lld\n", (int)s, (long long)info.v_bits, (long long)info.entries, (long long)info.d_bits);
+    col[1] = col[0];  /* a source listed twice */
+    s = nd_compress_links(N, row_ptr, col, NULL, 0, NULL, 0, NULL, 0, NULL, 0, &info);
+    printf("%d %s\n", (int)s, nd_status_str(s));
+    return 0;
+}
+""")
+    exe = tmp_path / "use_nd"
+    libdir = os.path.dirname(nd.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", libdir, "-l:libnd.so", "-Wl,-rpath," + libdir], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    assert out[0].split() == ["0", "6", "1", "0"]
+    assert out[1].startswith("-1 invalid argument")
