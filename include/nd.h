@@ -236,8 +236,7 @@ nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end
  * Y (host, may be NULL; count * y_stride doubles): Y[i * y_stride + k * nvars * n + v * n + j]
  * = variable v of element j at t_k; y_stride >= (outputs of i) * nvars * n_i.
  * Outputs a network does not reach (max_steps) read NaN.  The device holds R and Y in a
- * scratch buffer for the call.  Rings of at most 1024 elements only (ND_ERR_UNSUPPORTED
- * otherwise).  Otherwise as nd_run_adaptive. */
+ * scratch buffer for the call.  Otherwise as nd_run_adaptive. */
 nd_status nd_run_adaptive_dense(const nd_handle* h, int32_t count, const double* t_end, const double* dt0,
                                 double rtol, double atol, int64_t max_steps, double t_out, double* R,
                                 int64_t r_stride, double* Y, int64_t y_stride, nd_adaptive_stats* stats,

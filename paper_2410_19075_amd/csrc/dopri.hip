@@ -283,6 +283,11 @@ struct DtCtl {
     double t, h, hs, facmax;
     int64_t acc, rej;
     int32_t done, last, f, ypar;  // f: physical buffer of k1 (k_q lives at (f + q - 1) mod 7)
+    // dense output: outputs [out_lo, out_hi) lie in the step just accepted, which
+    // started at t_prev with size hs_prev, state y[ypar_prev] and k1 at f_prev
+    int64_t next, out_lo, out_hi;
+    double t_prev, hs_prev;
+    int32_t f_prev, ypar_prev;
 };
 
 // Per-ring buffers of one call.
@@ -296,6 +301,10 @@ struct DtNet {
     double* tot;      // [2][G] tile totals, then (after the offsets launch) exclusive offsets
     double* errp;     // [G] error partial sums of the attempt
     DtCtl* ctl;
+    int64_t K;        // dense output: last output index (-1: none)
+    double* Rpart;    // dense output: [K + 1][G][2] per-tile sums of the order parameter
+    double* R;        // dense output: R of outputs 0 .. K (device)
+    double* Y;        // dense output: states at the outputs (device, may be NULL)
 };
 
 template <int MODEL>
@@ -478,12 +487,19 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
 
 // The accept / reject decision of the attempt and the next step (one thread
 // per ring; the error partials are added in tile order).
-__global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol, int64_t max_steps) {
+__global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol, int64_t max_steps, double t_out) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= count) return;
     const DtNet& r = R[b];
     DtCtl c = *r.ctl;
-    if (c.done) return;
+    if (c.done) {
+        if (c.out_hi != c.out_lo) {  // nothing more to emit
+            c.out_lo = c.out_hi = 0;
+            *r.ctl = c;
+        }
+        return;
+    }
+    c.out_lo = c.out_hi = 0;
     bool accept = true;
     double f = 1.0;
     if (rtol > 0.0) {
@@ -494,6 +510,16 @@ __global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol
         accept = err <= 1.0;
     }
     if (accept) {
+        if (r.K >= 0) {  // outputs inside (t, t + hs]; the last step takes every one left
+            const double tn = c.last ? r.tend : c.t + c.hs;
+            c.out_lo = c.next;
+            while (c.next <= r.K && ((double)c.next * t_out <= tn || c.last)) ++c.next;
+            c.out_hi = c.next;
+            c.t_prev = c.t;
+            c.hs_prev = c.hs;
+            c.f_prev = c.f;
+            c.ypar_prev = c.ypar;
+        }
         c.t = c.last ? r.tend : c.t + c.hs;
         ++c.acc;
         if (rtol > 0.0) c.h = c.hs * fmin(c.facmax, fmax(0.2, f));
@@ -512,6 +538,77 @@ __global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol
     }
     *r.ctl = c;
 }
+
+// Dense output of the step just accepted: for each of its outputs, the
+// continuous extension on the tile's elements (the state, when requested) and
+// the tile's sums of the order parameter's unit vectors.
+template <int MODEL>
+__global__ __launch_bounds__(kDtBS) void k_dt_emit(const DtNet* __restrict__ R, const int2* __restrict__ work,
+                                                   double t_out) {
+    using M = RingModel<MODEL, double>;
+    constexpr int V = M::V, NW = kDtBS / kWave;
+    __shared__ double lds[2 * NW];
+    const int2 wk = work[blockIdx.x];
+    const DtNet& r = R[wk.x];
+    const DtCtl c = *r.ctl;
+    if (c.out_hi <= c.out_lo) return;
+    const int n = r.n, t0 = wk.y * kDtT, tid = threadIdx.x;
+    const double* y = r.y[c.ypar_prev];
+    for (int64_t ko = c.out_lo; ko < c.out_hi; ++ko) {
+        const double theta = fmin(((double)ko * t_out - c.t_prev) / c.hs_prev, 1.0);
+        double wt[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double b = q < 6 ? kDpA[6][q] : 0.0, e1 = q == 0 ? 1.0 : 0.0, e7 = q == 6 ? 1.0 : 0.0;
+            wt[q] = theta * (b + (1.0 - theta) * (e1 - b + theta * (2.0 * b - e1 - e7 + (1.0 - theta) * kDpD[q])));
+        }
+        double s2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < kDtEPT; ++e) {
+            const int i = t0 + tid * kDtEPT + e;
+            if (i >= n) continue;
+            double yt[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                yt[v] = y[(int64_t)v * n + i];
+                if (theta != 0.0) {  // theta = 0: the initial state (no stage slopes yet)
+                    double a = 0.0;
+                    for (int q = 0; q < 7; ++q) a += wt[q] * r.k[(c.f_prev + q) % 7][(int64_t)v * n + i];
+                    yt[v] += c.hs_prev * a;
+                }
+                if (r.Y) r.Y[ko * V * n + (int64_t)v * n + i] = yt[v];
+            }
+            if constexpr (MODEL == ND_FHN) {
+                const double rr = sqrt(yt[0] * yt[0] + yt[1] * yt[1]);
+                s2[0] += yt[0] / rr;
+                s2[1] += yt[1] / rr;
+            } else {
+                const double2 x = M::map(yt);
+                s2[0] += x.x;
+                s2[1] += x.y;
+            }
+        }
+        block_sum<kDtBS, 2>(s2, lds);
+        if (tid == 0) {
+            r.Rpart[(ko * r.G + wk.y) * 2] = s2[0];
+            r.Rpart[(ko * r.G + wk.y) * 2 + 1] = s2[1];
+        }
+    }
+}
+
+// R of every emitted output from the tiles' sums, added in tile order.
+__global__ __launch_bounds__(kDtBS) void k_dt_reduce_R(const DtNet* __restrict__ R) {
+    const DtNet& r = R[blockIdx.x];
+    const int64_t emitted = min(r.ctl->next, r.K + 1);
+    for (int64_t ko = threadIdx.x; ko < emitted; ko += kDtBS) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int q = 0; q < r.G; ++q) {
+            s0 += r.Rpart[(ko * r.G + q) * 2];
+            s1 += r.Rpart[(ko * r.G + q) * 2 + 1];
+        }
+        r.R[ko] = sqrt(s0 * s0 + s1 * s1) / (double)r.n;
+    }
+}
 }  // namespace nd
 
 using namespace nd;
@@ -520,7 +617,9 @@ using namespace nd;
 // replayed in groups of attempts until every ring is done.
 static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, int topo, const double* t_end,
                                     const double* dt0, double rtol, double atol, int64_t max_steps,
-                                    nd_adaptive_stats* stats, hipStream_t st) {
+                                    nd_adaptive_stats* stats, hipStream_t st, double t_out, double* Rh,
+                                    int64_t r_stride, double* Yh, int64_t y_stride) {
+    const bool dense = t_out > 0.0;
     const int count = (int)nets.size();
     std::vector<DtNet> rs(count);
     std::vector<DtCtl> cs(count);
@@ -531,10 +630,13 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         const Net* nt = nets[b];
         const int64_t n = nt->prob.n, len = nvars_of(nt->prob.model) * n, G = (n + kDtT - 1) / kDtT;
         bytes += (size_t)(8 * len + 4 * n + 3 * G) * 8 + sizeof(DtCtl);
+        if (dense) bytes += (size_t)(2 * ((int64_t)std::floor(t_end[b] / t_out) + 1) * G) * 8;
         for (int64_t t = 0; t < G; ++t) work.push_back(make_int2(b, (int)t));
     }
     const size_t bd = (size_t)count * sizeof(DtNet), bn = (size_t)count * sizeof(NetDesc),
                  bw = work.size() * sizeof(int2);
+    const size_t br = dense ? (size_t)count * r_stride * 8 : 0, by = dense && Yh ? (size_t)count * y_stride * 8 : 0;
+    bytes += br + by;
     char* buf = nullptr;
     hipError_t e = hipMallocAsync((void**)&buf, bd + bn + bw + bytes + 256, st);
     if (e != hipSuccess) return hip_fail(e, "adaptive scratch");
@@ -565,6 +667,10 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         r.tot = (double*)take(2 * r.G * 8);
         r.errp = (double*)take(r.G * 8);
         r.ctl = (DtCtl*)take(sizeof(DtCtl));
+        r.K = dense ? (int64_t)std::floor(t_end[b] / t_out) : -1;
+        r.Rpart = dense ? (double*)take(2 * (r.K + 1) * r.G * 8) : nullptr;
+        r.R = nullptr;
+        r.Y = nullptr;
         DtCtl& c = cs[b];
         c = DtCtl{};
         c.h = dt0[b];
@@ -572,6 +678,18 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         c.done = !(0.0 < t_end[b] && max_steps > 0);
         c.last = t_end[b] <= c.h * (1.0 + 1e-12);
         c.hs = c.last ? t_end[b] : c.h;
+        if (r.K >= 0) {  // output 0 is the initial state (theta = 0)
+            c.out_lo = 0;
+            c.out_hi = 1;
+            c.next = 1;
+            c.hs_prev = 1.0;
+        }
+    }
+    double* d_R = dense ? (double*)take(br) : nullptr;
+    double* d_Y = by ? (double*)take(by) : nullptr;
+    for (int b = 0; b < count; ++b) {
+        if (d_R) rs[b].R = d_R + (size_t)b * r_stride;
+        if (d_Y) rs[b].Y = d_Y + (size_t)b * y_stride;
     }
     const int tiles = (int)work.size();
     auto stage = [&](int s) {
@@ -597,20 +715,31 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         }
         return hipGetLastError();
     };
+    auto emit = [&]() {
+        if (model == ND_KURAMOTO) hipLaunchKernelGGL(k_dt_emit<ND_KURAMOTO>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, t_out);
+        else if (model == ND_FHN) hipLaunchKernelGGL(k_dt_emit<ND_FHN>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, t_out);
+        else hipLaunchKernelGGL(k_dt_emit<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, t_out);
+        return hipGetLastError();
+    };
+    // outputs a run does not reach read as NaN (all bits set)
+    if (dense) e = hipMemsetAsync(d_R, 0xff, br + by, st);
     // the control blocks live inside the scratch: write them with the descriptors
     for (int b = 0; b < count && e == hipSuccess; ++b)
         e = hipMemcpyAsync(rs[b].ctl, &cs[b], sizeof(DtCtl), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_r, rs.data(), bd, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_desc, descs.data(), bn, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(d_work, work.data(), bw, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = stage(0);  // k1 = f(y)
+    if (e == hipSuccess && dense) e = emit();  // output 0
+    if (e == hipSuccess) e = stage(0);            // k1 = f(y)
     constexpr int kAttempts = 8;        // attempts launched between checks of the done flags
     while (e == hipSuccess) {
         for (int a = 0; a < kAttempts && e == hipSuccess; ++a) {
             for (int s = 1; s <= 6 && e == hipSuccess; ++s) e = stage(s);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL(k_dt_control, dim3((count + 63) / 64), dim3(64), 0, st, d_r, count, rtol, max_steps);
+                hipLaunchKernelGGL(k_dt_control, dim3((count + 63) / 64), dim3(64), 0, st, d_r, count, rtol, max_steps,
+                                   t_out);
                 e = hipGetLastError();
+                if (e == hipSuccess && dense) e = emit();
             }
         }
         for (int b = 0; b < count && e == hipSuccess; ++b)
@@ -620,6 +749,12 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         bool all = true;
         for (const DtCtl& c : cs) all = all && c.done;
         if (all) break;
+    }
+    if (e == hipSuccess && dense) {
+        hipLaunchKernelGGL(k_dt_reduce_R, dim3(count), dim3(kDtBS), 0, st, d_r);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(Rh, d_R, br, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && by) e = hipMemcpyAsync(Yh, d_Y, by, hipMemcpyDeviceToHost, st);
     }
     // a state that ended in the scratch buffer goes back to the network
     for (int b = 0; b < count && e == hipSuccess; ++b)
@@ -681,8 +816,8 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
         descs[i] = n->run_desc(dt0[i], 0);
     }
     if (tiled) {
-        if (dense) return fail(ND_ERR_UNSUPPORTED, "dense output is for rings of at most %d elements", kDpCap);
-        return run_adaptive_tiled(nets, model, topo, t_end, dt0, rtol, atol, max_steps, stats, (hipStream_t)stream);
+        return run_adaptive_tiled(nets, model, topo, t_end, dt0, rtol, atol, max_steps, stats, (hipStream_t)stream,
+                                  dense ? t_out : 0.0, R, r_stride, Y, y_stride);
     }
     hipStream_t st = (hipStream_t)stream;
     void* buf = nullptr;

@@ -260,14 +260,35 @@ def test_tiled_adaptive_batch_fixed_steps_and_budget(nd):
     assert s.t == pytest.approx(t, rel=1e-6) and normwise(y, ref, nv) < 1e-6
 
 
-def test_tiled_adaptive_rejects_dense_output(nd):
-    h = nd.nd_create(nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 3000, KUR, radius=100))
+@pytest.mark.parametrize("case", ["ring", "links"])
+def test_tiled_dense_output_matches_oracle(nd, case):
+    """Dense output on the tiled path (a ring of 3000, a compressed small-world
+    matrix): R and the state at every output time, as the oracle's."""
+    print(f"case tiled dense {case}", flush=True)
+    if case == "ring":
+        p, onet, y0, nv = net(nd, "kuramoto", 3000, 700, 31)
+        t_end, rtol, t_out = 2.0, 1e-8, 0.1
+    else:
+        p, onet, y0, nv = links_net(nd, "fhn", "small_world", 32)
+        t_end, rtol, t_out = 1.0, 1e-7, 0.05
+    n = y0.size // nv
+    h = nd.nd_create(p)
     try:
-        with pytest.raises(nd.NDError) as ei:
-            nd.nd_run_adaptive_dense([h], [1.0], [1e-3], 1e-6, 1e-9, 0.1)
-        assert ei.value.status == nd.ND_ERR_UNSUPPORTED
+        nd.nd_set_state(h, y0, on_device=0)
+        (st,), R, Y = nd.nd_run_adaptive_dense([h], [t_end], [1e-3], rtol, rtol * 1e-2, t_out, state_len=nv * n)
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
     finally:
         nd.nd_destroy(h)
+    ref, t, acc, rej, _, Rref, Yref = O.run_dopri_dense(onet, y0, t_end, rtol, rtol * 1e-2, 1e-3, t_out, states=True)
+    assert (st.accepted, st.rejected) == (acc, rej) and st.t == t
+    K = int(np.floor(t_end / t_out))
+    assert not np.any(np.isnan(R[0]))
+    assert np.max(np.abs(R[0] - Rref)) < 1e-9
+    Yg = Y[0].reshape(K + 1, nv * n)
+    for k in range(K + 1):
+        assert normwise(Yg[k], Yref[k], nv) < 1e-9
+    assert normwise(y, ref, nv) < 1e-10
 
 
 def links_net(nd, model, kind, seed):
