@@ -523,6 +523,7 @@ def main_adaptive(nd, torch, args, stream):
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    Rs = []
 
     def one():
         for h, y0 in zip(hs, y0s):
@@ -530,7 +531,12 @@ def main_adaptive(nd, torch, args, stream):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0.record(stream)
-        st = nd.nd_run_adaptive(hs, [t_end] * len(hs), [1e-3] * len(hs), rtol, atol, stream=stream)
+        if args.workload == "adaptive3d":  # with R at every time unit from the dense output
+            st, Rout, _ = nd.nd_run_adaptive_dense(hs, [t_end] * len(hs), [1e-3] * len(hs), rtol, atol, 1.0,
+                                                   stream=stream)
+            Rs.append(Rout[0])
+        else:
+            st = nd.nd_run_adaptive(hs, [t_end] * len(hs), [1e-3] * len(hs), rtol, atol, stream=stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3, st
@@ -577,6 +583,8 @@ def main_adaptive(nd, torch, args, stream):
                                   f"per-network step control",
                       "global_batch": args.batch, "parallelism": "single-gpu"},
            "accepted_steps": acc, "rejected_steps": rej, "roofline": roof}
+    if Rs:
+        out["R_every_10_time_units"] = [float(x) for x in Rs[-1][::10]]
     for h in hs:
         nd.nd_destroy(h)
     if not args.no_cpu_baseline:
