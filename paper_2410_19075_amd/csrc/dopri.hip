@@ -1,8 +1,9 @@
-// Dormand-Prince 5(4) with step-size control for rings held by one workgroup,
-// entirely on the device.
+// Dormand-Prince 5(4) with step-size control on the device: rings held by one
+// workgroup each, and (further below) rings of any size and compressed
+// coupling matrices tiled over workgroups.
 //
 // The paper's default solver is the adaptive embedded pair of Dormand and
-// Prince (Sec. III.A).  Here every ring of up to 1024 elements is integrated
+// Prince (Sec. III.A).  Every ring of up to 1024 elements is integrated
 // by one workgroup from t = 0 to its own t_end: the state and the seven stage
 // slopes stay in registers, each stage's window sums come from LDS prefix sums
 // of the mapped stage values (as in the resident RK4 kernel), and the step
