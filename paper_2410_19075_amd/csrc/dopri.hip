@@ -297,6 +297,7 @@ struct DtNet {
     double tend;
     double* y[2];     // state, and the fifth-order solution of the attempt
     double* k[7];     // stage slopes (physical buffers)
+    double* Z;        // stage value of stages 1 .. 5 (stage 0 is y, stage 6 goes to y[ypar ^ 1])
     double* M;        // [2][n] map of the current stage value
     double* pre;      // [2][n] in-tile inclusive prefix of M
     double* tot;      // [2][G] tile totals, then (after the offsets launch) exclusive offsets
@@ -343,9 +344,10 @@ __global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, c
             double z[V];
             dt_stage_value<MODEL>(r, c, s, i, z);
             x = M::map(z);
-            if (s == 6) {
+            if (s > 0) {  // kept for the RHS launch of this stage
+                double* zo = s == 6 ? r.y[c.ypar ^ 1] : r.Z;
 #pragma unroll
-                for (int v = 0; v < V; ++v) r.y[c.ypar ^ 1][(int64_t)v * n + i] = z[v];
+                for (int v = 0; v < V; ++v) zo[(int64_t)v * n + i] = z[v];
             }
             r.M[i] = x.x;
             r.M[n + i] = x.y;
@@ -422,8 +424,11 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
     for (int e = 0; e < kDtEPT; ++e) {
         const int i = t0 + tid * kDtEPT + e;
         if (i >= n) continue;
+        // the stage value as the map launch computed it
+        const double* zs = s == 0 ? r.y[c.ypar] : (s == 6 ? r.y[c.ypar ^ 1] : r.Z);
         double z[V];
-        dt_stage_value<MODEL>(r, c, s, i, z);
+#pragma unroll
+        for (int v = 0; v < V; ++v) z[v] = zs[(int64_t)v * n + i];
         const double2 x = make_double2(r.M[i], r.M[n + i]);
         double2 W;
         if constexpr (TOPO == ND_RING) {
@@ -630,7 +635,7 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
     for (int b = 0; b < count; ++b) {
         const Net* nt = nets[b];
         const int64_t n = nt->prob.n, len = nvars_of(nt->prob.model) * n, G = (n + kDtT - 1) / kDtT;
-        bytes += (size_t)(8 * len + 4 * n + 3 * G) * 8 + sizeof(DtCtl);
+        bytes += (size_t)(9 * len + 4 * n + 3 * G) * 8 + sizeof(DtCtl);
         if (dense) bytes += (size_t)(2 * ((int64_t)std::floor(t_end[b] / t_out) + 1) * G) * 8;
         for (int64_t t = 0; t < G; ++t) work.push_back(make_int2(b, (int)t));
     }
@@ -663,6 +668,7 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         r.y[0] = descs[b].y[descs[b].ypar];
         r.y[1] = (double*)take(len * 8);
         for (int q = 0; q < 7; ++q) r.k[q] = (double*)take(len * 8);
+        r.Z = (double*)take(len * 8);
         r.M = (double*)take(2 * n * 8);
         r.pre = (double*)take(2 * n * 8);
         r.tot = (double*)take(2 * r.G * 8);
