@@ -80,6 +80,21 @@ def test_csr_validation():
         nd.nd_footprint(bad)
 
 
+def test_size_limits_of_rings_and_lattices():
+    """Rings and lattices hold at most 2^29 - 1 elements (32-bit element
+    offsets with headroom for window ends); one more is rejected on the host."""
+    from paper_2410_19075_amd import nd
+    top = 2 ** 29 - 1
+    ring = lambda n: nd.problem(nd.ND_KURAMOTO, nd.ND_RING, n, [0.0, 1.0, 1.46], radius=n // 4)
+    assert nd.nd_footprint(ring(top)) > 6 * top * 8
+    with pytest.raises(nd.NDError):
+        nd.nd_footprint(ring(top + 1))
+    cube = lambda e: nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, e ** 3, [0.0, 1.0, 0.8], radius=4, dims=(e, e, e))
+    assert nd.nd_footprint(cube(800)) > 0
+    with pytest.raises(nd.NDError):
+        nd.nd_footprint(cube(813))  # 813^3 > 2^29
+
+
 def test_footprint_grows_with_precision_and_size():
     from paper_2410_19075_amd import nd
     f64 = nd.nd_footprint(nd.problem(nd.ND_FHN, nd.ND_RING, 65536, [0.05, 0.5, 0.1, 1.47], radius=22937))
