@@ -309,67 +309,71 @@ struct DtNet {
     double* Y;        // dense output: states at the outputs (device, may be NULL)
 };
 
-template <int MODEL>
-__device__ __forceinline__ void dt_stage_value(const DtNet& r, const DtCtl& c, int s, int i, double* z) {
-    using M = RingModel<MODEL, double>;
-    constexpr int V = M::V;
-    const double* y = r.y[c.ypar];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        double a = 0.0;
-        for (int q = 0; q < s; ++q) a += kDpA[s][q] * r.k[(c.f + q) % 7][(int64_t)v * r.n + i];
-        z[v] = s == 0 ? y[(int64_t)v * r.n + i] : y[(int64_t)v * r.n + i] + c.hs * a;
-    }
-}
-
-// Stage value z of stage s (s = 0: the state; s = 6: the fifth-order
+// Stage value z of stage S (S = 0: the state; S = 6: the fifth-order
 // solution, kept in y[ypar ^ 1]), its map and the tile's inclusive prefix.
-template <int MODEL>
-__global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, const int2* __restrict__ work, int s) {
+// Element e * kDtBS + tid of the tile belongs to thread tid, so every access
+// of a wave is one contiguous run; the stage is a template parameter so the
+// slopes' loads are all issued before the sums that use them.
+template <int MODEL, int S>
+__global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, const int2* __restrict__ work) {
     using M = RingModel<MODEL, double>;
-    constexpr int V = M::V, NW = kDtBS / kWave;
-    __shared__ double lds[4 * NW];
+    constexpr int V = M::V, NW = kDtBS / kWave, NE = 2 * kDtEPT;
+    __shared__ double lds[2 * NE * NW];
     const int2 wk = work[blockIdx.x];
     const DtNet& r = R[wk.x];
     const DtCtl c = *r.ctl;
     if (c.done) return;
     const int n = r.n, t0 = wk.y * kDtT, tid = threadIdx.x;
-    double tot[2] = {0.0, 0.0}, none[1] = {0.0};
-    double pv[kDtEPT][2];
+    const double* __restrict__ y = r.y[c.ypar];
+    const double* kq[S > 0 ? S : 1];
+#pragma unroll
+    for (int q = 0; q < S; ++q) kq[q] = r.k[(c.f + q) % 7];
+    double* __restrict__ zo = S == 6 ? r.y[c.ypar ^ 1] : r.Z;
+    double xs[NE];
 #pragma unroll
     for (int e = 0; e < kDtEPT; ++e) {
-        const int i = t0 + tid * kDtEPT + e;
+        const int i = t0 + e * kDtBS + tid;
         double2 x = make_double2(0.0, 0.0);
         if (i < n) {
             double z[V];
-            dt_stage_value<MODEL>(r, c, s, i, z);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int64_t o = (int64_t)v * n + i;
+                double a = 0.0;
+#pragma unroll
+                for (int q = 0; q < S; ++q) a += kDpA[S][q] * kq[q][o];
+                z[v] = S == 0 ? y[o] : y[o] + c.hs * a;
+            }
             x = M::map(z);
-            if (s > 0) {  // kept for the RHS launch of this stage
-                double* zo = s == 6 ? r.y[c.ypar ^ 1] : r.Z;
+            if (S > 0) {  // kept for the RHS launch of this stage
 #pragma unroll
                 for (int v = 0; v < V; ++v) zo[(int64_t)v * n + i] = z[v];
             }
             r.M[i] = x.x;
             r.M[n + i] = x.y;
         }
-        tot[0] += x.x;
-        tot[1] += x.y;
-        pv[e][0] = tot[0];
-        pv[e][1] = tot[1];
+        xs[2 * e] = x.x;
+        xs[2 * e + 1] = x.y;
     }
-    const double own0 = tot[0], own1 = tot[1];
-    block_sum_and_exscan<kDtBS, 1, 2>(none, tot, lds);
+    // block sums and thread-exclusive prefixes of each element run
+    double bs[NE], ex[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) bs[q] = ex[q] = xs[q];
+    block_sum_and_exscan<kDtBS, NE, NE>(bs, ex, lds);
+    double off0 = 0.0, off1 = 0.0;
 #pragma unroll
     for (int e = 0; e < kDtEPT; ++e) {
-        const int i = t0 + tid * kDtEPT + e;
+        const int i = t0 + e * kDtBS + tid;
         if (i < n) {
-            r.pre[i] = tot[0] + pv[e][0];
-            r.pre[n + i] = tot[1] + pv[e][1];
+            r.pre[i] = off0 + (ex[2 * e] + xs[2 * e]);
+            r.pre[n + i] = off1 + (ex[2 * e + 1] + xs[2 * e + 1]);
         }
+        off0 += bs[2 * e];
+        off1 += bs[2 * e + 1];
     }
-    if (tid == kDtBS - 1) {
-        r.tot[wk.y] = tot[0] + own0;
-        r.tot[r.G + wk.y] = tot[1] + own1;
+    if (tid == 0) {
+        r.tot[wk.y] = off0;
+        r.tot[r.G + wk.y] = off1;
     }
 }
 
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
     double es[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < kDtEPT; ++e) {
-        const int i = t0 + tid * kDtEPT + e;
+        const int i = t0 + e * kDtBS + tid;
         if (i >= n) continue;
         // the stage value as the map launch computed it
         const double* zs = s == 0 ? r.y[c.ypar] : (s == 6 ? r.y[c.ypar ^ 1] : r.Z);
@@ -510,6 +514,7 @@ __global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol
     double f = 1.0;
     if (rtol > 0.0) {
         double sum = 0.0;
+#pragma unroll 8
         for (int q = 0; q < r.G; ++q) sum += r.errp[q];
         const double err = sqrt(sum / ((double)r.V * (double)r.n));
         f = 0.9 * pow(err, -0.2);
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(kDtBS) void k_dt_emit(const DtNet* __restrict__ R, 
         double s2[2] = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < kDtEPT; ++e) {
-            const int i = t0 + tid * kDtEPT + e;
+            const int i = t0 + e * kDtBS + tid;
             if (i >= n) continue;
             double yt[V];
 #pragma unroll
@@ -618,6 +623,25 @@ __global__ __launch_bounds__(kDtBS) void k_dt_reduce_R(const DtNet* __restrict__
 }  // namespace nd
 
 using namespace nd;
+
+typedef void (*DtMapFn)(const DtNet*, const int2*);
+template <int MODEL>
+static DtMapFn dt_map_of_model(int s) {
+    switch (s) {
+        case 0: return k_dt_map<MODEL, 0>;
+        case 1: return k_dt_map<MODEL, 1>;
+        case 2: return k_dt_map<MODEL, 2>;
+        case 3: return k_dt_map<MODEL, 3>;
+        case 4: return k_dt_map<MODEL, 4>;
+        case 5: return k_dt_map<MODEL, 5>;
+        default: return k_dt_map<MODEL, 6>;
+    }
+}
+static DtMapFn dt_map_kernel(int model, int s) {
+    if (model == ND_KURAMOTO) return dt_map_of_model<ND_KURAMOTO>(s);
+    if (model == ND_FHN) return dt_map_of_model<ND_FHN>(s);
+    return dt_map_of_model<ND_KURAMOTO_INERTIA>(s);
+}
 
 // Rings beyond one workgroup: buffers per ring, the stage / controller launches
 // replayed in groups of attempts until every ring is done.
@@ -700,13 +724,8 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
     }
     const int tiles = (int)work.size();
     auto stage = [&](int s) {
-        if (model == ND_KURAMOTO) {
-            hipLaunchKernelGGL(k_dt_map<ND_KURAMOTO>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
-        } else if (model == ND_FHN) {
-            hipLaunchKernelGGL(k_dt_map<ND_FHN>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
-        } else {
-            hipLaunchKernelGGL(k_dt_map<ND_KURAMOTO_INERTIA>, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work, s);
-        }
+        const DtMapFn map = dt_map_kernel(model, s);
+        hipLaunchKernelGGL(map, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work);
         if (topo == ND_RING) hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
         auto rhs = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol, atol);
