@@ -294,11 +294,12 @@ struct DtCtl {
 // Per-ring buffers of one call.
 struct DtNet {
     int32_t n, P, G, V;
+    int32_t gather;   // the RHS reads other elements' maps (compressed coupling matrix)
     double tend;
     double* y[2];     // state, and the fifth-order solution of the attempt
     double* k[7];     // stage slopes (physical buffers)
     double* Z;        // stage value of stages 1 .. 5 (stage 0 is y, stage 6 goes to y[ypar ^ 1])
-    double* M;        // [2][n] map of the current stage value
+    double* M;        // [2][n] map of the current stage value (written when gather is set)
     double* pre;      // [2][n] in-tile inclusive prefix of M
     double* tot;      // [2][G] tile totals, then (after the offsets launch) exclusive offsets
     double* errp;     // [G] error partial sums of the attempt
@@ -349,8 +350,10 @@ __global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, c
 #pragma unroll
                 for (int v = 0; v < V; ++v) zo[(int64_t)v * n + i] = z[v];
             }
-            r.M[i] = x.x;
-            r.M[n + i] = x.y;
+            if (r.gather) {
+                r.M[i] = x.x;
+                r.M[n + i] = x.y;
+            }
         }
         xs[2 * e] = x.x;
         xs[2 * e + 1] = x.y;
@@ -433,7 +436,9 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
         double z[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) z[v] = zs[(int64_t)v * n + i];
-        const double2 x = make_double2(r.M[i], r.M[n + i]);
+        // the element's own map: stored by the map launch where the rows gather
+        // maps anyway, else recomputed from the same stage value (same bits)
+        const double2 x = TOPO == ND_LINKS ? make_double2(r.M[i], r.M[n + i]) : M::map(z);
         double2 W;
         if constexpr (TOPO == ND_RING) {
             const int lo = i - P, hi = i + P;
@@ -685,6 +690,7 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         DtNet& r = rs[b];
         r.n = (int32_t)n;
         r.P = (int32_t)nt->prob.radius;
+        r.gather = topo == ND_LINKS;
         r.G = (int32_t)((n + kDtT - 1) / kDtT);
         r.V = nvars_of(nt->prob.model);
         r.tend = t_end[b];
