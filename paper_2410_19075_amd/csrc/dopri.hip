@@ -299,7 +299,7 @@ struct DtNet {
     double* y[2];     // state, and the fifth-order solution of the attempt
     double* k[7];     // stage slopes (physical buffers)
     double* Z;        // stage value of stages 1 .. 5 (stage 0 is y, stage 6 goes to y[ypar ^ 1])
-    double* M;        // [2][n] map of the current stage value (written when gather is set)
+    double* M;        // [n] map of the current stage value, as double2 (written when gather is set)
     double* pre;      // [2][n] in-tile inclusive prefix of M
     double* tot;      // [2][G] tile totals, then (after the offsets launch) exclusive offsets
     double* errp;     // [G] error partial sums of the attempt
@@ -350,10 +350,7 @@ __global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, c
 #pragma unroll
                 for (int v = 0; v < V; ++v) zo[(int64_t)v * n + i] = z[v];
             }
-            if (r.gather) {
-                r.M[i] = x.x;
-                r.M[n + i] = x.y;
-            }
+            if (r.gather) ((double2*)r.M)[i] = x;
         }
         xs[2 * e] = x.x;
         xs[2 * e + 1] = x.y;
@@ -413,11 +410,15 @@ __global__ __launch_bounds__(kDtBS) void k_dt_offsets(const DtNet* __restrict__ 
 // the attempt.
 template <int MODEL, int TOPO>
 __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, const NetDesc* __restrict__ D,
-                                                  const int2* __restrict__ work, int s, double rtol, double atol) {
+                                                  const int2* __restrict__ work, int nwork, int s, double rtol,
+                                                  double atol) {
     using M = RingModel<MODEL, double>;
     constexpr int V = M::V, NW = kDtBS / kWave;
     __shared__ double lds[NW];
-    const int2 wk = work[blockIdx.x];
+    // row tiles that share gathers stay on one XCD (its own L2)
+    const int w = xcd_work(blockIdx.x, nwork);
+    if (w < 0) return;
+    const int2 wk = work[w];
     const DtNet& r = R[wk.x];
     const NetDesc& d = D[wk.x];
     const DtCtl c = *r.ctl;
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
         for (int v = 0; v < V; ++v) z[v] = zs[(int64_t)v * n + i];
         // the element's own map: stored by the map launch where the rows gather
         // maps anyway, else recomputed from the same stage value (same bits)
-        const double2 x = TOPO == ND_LINKS ? make_double2(r.M[i], r.M[n + i]) : M::map(z);
+        const double2 x = TOPO == ND_LINKS ? ((const double2*)r.M)[i] : M::map(z);
         double2 W;
         if constexpr (TOPO == ND_RING) {
             const int lo = i - P, hi = i + P;
@@ -457,12 +458,15 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
         } else {
             // row i = (V XOR D[C_i]) shifted by i: V's positions, then the entry's
             // signed positions, divided by the row's link count
+            const double2* __restrict__ mp = (const double2*)r.M;
             double w0 = 0.0, w1 = 0.0;
+#pragma unroll 8
             for (int q = 0; q < d.lnv; ++q) {
                 int j = i + d.lvpos[q];
                 j -= j >= n ? n : 0;
-                w0 += r.M[j];
-                w1 += r.M[n + j];
+                const double2 m = mp[j];
+                w0 += m.x;
+                w1 += m.y;
             }
             const int ke = d.lrow[i];
             for (int e2 = d.ldptr[ke]; e2 < d.ldptr[ke + 1]; ++e2) {
@@ -470,8 +474,9 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
                 int j = i + (v & ~kLinksRemove);
                 j -= j >= n ? n : 0;
                 const double sg = (v & kLinksRemove) ? -1.0 : 1.0;
-                w0 += sg * r.M[j];
-                w1 += sg * r.M[n + j];
+                const double2 m = mp[j];
+                w0 += sg * m.x;
+                w1 += sg * m.y;
             }
             const double inv = d.linv[ke];
             W = inv != 0.0 ? make_double2(w0 * inv, w1 * inv)
@@ -734,7 +739,8 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         hipLaunchKernelGGL(map, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work);
         if (topo == ND_RING) hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
         auto rhs = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_desc, d_work, s, rtol, atol);
+            hipLaunchKernelGGL(kern, dim3((tiles + 7) / 8 * 8), dim3(kDtBS), 0, st, d_r, d_desc, d_work, tiles, s, rtol,
+                               atol);
         };
         if (topo == ND_RING) {
             if (model == ND_KURAMOTO) rhs(k_dt_rhs<ND_KURAMOTO, ND_RING>);
