@@ -505,12 +505,18 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
     }
 }
 
-// The accept / reject decision of the attempt and the next step (one thread
-// per ring; the error partials are added in tile order).
-__global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol, int64_t max_steps, double t_out) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= count) return;
-    const DtNet& r = R[b];
+// The accept / reject decision of the attempt and the next step (one wave per
+// ring: lane l adds the error partials of tiles l, l + 64, ... in order, the
+// wave adds the lanes' sums in a fixed tree; lane 0 decides).
+__global__ __launch_bounds__(kWave) void k_dt_control(const DtNet* __restrict__ R, double rtol, int64_t max_steps,
+                                                       double t_out) {
+    const DtNet& r = R[blockIdx.x];
+    double sum = 0.0;
+    if (rtol > 0.0 && !r.ctl->done) {  // uniform over the wave
+        for (int q = threadIdx.x; q < r.G; q += kWave) sum += r.errp[q];
+        sum = wave_sum(sum);
+    }
+    if (threadIdx.x != 0) return;
     DtCtl c = *r.ctl;
     if (c.done) {
         if (c.out_hi != c.out_lo) {  // nothing more to emit
@@ -523,9 +529,6 @@ __global__ void k_dt_control(const DtNet* __restrict__ R, int count, double rtol
     bool accept = true;
     double f = 1.0;
     if (rtol > 0.0) {
-        double sum = 0.0;
-#pragma unroll 8
-        for (int q = 0; q < r.G; ++q) sum += r.errp[q];
         const double err = sqrt(sum / ((double)r.V * (double)r.n));
         f = 0.9 * pow(err, -0.2);
         accept = err <= 1.0;
@@ -617,17 +620,23 @@ __global__ __launch_bounds__(kDtBS) void k_dt_emit(const DtNet* __restrict__ R, 
     }
 }
 
-// R of every emitted output from the tiles' sums, added in tile order.
+// R of every emitted output from the tiles' sums: block (ring, y) takes outputs
+// y, y + kDtRBlocks, ...; thread l adds tiles l, l + kDtBS, ... in order and
+// the block adds the threads' sums in a fixed order.
+constexpr int kDtRBlocks = 64;
 __global__ __launch_bounds__(kDtBS) void k_dt_reduce_R(const DtNet* __restrict__ R) {
+    constexpr int NW = kDtBS / kWave;
+    __shared__ double lds[2 * NW];
     const DtNet& r = R[blockIdx.x];
     const int64_t emitted = min(r.ctl->next, r.K + 1);
-    for (int64_t ko = threadIdx.x; ko < emitted; ko += kDtBS) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int q = 0; q < r.G; ++q) {
-            s0 += r.Rpart[(ko * r.G + q) * 2];
-            s1 += r.Rpart[(ko * r.G + q) * 2 + 1];
+    for (int64_t ko = blockIdx.y; ko < emitted; ko += kDtRBlocks) {  // uniform over the block
+        double s2[2] = {0.0, 0.0};
+        for (int q = threadIdx.x; q < r.G; q += kDtBS) {
+            s2[0] += r.Rpart[(ko * r.G + q) * 2];
+            s2[1] += r.Rpart[(ko * r.G + q) * 2 + 1];
         }
-        r.R[ko] = sqrt(s0 * s0 + s1 * s1) / (double)r.n;
+        block_sum<kDtBS, 2>(s2, lds);
+        if (threadIdx.x == 0) r.R[ko] = sqrt(s2[0] * s2[0] + s2[1] * s2[1]) / (double)r.n;
     }
 }
 }  // namespace nd
@@ -774,7 +783,7 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         for (int a = 0; a < kAttempts && e == hipSuccess; ++a) {
             for (int s = 1; s <= 6 && e == hipSuccess; ++s) e = stage(s);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL(k_dt_control, dim3((count + 63) / 64), dim3(64), 0, st, d_r, count, rtol, max_steps,
+                hipLaunchKernelGGL(k_dt_control, dim3(count), dim3(kWave), 0, st, d_r, rtol, max_steps,
                                    t_out);
                 e = hipGetLastError();
                 if (e == hipSuccess && dense) e = emit();
@@ -789,7 +798,7 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         if (all) break;
     }
     if (e == hipSuccess && dense) {
-        hipLaunchKernelGGL(k_dt_reduce_R, dim3(count), dim3(kDtBS), 0, st, d_r);
+        hipLaunchKernelGGL(k_dt_reduce_R, dim3(count, kDtRBlocks), dim3(kDtBS), 0, st, d_r);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(Rh, d_R, br, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess && by) e = hipMemcpyAsync(Yh, d_Y, by, hipMemcpyDeviceToHost, st);
