@@ -278,6 +278,9 @@ __global__ __launch_bounds__(kDpBS) __attribute__((amdgpu_waves_per_eu(4))) void
 // is its tile's offset (fixed-order scan of the tile totals) plus its
 // in-tile inclusive prefix.
 constexpr int kDtBS = 256, kDtEPT = 2, kDtT = kDtBS * kDtEPT;
+// rings of at most this many tiles get their tile offsets in each RHS workgroup
+// (a scan of the tile totals into LDS); longer rings in a launch of their own
+constexpr int kDtScanMax = 2048;
 
 // Per-ring control block, advanced by the controller on the device.
 struct DtCtl {
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(kDtBS) void k_dt_map(const DtNet* __restrict__ R, c
 // Exclusive offsets of the tiles (one workgroup per ring, fixed order).
 __global__ __launch_bounds__(kDtBS) void k_dt_offsets(const DtNet* __restrict__ R) {
     const DtNet& r = R[blockIdx.x];
-    if (r.ctl->done) return;
+    if (r.ctl->done || r.G <= kDtScanMax) return;
     __shared__ double lds[4 * (kDtBS / kWave)];
     __shared__ double chunk[2];
     double carry0 = 0.0, carry1 = 0.0;
@@ -414,7 +417,8 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
                                                   double atol) {
     using M = RingModel<MODEL, double>;
     constexpr int V = M::V, NW = kDtBS / kWave;
-    __shared__ double lds[NW];
+    __shared__ double lds[3 * NW];
+    extern __shared__ double dt_off[];  // [2][G]: exclusive tile offsets (rings of <= kDtScanMax tiles)
     // row tiles that share gathers stay on one XCD (its own L2)
     const int w = xcd_work(blockIdx.x, nwork);
     if (w < 0) return;
@@ -424,8 +428,30 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
     const DtCtl c = *r.ctl;
     if (c.done) return;
     const int n = r.n, P = r.P, t0 = wk.y * kDtT, tid = threadIdx.x;
+    const int G = r.G;
+    const bool local = TOPO == ND_RING && G <= kDtScanMax;  // uniform over the block
+    if (local) {
+        // each thread adds a run of consecutive tile totals; the block scans the
+        // runs' sums; every workgroup of the ring computes the same offsets
+        const int per = (G + kDtBS - 1) / kDtBS, u0 = min(tid * per, G), u1 = min(u0 + per, G);
+        double v[2] = {0.0, 0.0}, none[1] = {0.0};
+        for (int u = u0; u < u1; ++u) {
+            v[0] += r.tot[u];
+            v[1] += r.tot[G + u];
+        }
+        block_sum_and_exscan<kDtBS, 1, 2>(none, v, lds);
+        for (int u = u0; u < u1; ++u) {
+            dt_off[u] = v[0];
+            dt_off[G + u] = v[1];
+            v[0] += r.tot[u];
+            v[1] += r.tot[G + u];
+        }
+        __syncthreads();
+    }
     auto S = [&](int k, int comp) {  // inclusive global prefix of element k (k = -1: 0)
-        return k < 0 ? 0.0 : r.tot[comp * r.G + k / kDtT] + r.pre[comp * n + k];
+        if (k < 0) return 0.0;
+        const double o = local ? dt_off[comp * G + k / kDtT] : r.tot[comp * G + k / kDtT];
+        return o + r.pre[comp * n + k];
     };
     double es[1] = {0.0};
 #pragma unroll
@@ -743,13 +769,21 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         if (d_Y) rs[b].Y = d_Y + (size_t)b * y_stride;
     }
     const int tiles = (int)work.size();
+    // tile offsets: in the RHS launch (LDS) for rings of up to kDtScanMax tiles
+    bool long_rings = false;
+    int local_g = 0;
+    for (const DtNet& r : rs) {
+        if (r.G > kDtScanMax) long_rings = true;
+        else local_g = std::max(local_g, (int)r.G);
+    }
+    const size_t off_bytes = topo == ND_RING ? (size_t)2 * local_g * 8 : 0;
     auto stage = [&](int s) {
         const DtMapFn map = dt_map_kernel(model, s);
         hipLaunchKernelGGL(map, dim3(tiles), dim3(kDtBS), 0, st, d_r, d_work);
-        if (topo == ND_RING) hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
+        if (topo == ND_RING && long_rings) hipLaunchKernelGGL(k_dt_offsets, dim3(count), dim3(kDtBS), 0, st, d_r);
         auto rhs = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((tiles + 7) / 8 * 8), dim3(kDtBS), 0, st, d_r, d_desc, d_work, tiles, s, rtol,
-                               atol);
+            hipLaunchKernelGGL(kern, dim3((tiles + 7) / 8 * 8), dim3(kDtBS), off_bytes, st, d_r, d_desc, d_work, tiles, s,
+                               rtol, atol);
         };
         if (topo == ND_RING) {
             if (model == ND_KURAMOTO) rhs(k_dt_rhs<ND_KURAMOTO, ND_RING>);

@@ -234,6 +234,26 @@ def test_tiled_adaptive_matches_oracle(nd, model, n, P, t_end, rtol):
     assert st.h_next == pytest.approx(hnext, rel=1e-4)
 
 
+def test_tiled_adaptive_long_ring_and_mixed_batch(nd):
+    """Rings of more than 2048 tiles of 512 take their tile offsets from a launch
+    of their own, shorter rings scan them inside the RHS launch: an FHN ring of
+    2048 * 512 + 1000 elements alone and in a batch with a ring of 3000, each
+    against the oracle's accepted and rejected steps and state."""
+    n, P = 2048 * 512 + 1000, 4
+    print(f"case tiled long ring n={n}", flush=True)
+    p, onet, y0, nv = net(nd, "fhn", n, P, 12)
+    ref, t, acc, rej, _ = O.run_dopri(onet, y0, 0.2, 1e-6, 1e-8, 1e-3)
+    (y,), (st,) = run_gpu(nd, [p], [y0], [0.2], [1e-3], 1e-6, 1e-8)
+    assert (st.accepted, st.rejected) == (acc, rej) and st.t == t
+    assert normwise(y, ref, nv) < 1e-10
+    p2, onet2, y02, _ = net(nd, "fhn", 3000, 900, 13)
+    ref2, t2, acc2, rej2, _ = O.run_dopri(onet2, y02, 0.3, 1e-6, 1e-8, 1e-3)
+    ys, sts = run_gpu(nd, [p, p2], [y0, y02], [0.2, 0.3], [1e-3, 1e-3], 1e-6, 1e-8)
+    assert (sts[0].accepted, sts[0].rejected) == (acc, rej)
+    assert (sts[1].accepted, sts[1].rejected) == (acc2, rej2) and sts[1].t == t2
+    assert normwise(ys[0], ref, nv) < 1e-10 and normwise(ys[1], ref2, nv) < 1e-10
+
+
 def test_tiled_adaptive_batch_fixed_steps_and_budget(nd):
     """A batch with a small and two large rings (all on the tiled path), one of
     them with t_end = 0; then fixed steps, and a step budget."""
