@@ -561,7 +561,8 @@ def main_adaptive(nd, torch, args, stream):
         achieved = acc * n * bpe / ev_total / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_dt_map + k_dt_offsets + k_dt_rhs + k_dt_control", "bytes_per_element_step": bpe}
+                "kernel": "k_dt_map + k_dt_rhs + k_dt_control" + (" + k_dt_emit" if args.workload == "adaptive3d" else ""),
+                "bytes_per_element_step": bpe}
         what = f"{args.batch} FitzHugh-Nagumo rings N={n} P={P} (0.35N), eps=0.05 a=0.5 sigma=0.1 phi=pi/2-0.1"
         if args.workload == "adaptive3d":
             what = (f"Kuramoto-Sakaguchi with inertia, 3D lattice {args.n}^3 periodic, ball of radius 2 (33 links) "
