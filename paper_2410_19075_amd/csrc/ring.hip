@@ -321,13 +321,16 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
 // registers for a whole chunk of steps.  Per stage the mapped values are
 // prefix-summed in LDS (double) and every window sum is a difference of two
 // prefix values (wrapping through the ring total); no global memory traffic
-// between stages.  Each thread owns EPT consecutive elements.
+// between stages.  Each thread owns EPT consecutive elements.  The prefix
+// array holds element k at k + k / EPT, so the lanes' stride-EPT accesses land
+// on distinct LDS banks (stride EPT + 1 doubles, at any offset).
 template <int MODEL, class KT, int BS, int EPT, bool MV>
 __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict__ D, const int2* __restrict__ work,
                                                       const int* __restrict__ nwork_p, int chunk) {
     using M = RingModel<MODEL, KT>;
-    constexpr int V = M::V, T = BS * EPT, NW = BS / kWave;
-    extern __shared__ double pf[];  // [2][T]: inclusive prefix sums of the two map components
+    constexpr int V = M::V, T = BS * EPT, NW = BS / kWave, TP = T + BS;
+    auto px = [](int k) { return k + k / EPT; };  // padded position of element k
+    extern __shared__ double pf[];  // [2][TP]: inclusive prefix sums of the two map components (padded)
     __shared__ double lds[8 * NW];
     const int nwork = *nwork_p;
     const int tid = threadIdx.x;
@@ -371,8 +374,8 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
                     tot[1] += x[e].y;
                     // thread-local inclusive prefix, completed below with the
                     // block-exclusive offset of this thread
-                    pf[tid * EPT + e] = tot[0];
-                    pf[T + tid * EPT + e] = tot[1];
+                    pf[px(tid * EPT + e)] = tot[0];
+                    pf[TP + px(tid * EPT + e)] = tot[1];
                     if constexpr (MODEL == ND_FHN) {
                         if (s == 1 && i < n) {
                             const double r = sqrt(z[e][0] * z[e][0] + z[e][1] * z[e][1]);
@@ -384,11 +387,11 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
                 block_sum_and_exscan<BS, 2, 2>(ru, tot, lds);
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
-                    pf[tid * EPT + e] = tot[0] + pf[tid * EPT + e];
-                    pf[T + tid * EPT + e] = tot[1] + pf[T + tid * EPT + e];
+                    pf[px(tid * EPT + e)] = tot[0] + pf[px(tid * EPT + e)];
+                    pf[TP + px(tid * EPT + e)] = tot[1] + pf[TP + px(tid * EPT + e)];
                 }
                 lds_barrier();
-                const double t0 = pf[n - 1], t1 = pf[T + n - 1];
+                const double t0 = pf[px(n - 1)], t1 = pf[TP + px(n - 1)];
                 if (s == 1 && tid == 0 && (d.obs & OBS_R) && (g % d.r_every) == 0) {
                     const double c = MODEL == ND_FHN ? ru[0] : t0, sn = MODEL == ND_FHN ? ru[1] : t1;
                     gp(d.R)[g / d.r_every] = sqrt(c * c + sn * sn) / (double)n;
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
                     if (i < n) {
                         // prefix(k) = sum_{j<k} x_j; window [i-P, i+P] through the ring total
                         const int lo = i - P, hi = i + P + 1;
-                        auto pre = [&](int k, int c) { return k == 0 ? 0.0 : pf[c * T + k - 1]; };
+                        auto pre = [&](int k, int c) { return k == 0 ? 0.0 : pf[c * TP + px(k - 1)]; };
                         double w0, w1;
                         if (lo < 0) {
                             w0 = pre(hi, 0) + (t0 - pre(lo + n, 0));
@@ -556,7 +559,7 @@ static RingLaunch resident_entry() {
     r.resident_mv = k_ring_resident<MODEL, KT, BS, EPT, true>;
     r.bs = BS;
     r.tile = -BS * EPT;
-    r.smem = 2 * BS * EPT * sizeof(double);
+    r.smem = 2 * (BS * EPT + BS) * sizeof(double);  // padded prefix arrays
     return r;
 }
 

@@ -78,6 +78,40 @@ def _dtype(name):
     return "f32" if re.search(r"<[^>]*\bfloat\b", name) else "f64"
 
 
+def _sq_section(a):
+    """Per-dispatch averages of every counter of the --sq pass for the filtered
+    kernels, and two figures derived from them: the VALU issue share (a wave64
+    VALU instruction occupies its SIMD for 4 cycles, transcendental ones longer,
+    so this is a lower bound on VALU-busy time) against the kernel's average
+    duration from --trace, and LDS bank-conflict cycles per LDS-active cycle."""
+    c = _counters(a.sq)
+    sel = {n: d for n, d in c.items() if any(f in n for f in a.filter.split("|"))}
+    names = sorted({cn for d in sel.values() for cn in d})
+    L = ["## SQ counters per dispatch (`--pmc " + " ".join(names) + "`)", "",
+         "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    avg = {}
+    for n, d in sorted(sel.items()):
+        avg[n] = {cn: sum(v) / len(v) for cn, v in d.items() if v}
+        L.append(f"| `{_short(n)}` | " + " | ".join(f"{avg[n][cn]:.4g}" if cn in avg[n] else "-" for cn in names) + " |")
+    L.append("")
+    dur = {}
+    if a.trace:
+        for n, v in _kernels(a.trace).items():
+            dur[n] = sum(v) / len(v) * 1e-9
+    rows = []
+    for n, m in sorted(avg.items()):
+        valu = m.get("SQ_INSTS_VALU")
+        share = (valu * 4 / (a.simds * a.clock_ghz * 1e9 * dur[n])) if valu and dur.get(n) else None
+        lds = m.get("SQ_ACTIVE_INST_LDS")
+        conf = (m["SQ_LDS_BANK_CONFLICT"] / lds) if lds and "SQ_LDS_BANK_CONFLICT" in m else None
+        rows.append(f"| `{_short(n)}` | {dur.get(n, 0) * 1e6:.2f} | "
+                    f"{'-' if share is None else f'{share:.2f}'} | {'-' if conf is None else f'{conf:.3f}'} |")
+    L += ["Derived: VALU issue share = SQ_INSTS_VALU x 4 cycles / (%d SIMDs x %.1f GHz x avg duration); "
+          "LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS." % (a.simds, a.clock_ghz), "",
+          "| kernel | avg us | VALU issue share | LDS conflict |", "|---|---|---|---|"] + rows + [""]
+    return L
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
@@ -92,6 +126,9 @@ def main():
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-bytes", type=float, default=0)
     ap.add_argument("--group", type=int, default=1, help="dispatches of the filtered kernels per launch unit")
+    ap.add_argument("--sq", help="counter database of an --pmc pass over SQ_* (and GRBM_*) counters")
+    ap.add_argument("--clock-ghz", type=float, default=2.4, help="shader clock for the issue-time estimate")
+    ap.add_argument("--simds", type=int, default=1024, help="SIMDs of the chip (256 CUs x 4)")
     ap.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args()
     L = [f"# {a.title or a.filter}", "", "Commands (run from the repository root):", "", "```"] + a.cmd + ["```", ""]
@@ -135,6 +172,8 @@ def main():
                 acc[0] += sum(v) * 1024.0 * scale.get(cname, 1.0)
                 acc[1] += len(v)
         L.append("")
+    if a.sq:
+        L += _sq_section(a)
     L += ["kernel-source-sha256: " + source_hash(a.sources.split(","))]
     for dt in ("f64", "f32"):
         f, w = per.get((dt, "FETCH_SIZE")), per.get((dt, "WRITE_SIZE"))
