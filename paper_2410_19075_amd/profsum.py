@@ -80,10 +80,13 @@ def _dtype(name):
 
 def _sq_section(a):
     """Per-dispatch averages of every counter of the --sq pass for the filtered
-    kernels, and two figures derived from them: the VALU issue share (a wave64
-    VALU instruction occupies its SIMD for 4 cycles, transcendental ones longer,
-    so this is a lower bound on VALU-busy time) against the kernel's average
-    duration from --trace, and LDS bank-conflict cycles per LDS-active cycle."""
+    kernels, and figures derived from them with the kernel's average duration
+    from --trace in place of the GPU-busy cycles of the profiler's own derived
+    metrics: VALU busy = SQ_ACTIVE_INST_VALU (quad-cycles) / (CUs x cycles);
+    VALU issue share = SQ_INSTS_VALU x 4 cycles / (SIMDs x cycles) (a wave64
+    VALU instruction holds its SIMD for 4 cycles, transcendental ones longer);
+    LDS conflict share = SQ_LDS_BANK_CONFLICT / (CUs x cycles); conflicts per
+    LDS access = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)."""
     c = _counters(a.sq)
     sel = {n: d for n, d in c.items() if any(f in n for f in a.filter.split("|"))}
     names = sorted({cn for d in sel.values() for cn in d})
@@ -98,17 +101,24 @@ def _sq_section(a):
     if a.trace:
         for n, v in _kernels(a.trace).items():
             dur[n] = sum(v) / len(v) * 1e-9
+    cus = a.simds // 4
+
+    def fmt(x, f="%.2f"):
+        return "-" if x is None else f % x
+
     rows = []
     for n, m in sorted(avg.items()):
-        valu = m.get("SQ_INSTS_VALU")
-        share = (valu * 4 / (a.simds * a.clock_ghz * 1e9 * dur[n])) if valu and dur.get(n) else None
-        lds = m.get("SQ_ACTIVE_INST_LDS")
-        conf = (m["SQ_LDS_BANK_CONFLICT"] / lds) if lds and "SQ_LDS_BANK_CONFLICT" in m else None
-        rows.append(f"| `{_short(n)}` | {dur.get(n, 0) * 1e6:.2f} | "
-                    f"{'-' if share is None else f'{share:.2f}'} | {'-' if conf is None else f'{conf:.3f}'} |")
-    L += ["Derived: VALU issue share = SQ_INSTS_VALU x 4 cycles / (%d SIMDs x %.1f GHz x avg duration); "
-          "LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS." % (a.simds, a.clock_ghz), "",
-          "| kernel | avg us | VALU issue share | LDS conflict |", "|---|---|---|---|"] + rows + [""]
+        cyc = dur.get(n, 0.0) * a.clock_ghz * 1e9
+        busy = m["SQ_ACTIVE_INST_VALU"] / (cus * cyc) if cyc and "SQ_ACTIVE_INST_VALU" in m else None
+        share = m["SQ_INSTS_VALU"] * 4 / (a.simds * cyc) if cyc and "SQ_INSTS_VALU" in m else None
+        conf = m["SQ_LDS_BANK_CONFLICT"] / (cus * cyc) if cyc and "SQ_LDS_BANK_CONFLICT" in m else None
+        idx = m.get("SQ_LDS_IDX_ACTIVE", 0.0) - m.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        per = m["SQ_LDS_BANK_CONFLICT"] / idx if idx > 0 and "SQ_LDS_BANK_CONFLICT" in m else None
+        rows.append(f"| `{_short(n)}` | {dur.get(n, 0) * 1e6:.2f} | {fmt(busy)} | {fmt(share)} | {fmt(conf)} | "
+                    f"{fmt(per, '%.3f')} |")
+    L += ["Derived (%d CUs, %d SIMDs, %.1f GHz; durations from the kernel trace):" % (cus, a.simds, a.clock_ghz), "",
+          "| kernel | avg us | VALU busy | VALU issue share | LDS conflict share | conflicts per LDS access |",
+          "|---|---|---|---|---|---|"] + rows + [""]
     return L
 
 
