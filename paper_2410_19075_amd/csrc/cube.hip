@@ -12,7 +12,9 @@
 //     (cos z, sin z) plane by plane and keeps the last 2H+1 of them in
 //     registers; the z-direction sum is a running sum (new plane in, oldest
 //     out) in double;
-//   * the z-sums go to LDS; an x-pass (sliding along runs of 4 outputs) and a
+//   * the z-sums go to LDS; an x-pass (H <= 2: one thread per output column
+//     and halo row, 2H+1 terms; longer windows: sliding along runs of 4
+//     outputs) and a
 //     y-pass (2H+1 terms) finish the cube sum for the cx x cy outputs;
 //   * the RHS and the RK bookkeeping follow the 13-access schedule of the ring
 //     kernels (y double-buffered, k in the bulk type).
@@ -115,12 +117,17 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         const bool outv = tid < cx * cy && (tid % cx) < ex && (tid / cx) < ey;
         const int ox = outv ? tid % cx : 0, oy = outv ? tid / cx : 0;
         const uint32_t obase = (uint32_t)(x0 + ox) + (uint32_t)n1 * (uint32_t)(y0 + oy);
-        // x-pass thread: a run of up to kRunX consecutive outputs of one row
+        // x-pass thread. Short windows (H <= 2): one output column of one halo
+        // row (HY * cx <= HX * HY threads), consecutive lanes on consecutive LDS
+        // entries. Longer windows: a run of up to kRunX consecutive outputs of
+        // one row, sliding the window along it (fewer LDS reads per output).
+        constexpr bool kDirectX = H <= 2;
         constexpr int kRunX = 4;
         const int nsx = (cx + kRunX - 1) / kRunX;
-        const bool xr = tid < HY * nsx;
-        const int xrow = xr ? tid / nsx : 0, xs0 = xr ? (tid - xrow * nsx) * kRunX : 0;
-        const int xcnt = xr ? min(kRunX, cx - xs0) : 0;
+        const bool xr = kDirectX ? tid < HY * cx : tid < HY * nsx;
+        const int xrow = xr ? (kDirectX ? tid / cx : tid / nsx) : 0;
+        const int xs0 = xr ? (kDirectX ? tid - xrow * cx : (tid - xrow * nsx) * kRunX) : 0;
+        const int xcnt = kDirectX ? 1 : (xr ? min(kRunX, cx - xs0) : 0);
 
         auto zval = [&](uint32_t i) {
             const double yy = ld32(y, i);
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
                             make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
                     lds_barrier();
-                    // x-pass over the HY rows: sliding window along each run
+                    // x-pass over the HY rows
                     if (xr) {
                         const double2* src = S1 + buf * HX * HY + xrow * HX + xs0;
                         double2* dst = S2 + buf * HY * cx + xrow * cx + xs0;
@@ -208,13 +215,15 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                             a.y += src[dx].y;
                         }
                         dst[0] = a;
+                        if constexpr (!kDirectX) {
 #pragma unroll
-                        for (int r = 1; r < kRunX; ++r) {
-                            if (r < xcnt) {
-                                const double2 in = src[r + 2 * H], out = src[r - 1];
-                                a.x = (a.x + in.x) - out.x;
-                                a.y = (a.y + in.y) - out.y;
-                                dst[r] = a;
+                            for (int r = 1; r < kRunX; ++r) {
+                                if (r < xcnt) {
+                                    const double2 in = src[r + 2 * H], out = src[r - 1];
+                                    a.x = (a.x + in.x) - out.x;
+                                    a.y = (a.y + in.y) - out.y;
+                                    dst[r] = a;
+                                }
                             }
                         }
                     }
