@@ -67,6 +67,7 @@
 #define ORC_OK 0
 #define ORC_EINVAL -1
 #define ORC_ENOMEM -2
+#define ORC_ENUMERIC -5 /* Dormand-Prince: non-finite error estimate or step below its floor */
 
 enum { ORC_KURAMOTO = 0, ORC_FHN = 1, ORC_HH = 2, ORC_INERTIA = 3 };
 enum { ORC_RING = 0, ORC_CUBE = 1, ORC_CSR = 2, ORC_BALL = 3, ORC_DISK = 4, ORC_LINKS = 5 };
@@ -530,6 +531,11 @@ double orc_order_parameter(int model, int64_t n, const double* y) { return order
  * The fifth-order solution propagates and the last stage is the first stage of
  * the next step (first same as last).  rtol <= 0 selects fixed steps of dt0
  * with no control (used by the order pin).
+ * Failure (controlled runs only): an attempt whose proposed step h lies below
+ * 10 units in the last place of t (the floor scipy's solvers use), or whose
+ * error estimate is not finite (a NaN or Inf in the state or the slopes), ends
+ * the run with ORC_ENUMERIC; y keeps the last accepted state and the failed
+ * attempt is not counted.
  * stats[4] = {t reached, accepted steps, rejected steps, last proposed h}. */
 static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
 static const double DP_A[7][6] = {
@@ -626,7 +632,12 @@ static int dopri_core(int model, int topo, int64_t n, int64_t radius, int64_t n1
         next = 1;
     }
     rhs(&m, y, k[0]);
+    int failed = 0;
     while (t < t_end && acc + rej < max_steps) {
+        if (rtol > 0.0 && h < 10.0 * (nextafter(t, INFINITY) - t)) {
+            failed = 1;
+            break;
+        }
         /* the step that reaches t_end (within a relative 1e-12 of h) ends on it */
         const int last = t_end - t <= h * (1.0 + 1e-12);
         const double hs = last ? t_end - t : h;
@@ -651,6 +662,10 @@ static int dopri_core(int model, int topo, int64_t n, int64_t radius, int64_t n1
                 sum += (e / sc) * (e / sc);
             }
             const double err = sqrt(sum / (double)len);
+            if (!isfinite(err)) {
+                failed = 1;
+                break;
+            }
             f = 0.9 * pow(err, -0.2);
             accept = err <= 1.0;
         }
@@ -699,5 +714,5 @@ static int dopri_core(int model, int topo, int64_t n, int64_t radius, int64_t n1
     free(z);
     free(yt);
     for (int s = 0; s < 7; ++s) free(k[s]);
-    return ORC_OK;
+    return failed ? ORC_ENUMERIC : ORC_OK;
 }

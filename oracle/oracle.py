@@ -139,9 +139,24 @@ def order_parameter(model, n, y):
     return lib().orc_order_parameter(int(model), int(n), _p(y))
 
 
+class DopriFailure(FloatingPointError):
+    """A controlled Dormand-Prince run stopped: its error estimate was not finite
+    or its proposed step fell below 10 units in the last place of t.  `result`
+    holds (y, t reached, accepted, rejected, last proposed step) at the stop."""
+
+    def __init__(self, result):
+        super().__init__(f"Dormand-Prince run failed at t={result[1]!r} after {result[2]} accepted steps")
+        self.result = result
+
+
+ORC_ENUMERIC = -5
+
+
 def run_dopri(net, y0, t_end, rtol, atol, dt0, max_steps=10 ** 7):
     """Dormand-Prince 5(4) with step-size control (rtol <= 0: fixed steps of dt0);
-    returns (y, t reached, accepted steps, rejected steps, last proposed step)."""
+    returns (y, t reached, accepted steps, rejected steps, last proposed step).
+    Raises DopriFailure when a controlled run fails (non-finite error estimate,
+    step below its floor)."""
     y = np.array(y0, dtype=np.float64, copy=True).ravel()
     assert y.size == net.nvars * net.n
     st = np.zeros(4)
@@ -149,6 +164,8 @@ def run_dopri(net, y0, t_end, rtol, atol, dt0, max_steps=10 ** 7):
     rc = lib().orc_run_dopri(net.model, net.topo, net.n, net.radius, n1, n2, n3, _p(net.row_ptr), _p(net.col),
                              _p(net.w), _p(net.params), _p(net.per_elem), _p(y), float(t_end), float(rtol),
                              float(atol), float(dt0), int(max_steps), _p(st))
+    if rc == ORC_ENUMERIC:
+        raise DopriFailure((y, st[0], int(st[1]), int(st[2]), st[3]))
     if rc != 0:
         raise ValueError(f"oracle dopri run failed ({rc})")
     return y, st[0], int(st[1]), int(st[2]), st[3]
@@ -168,6 +185,8 @@ def run_dopri_dense(net, y0, t_end, rtol, atol, dt0, t_out, states=False, max_st
                                    _p(net.col), _p(net.w), _p(net.params), _p(net.per_elem), _p(y), float(t_end),
                                    float(rtol), float(atol), float(dt0), int(max_steps), _p(st), float(t_out),
                                    _p(R), _p(Y))
+    if rc == ORC_ENUMERIC:
+        raise DopriFailure((y, st[0], int(st[1]), int(st[2]), st[3]))
     if rc != 0:
         raise ValueError(f"oracle dense dopri run failed ({rc})")
     return y, st[0], int(st[1]), int(st[2]), st[3], R, Y

@@ -834,6 +834,108 @@ def test_dopri_tolerance_proportionality_against_library(rtol):
     assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 100 * rtol
 
 
+def scipy_rk45_run(net, y0, t_end, rtol, atol, h0):
+    """Step scipy's RK45 (the same Dormand-Prince pair and textbook controller)
+    to t_end; returns (y, t, accepted, rejected, next proposed step). Every
+    attempt costs six right-hand-side calls after the first one at t = 0."""
+    from scipy.integrate import RK45
+    s = RK45(lambda _t, yy: O.rhs(net, yy), 0.0, np.array(y0, dtype=np.float64), t_end, rtol=rtol, atol=atol,
+             first_step=h0)
+    acc = 0
+    while s.status == "running":
+        s.step()
+        acc += 1
+    assert s.status == "finished"
+    attempts = (s.nfev - 1) // 6
+    assert s.nfev == 1 + 6 * attempts
+    return s.y, s.t, acc, attempts - acc, s.h_abs
+
+
+@pytest.mark.parametrize("case", ["fhn", "kuramoto", "inertia"])
+def test_dopri_controller_takes_the_library_steps(case):
+    """The step-size controller (error norm, accept test, growth and shrink
+    factors, facmax = 1 after a rejection, the last step cut to t_end) follows
+    the textbook Dormand-Prince controller that scipy's RK45 implements: the
+    same accepted and rejected step counts, the same next proposed step and the
+    same final state. A wrong exponent, safety factor or norm, or a missing
+    facmax = 1 after a rejection, changes the step sequence."""
+    if case == "fhn":
+        n, P, prm = 48, 9, np.array([0.05, 0.5, 0.1, math.pi / 2 - 0.1])
+        net, y0, t_end, rtol, atol, h0 = O.ring(O.FHN, n, P, prm), inputs.fhn_circle(41, n), 3.0, 1e-7, 1e-9, 0.05
+    elif case == "kuramoto":
+        n, P = 64, 16
+        net = O.ring(O.KURAMOTO, n, P, kur(0.0, 1.0, 1.46))
+        y0, t_end, rtol, atol, h0 = inputs.kuramoto_phases(42, n), 20.0, 1e-9, 1e-11, 0.5
+    else:
+        n, P = 40, 5
+        net = O.ring(O.INERTIA, n, P, inert(0.1, 1.0, 0.45, 1.0, 0.05))
+        y0 = np.concatenate([inputs.kuramoto_phases(43, n), np.zeros(n)])
+        t_end, rtol, atol, h0 = 10.0, 1e-6, 1e-8, 1.0
+    y, t, acc, rej, h = O.run_dopri(net, y0, t_end, rtol, atol, h0)
+    ys, ts, accs, rejs, hs = scipy_rk45_run(net, y0, t_end, rtol, atol, h0)
+    assert rej > 0, "the case must exercise rejections"
+    assert (acc, rej) == (accs, rejs)
+    assert t == ts == t_end
+    # err is a small difference of two solutions, so its rounding (summation order)
+    # moves the proposed steps at the 1e-8 level; a wrong exponent or factor moves them by O(1)
+    assert h == pytest.approx(hs, rel=1e-6)
+    assert np.max(np.abs(y - ys)) / np.max(np.abs(ys)) < 1e-12
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_dopri_non_finite_state_fails_at_once(bad):
+    """A non-finite state gives a non-finite error estimate; the controlled run
+    stops at the first attempt instead of rejecting until max_steps."""
+    n, P = 32, 4
+    y0 = inputs.kuramoto_phases(44, n)
+    y0[5] = bad
+    with pytest.raises(O.DopriFailure) as ei:
+        O.run_dopri(O.ring(O.KURAMOTO, n, P, kur(0.0, 1.0, 1.46)), y0, 1.0, 1e-8, 1e-10, 0.01, max_steps=10 ** 6)
+    _, t, acc, rej, _ = ei.value.result
+    assert (t, acc, rej) == (0.0, 0, 0)
+
+
+def test_dopri_step_floor():
+    """A proposed step below 10 units in the last place of t ends the run (the
+    floor of scipy's solvers); at t = 0 that floor is 10 times the smallest
+    subnormal, and a step just above it is taken."""
+    n, P = 32, 4
+    net = O.ring(O.KURAMOTO, n, P, kur(0.3, 0.0, 1.46))
+    y0 = inputs.kuramoto_phases(45, n)
+    tiny = 10 * np.nextafter(0.0, 1.0)
+    with pytest.raises(O.DopriFailure):
+        O.run_dopri(net, y0, 1.0, 1e-8, 1e-10, tiny / 2)
+    _, t, acc, _, _ = O.run_dopri(net, y0, 1.0, 1e-8, 1e-10, tiny * 2)
+    assert t == 1.0 and acc > 0
+
+
+def test_fhn_mean_phase_velocity_unwraps_the_geometric_phase():
+    """Uncoupled FHN oscillators (sigma = 0) on a limit cycle around the origin:
+    the oracle's mean phase velocity (atan2(v, u) unwrapped step by step) equals
+    the slope of np.unwrap(atan2(v, u)) sampled densely along an independent
+    DOP853 solution, over many cycles. Without the unwrap the value would be off
+    by 2 pi x cycles / time; a sign error flips it."""
+    n = 6
+    eps, a = 0.05, 0.5
+    prm = np.array([eps, a, 0.0, math.pi / 2 - 0.1])
+    net = O.ring(O.FHN, n, 1, prm)
+    y0 = inputs.fhn_circle(46, n)
+    dt, steps, mv0 = 0.01, 6000, 1500
+    _, _, mv = O.run(net, y0, dt, steps, mv_start=mv0)
+    t0, t1 = mv0 * dt, steps * dt
+    ts = np.linspace(0.0, t1, 600001)
+    ref = np.empty(n)
+    for j in range(n):
+        sol = solve_ivp(lambda _t, s: fhn_local(s[0], s[1], eps, a), (0.0, t1), [y0[j], y0[n + j]],
+                        method="DOP853", rtol=1e-12, atol=1e-12, t_eval=ts)
+        th = np.unwrap(np.arctan2(sol.y[1], sol.y[0]))
+        i0 = int(round(t0 / (t1 / 600000)))
+        ref[j] = (th[-1] - th[i0]) / (t1 - t0)
+    cycles = np.abs(ref) * (t1 - t0) / (2 * math.pi)
+    assert np.all(cycles > 5), "the horizon must cover several cycles"
+    assert np.max(np.abs(mv - ref)) < 1e-4 * np.max(np.abs(ref))
+
+
 # ------------------------------------------- compressed coupling matrix (Alg. 2)
 from oracle import compress as CM  # noqa: E402
 
