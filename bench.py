@@ -1,18 +1,21 @@
 """Throughput benchmark of the network-dynamics hot path on one MI355X.
 
-Default workload (--workload fhn): FitzHugh-Nagumo rings of N = 65536 elements,
-coupling radius P = floor(0.35 N) = 22937, eps = 0.05, a = 0.5, sigma = 0.1,
-phi = pi/2 - 0.1, initial (u, v) on the circle of radius 2 at seeded random
-angles, classical RK4 with dt = 0.01 over a horizon of 10^4 steps.  One
-benchmark step integrates a batch of B such rings (distinct seeds) over the
-full horizon with one batched launch sequence; `value` is the aggregate
-oscillator-steps per second in FP64, the FP32-bulk figure is reported beside it.
+Default workload (--workload cube): 3D Kuramoto-Sakaguchi on the periodic
+200^3 lattice (8e6 oscillators), cube neighbourhood of half-width 4 (728
+neighbours), alpha = 0.8, mu = 1, omega = 0, uniform phases plus a planted
+coherent ball, classical RK4 with dt = 0.05 over 2000 steps.  One benchmark
+step integrates the lattice over the full horizon; `value` is oscillator-steps
+per second in FP64, the FP32-bulk figure (FP32 maps and RHS, FP64 window sums
+and state) is reported beside it.  --n 400 runs the 400^3 lattice (6.4e7
+oscillators, beyond the 256 MB Infinity Cache).
 
 Other workloads (one JSON line each, same fields):
-  --workload cube      3D Kuramoto-Sakaguchi, 200^3 periodic lattice, cube
-                       half-width 4 (728 neighbours), alpha = 0.8, mu = 1,
-                       dt = 0.05, 2000 steps, uniform phases plus a planted
-                       coherent ball
+  --workload fhn       FitzHugh-Nagumo rings of N = 65536 elements, coupling
+                       radius P = floor(0.35 N) = 22937, eps = 0.05, a = 0.5,
+                       sigma = 0.1, phi = pi/2 - 0.1, (u, v) on the circle of
+                       radius 2 at seeded random angles, dt = 0.01, 10^4 steps;
+                       a batch of B rings (distinct seeds, --batch, default 64)
+                       per benchmark step in one batched launch sequence
   --workload hh        Hodgkin-Huxley, 10^6 neurons, random directed graph with
                        out-degree 100, weights U[0, 0.1], I_app U[8, 12],
                        dt = 0.01 ms, 5000 steps
@@ -97,7 +100,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3, help="timed benchmark steps")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="fhn")
+    ap.add_argument("--workload", choices=sorted(DEFAULTS), default="cube")
     ap.add_argument("--batch", type=int, default=0, help="networks per benchmark step (0 = workload default)")
     ap.add_argument("--n", type=int, default=0, help="elements (cube: edge) per network (0 = default)")
     ap.add_argument("--radius", type=int, default=2, help="ball: neighbourhood radius P")

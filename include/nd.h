@@ -74,7 +74,15 @@
  * device pointers that must stay valid until the work enqueued on the stream has completed.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued asynchronously
- * on it; only the getters with on_device = 0 synchronise it.
+ * on it: nd_run and nd_run_batch return without waiting for the device.  Only the getters with
+ * on_device = 0, nd_set_state with on_device = 0 (its host source is read before it returns) and
+ * nd_sync synchronise it.  nd_destroy and nd_set_config wait for the work enqueued for that
+ * network only (not for the whole device).
+ *
+ * Numerical failure: the stage kernels flag a network whose state turns non-finite (NaN or Inf)
+ * in a status word on the device.  The next synchronising call on that network (nd_get_state or
+ * nd_get_observables with on_device = 0, or nd_sync) returns ND_ERR_NUMERIC (the data are still
+ * copied); nd_set_state clears the flag.
  *
  * Errors: every call returns ND_OK (0) or a negative nd_status.  Argument errors are detected on
  * the host before any device work and return ND_ERR_INVALID_ARG; nd_last_error() then returns a
@@ -180,6 +188,10 @@ nd_status nd_get_state(nd_handle h, double* y, int64_t len, int32_t on_device, v
 nd_status nd_get_observables(nd_handle h, double* R, int64_t r_len, double* mean_vel, int64_t mv_len,
                              int32_t on_device, void* stream);
 
+/* Wait for the work enqueued on `stream` and report the network's numerical status: ND_OK, or
+ * ND_ERR_NUMERIC when a run since the last nd_set_state produced a non-finite state value. */
+nd_status nd_sync(nd_handle h, void* stream);
+
 nd_status nd_destroy(nd_handle h);
 
 /* Kernel configuration (chosen by the autotuner; callers normally leave it alone). */
@@ -213,12 +225,18 @@ typedef struct nd_kernel_config {
  * every few attempts.  At most max_steps step attempts per network.  The state
  * is advanced in place (read it with nd_get_state); no observables are recorded.  Blocks
  * until done; stats[i] receives the time reached, the accepted and rejected steps and the
- * step proposed next. */
+ * step proposed next.  A controlled network whose error estimate is not finite, or whose step
+ * falls below 10 units in the last place of t, stops there with stats[i].failed = 1; the call
+ * then returns ND_ERR_NUMERIC (after every network has finished or stopped). */
 typedef struct nd_adaptive_stats {
-    double t;          /* time reached (t_end unless max_steps ran out) */
+    double t;          /* time reached (t_end unless max_steps ran out or the run failed) */
     int64_t accepted;  /* accepted steps */
     int64_t rejected;  /* rejected step attempts */
     double h_next;     /* step size proposed for a continuation */
+    int32_t failed;    /* 1: the run stopped at t because its error estimate was not finite (a NaN
+                          or Inf in the state or the slopes) or its proposed step fell below 10 units
+                          in the last place of t; the state is the last accepted one */
+    int32_t reserved;
 } nd_adaptive_stats;
 
 nd_status nd_run_adaptive(const nd_handle* h, int32_t count, const double* t_end, const double* dt0, double rtol,

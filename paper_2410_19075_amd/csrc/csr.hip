@@ -190,6 +190,7 @@ __global__ __launch_bounds__(256) void k_csr_update(const NetDesc* __restrict__ 
             } else {
                 const double yo = fma(d.dt6, kk, fma(d.dt3, kv[v], gp(d.acc)[q]));
                 gp(d.y[par ^ 1])[q] = yo;
+                flag_nonfinite(d, yo);
                 zn[v] = yo;
             }
         }

@@ -257,7 +257,11 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                             const double kk1 = kq<KT>(k[1]);
                             if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + n, q, (KT)kk1);
                             if (stage == 2) st32(gp(d.acc) + n, q, fma(d.dt3, kk1, fma(d.dt6, kp1, y1)));
-                            if (stage == 4) st32(gp(d.y[par ^ 1]) + n, q, fma(d.dt6, kk1, fma(d.dt3, kp1, a1)));
+                            if (stage == 4) {
+                                const double yo1 = fma(d.dt6, kk1, fma(d.dt3, kp1, a1));
+                                st32(gp(d.y[par ^ 1]) + n, q, yo1);
+                                flag_nonfinite(d, yo1);
+                            }
                         }
                         if (stage == 1) {
                             st32(gp((KT*)d.k[0]), q, (KT)kk);
@@ -270,7 +274,9 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
                         } else if (stage == 3) {
                             st32(gp((KT*)d.k[2]), q, (KT)kk);
                         } else {
-                            st32(gp(d.y[par ^ 1]), q, fma(d.dt6, kk, fma(d.dt3, crk, cra)));
+                            const double yo = fma(d.dt6, kk, fma(d.dt3, crk, cra));
+                            st32(gp(d.y[par ^ 1]), q, yo);
+                            flag_nonfinite(d, yo);
                         }
                     }
                 }
@@ -488,8 +494,11 @@ __global__ __launch_bounds__(BS) void k_ball_stage(const NetDesc* __restrict__ D
                     const double kk = kq<KT>(k[v]);
                     if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + (int64_t)v * n, q, (KT)kk);
                     if (stage == 2) st32(gp(d.acc) + (int64_t)v * n, q, fma(d.dt3, kk, fma(d.dt6, kv[v], yv[v])));
-                    if (stage == 4)
-                        st32(gp(d.y[par ^ 1]) + (int64_t)v * n, q, fma(d.dt6, kk, fma(d.dt3, kv[v], av[v])));
+                    if (stage == 4) {
+                        const double yo = fma(d.dt6, kk, fma(d.dt3, kv[v], av[v]));
+                        st32(gp(d.y[par ^ 1]) + (int64_t)v * n, q, yo);
+                        flag_nonfinite(d, yo);
+                    }
                 }
                 if (stage == 1) {
                     part[0] += xo.x;

@@ -12,6 +12,9 @@
 //   accept when err <= 1, new h = h min(facmax, max(0.2, 0.9 err^(-1/5))),
 //   facmax = 10, or 1 right after a rejection; the step that reaches t_end
 //   (to within a relative 1e-12 of h) ends on it; rtol <= 0 means fixed steps.
+// A controlled run stops as failed when its error estimate is not finite (a
+// NaN or Inf in the state or the slopes) or its proposed step falls below 10
+// units in the last place of t; the state stays at the last accepted step.
 // The fifth-order solution propagates, and the last stage is the first stage
 // of the next step.  The error norm is one fixed-order block reduction, so the
 // accept/reject decisions are the same in every run.  Each ring decides for
@@ -26,6 +29,7 @@ namespace nd {
 
 namespace {
 constexpr int kDpBS = 512, kDpEPT = 2, kDpCap = kDpBS * kDpEPT;  // ring capacity 1024
+constexpr int kDpStats = 5;  // per ring: t, accepted, rejected, next h, failed
 
 __device__ __constant__ double kDpA[7][6] = {
     {0, 0, 0, 0, 0, 0},
@@ -166,8 +170,13 @@ __device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const 
         emit(0, 0.0, 0.0);
         next = 1;
     }
-    // every wave leaves the loop together: t, h and the counters are uniform
+    // every wave leaves the loop together: t, h, err and the counters are uniform
+    bool failed = false;
     while (t < tend && acc + rej < max_steps) {
+        if (rtol > 0.0 && h < 10.0 * (nextafter(t, INFINITY) - t)) {  // step below its floor
+            failed = true;
+            break;
+        }
         const bool last = tend - t <= h * (1.0 + 1e-12);
         const double hs = last ? tend - t : h;
         double z[EPT][V];
@@ -204,6 +213,10 @@ __device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const 
             }
             block_sum<kDpBS, 1>(sum, lds);
             const double err = sqrt(sum[0] / (double)(V * n));
+            if (!isfinite(err)) {  // a NaN or Inf in the state or the slopes
+                failed = true;
+                break;
+            }
             f = 0.9 * pow(err, -0.2);
             accept = err <= 1.0;
         }
@@ -243,11 +256,12 @@ __device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const 
         }
     }
     if (tid == 0) {
-        ND_GLOBAL double* st = gp(stats) + 4 * blockIdx.x;
+        ND_GLOBAL double* st = gp(stats) + kDpStats * blockIdx.x;
         st[0] = t;
         st[1] = (double)acc;
         st[2] = (double)rej;
         st[3] = h;
+        st[4] = failed ? 1.0 : 0.0;
     }
 }
 
@@ -292,6 +306,7 @@ struct DtCtl {
     int64_t next, out_lo, out_hi;
     double t_prev, hs_prev;
     int32_t f_prev, ypar_prev;
+    int32_t failed, pad_;  // failed: non-finite error estimate or step below its floor
 };
 
 // Per-ring buffers of one call.
@@ -556,6 +571,12 @@ __global__ __launch_bounds__(kWave) void k_dt_control(const DtNet* __restrict__ 
     double f = 1.0;
     if (rtol > 0.0) {
         const double err = sqrt(sum / ((double)r.V * (double)r.n));
+        if (!isfinite(err)) {  // a NaN or Inf in the state or the slopes: stop, state kept
+            c.failed = 1;
+            c.done = 1;
+            *r.ctl = c;
+            return;
+        }
         f = 0.9 * pow(err, -0.2);
         accept = err <= 1.0;
     }
@@ -582,6 +603,10 @@ __global__ __launch_bounds__(kWave) void k_dt_control(const DtNet* __restrict__ 
         c.facmax = 1.0;
     }
     c.done = !(c.t < r.tend && c.acc + c.rej < max_steps);
+    if (!c.done && rtol > 0.0 && c.h < 10.0 * (nextafter(c.t, INFINITY) - c.t)) {  // step below its floor
+        c.failed = 1;
+        c.done = 1;
+    }
     if (!c.done) {
         c.last = r.tend - c.t <= c.h * (1.0 + 1e-12);
         c.hs = c.last ? r.tend - c.t : c.h;
@@ -753,6 +778,10 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
         c.h = dt0[b];
         c.facmax = 10.0;
         c.done = !(0.0 < t_end[b] && max_steps > 0);
+        if (!c.done && rtol > 0.0 && c.h < 10.0 * std::nextafter(0.0, INFINITY)) {  // step below its floor
+            c.failed = 1;
+            c.done = 1;
+        }
         c.last = t_end[b] <= c.h * (1.0 + 1e-12);
         c.hs = c.last ? t_end[b] : c.h;
         if (r.K >= 0) {  // output 0 is the initial state (theta = 0)
@@ -846,12 +875,19 @@ static nd_status run_adaptive_tiled(const std::vector<Net*>& nets, int model, in
     if (e != hipSuccess) return hip_fail(e, "adaptive run (tiled)");
     if (ef != hipSuccess) return hip_fail(ef, "adaptive scratch free");
     if (es != hipSuccess) return hip_fail(es, "adaptive run (tiled)");
+    int bad = -1;
     for (int b = 0; b < count; ++b) {
         stats[b].t = cs[b].t;
         stats[b].accepted = cs[b].acc;
         stats[b].rejected = cs[b].rej;
         stats[b].h_next = cs[b].h;
+        stats[b].failed = cs[b].failed;
+        stats[b].reserved = 0;
+        if (cs[b].failed && bad < 0) bad = b;
     }
+    if (bad >= 0)
+        return fail(ND_ERR_NUMERIC, "adaptive run: network %d stopped at t = %.17g (non-finite error estimate or "
+                                    "step below its floor)", bad, cs[bad].t);
     return ND_OK;
 }
 
@@ -902,7 +938,7 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
     }
     hipStream_t st = (hipStream_t)stream;
     void* buf = nullptr;
-    const size_t bd = (size_t)count * sizeof(NetDesc), bt = (size_t)count * 8, bs = (size_t)count * 32;
+    const size_t bd = (size_t)count * sizeof(NetDesc), bt = (size_t)count * 8, bs = (size_t)count * kDpStats * 8;
     const size_t br = dense ? (size_t)count * r_stride * 8 : 0, by = dense && Y ? (size_t)count * y_stride * 8 : 0;
     hipError_t e = hipMallocAsync(&buf, bd + bt + bs + br + by, st);
     if (e != hipSuccess) return hip_fail(e, "adaptive scratch");
@@ -911,7 +947,7 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
     double* d_stats = (double*)((char*)buf + bd + bt);
     DenseOut o{dense ? t_out : 0.0, dense ? (double*)((char*)buf + bd + bt + bs) : nullptr, r_stride,
                by ? (double*)((char*)buf + bd + bt + bs + br) : nullptr, y_stride};
-    std::vector<double> h_stats((size_t)count * 4);
+    std::vector<double> h_stats((size_t)count * kDpStats);
     // outputs a run does not reach (max_steps) read as NaN (all bits set)
     if (dense) e = hipMemsetAsync(o.R, 0xff, br + by, st);
     if (e == hipSuccess && (e = hipMemcpyAsync(d_desc, descs.data(), bd, hipMemcpyHostToDevice, st)) == hipSuccess &&
@@ -935,12 +971,20 @@ static nd_status run_adaptive(const nd_handle* hs, int32_t count, const double* 
     if (e != hipSuccess) return hip_fail(e, "adaptive run");
     if (ef != hipSuccess) return hip_fail(ef, "adaptive scratch free");
     if (es != hipSuccess) return hip_fail(es, "adaptive run");
+    int bad = -1;
     for (int i = 0; i < count; ++i) {
-        stats[i].t = h_stats[4 * i];
-        stats[i].accepted = (int64_t)h_stats[4 * i + 1];
-        stats[i].rejected = (int64_t)h_stats[4 * i + 2];
-        stats[i].h_next = h_stats[4 * i + 3];
+        const double* q = h_stats.data() + kDpStats * i;
+        stats[i].t = q[0];
+        stats[i].accepted = (int64_t)q[1];
+        stats[i].rejected = (int64_t)q[2];
+        stats[i].h_next = q[3];
+        stats[i].failed = q[4] != 0.0;
+        stats[i].reserved = 0;
+        if (stats[i].failed && bad < 0) bad = i;
     }
+    if (bad >= 0)
+        return fail(ND_ERR_NUMERIC, "adaptive run: network %d stopped at t = %.17g (non-finite error estimate or "
+                                    "step below its floor)", bad, stats[bad].t);
     return ND_OK;
 }
 

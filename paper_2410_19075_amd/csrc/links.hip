@@ -346,6 +346,7 @@ __global__ __launch_bounds__(256) void k_links_stage(const NetDesc* __restrict__
                 } else {
                     const double yo = fma(d.dt6, kk, fma(d.dt3, kv[v], ld32(accp, ui)));
                     st32(gp(d.y[par ^ 1]) + (int64_t)v * n, ui, yo);
+                    flag_nonfinite(d, yo);
                     zn[v] = yo;
                 }
             }

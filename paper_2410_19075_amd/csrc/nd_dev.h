@@ -54,8 +54,10 @@ struct NetDesc {
     int64_t g0;         // run step index at the start of the current chunk
     int64_t nsteps;     // steps still to do at the start of the current chunk
     int32_t ypar;       // which y buffer holds the state at the start of the chunk
-    int32_t status;     // non-zero: a non-finite value was produced
+    int32_t* status;    // the network's status word: stage 4 stores 1 there when it produces a
+                        // non-finite state value (cleared when a new state is set)
 };
+
 
 enum : int32_t { OBS_R = 1, OBS_MV = 2 };
 
@@ -70,6 +72,12 @@ __device__ __forceinline__ ND_GLOBAL T* gp(T* p) {
 template <class T>
 __device__ __forceinline__ const ND_GLOBAL T* gp(const T* p) {
     return (const ND_GLOBAL T*)p;
+}
+
+// Flag a non-finite new state value in the network's status word (a plain
+// store of 1 from every lane that sees one; the host reads the word back).
+__device__ __forceinline__ void flag_nonfinite(const NetDesc& d, double v) {
+    if (!__builtin_isfinite(v)) *gp(d.status) = 1;
 }
 
 __device__ __forceinline__ int ring_wrap32(int i, int n) {

@@ -271,6 +271,7 @@ __global__ __launch_bounds__(BS) void k_ring_stage(const NetDesc* __restrict__ D
                     } else {
                         const double yo = fma(d.dt6, kk, fma(d.dt3, kv[e][v], av[e][v]));
                         st32(gp(d.y[par ^ 1]) + (int64_t)v * n, i, yo);
+                        flag_nonfinite(d, yo);
                         zn[v] = yo;
                     }
                 }
@@ -460,7 +461,10 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
             const int i = tid * EPT + e;
             if (i < n) {
 #pragma unroll
-                for (int v = 0; v < V; ++v) yout[(int64_t)v * n + i] = y[e][v];
+                for (int v = 0; v < V; ++v) {
+                    yout[(int64_t)v * n + i] = y[e][v];
+                    flag_nonfinite(d, y[e][v]);
+                }
                 const double2 xm = M::map(y[e]);
                 sums[0] += xm.x;
                 sums[1] += xm.y;

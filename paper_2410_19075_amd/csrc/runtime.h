@@ -19,6 +19,9 @@ nd_status validate_problem(const nd_problem* p);
 nd_kernel_config default_config(const nd_problem* p);
 int device_cu_count();
 bool tuned_config(const nd_problem* p, nd_kernel_config* out);
+// The configuration nd_create gives `p`: the autotuner's cached entry when there
+// is one, else the default.  Footprints and admission use the same resolution.
+nd_kernel_config config_for(const nd_problem* p);
 int ring_block(int tile);
 int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c);
 
@@ -37,9 +40,22 @@ struct Net {
     NetDesc* solo_desc = nullptr;  // launch arrays for running this network alone
     int2* solo_work = nullptr;
     int* solo_count = nullptr;
+    int32_t* status_dev = nullptr;   // status word the stage kernels flag (non-finite state)
+    int32_t* status_host = nullptr;  // pinned copy, read after a synchronising call
+    hipEvent_t last_ev = nullptr;    // recorded after the last work enqueued for this network
+    bool ev_recorded = false;
+    // chunk graph of this network alone, replayed by every nd_run with the same
+    // chunk length, grid and mean-velocity setting (rebuilt when the config changes)
+    hipGraphExec_t solo_graph[2] = {nullptr, nullptr};
+    int solo_graph_key[2][2] = {{0, 0}, {0, 0}};
     std::vector<void*> allocs;
 
     ~Net();
+    // wait until the device no longer uses this network's buffers
+    void quiesce();
+    // mark the network's buffers as used by the work enqueued on st so far
+    nd_status touch(hipStream_t st);
+    void drop_graphs();
     nd_status alloc(void** ptr, size_t bytes);
     nd_status create(const nd_problem* p);
     nd_status apply_config(const nd_kernel_config& c);
@@ -69,6 +85,11 @@ struct Group {
 };
 
 nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st);
+// Write one descriptor into device memory in stream order (the value travels as a
+// kernel argument, so no host buffer has to outlive the call).
+hipError_t put_desc(NetDesc* dst, const NetDesc& d, hipStream_t st);
+// Clear a network's status word in stream order.
+hipError_t clear_status(int32_t* status, hipStream_t st);
 nd_status capture_chunk(const Group& g, int K, hipGraphExec_t* out);
 bool graphs_enabled();
 nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t* steps, const nd_observe* obs,

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -291,6 +292,13 @@ nd_kernel_config default_config(const nd_problem* p) {
     return c;
 }
 
+nd_kernel_config config_for(const nd_problem* p) {
+    nd_kernel_config c = default_config(p);
+    nd_kernel_config tuned;
+    if (tuned_config(p, &tuned)) c = tuned;
+    return c;
+}
+
 int ring_block(int tile) {
     if (tile < 0) return tile == -4096 ? 512 : 256;
     return tile == 128 ? 64 : (tile == 256 ? 128 : 256);  // two elements per thread up to 512
@@ -330,8 +338,34 @@ nd_status Net::alloc(void** ptr, size_t bytes) {
     return ND_OK;
 }
 
+void Net::quiesce() {
+    if (ev_recorded) {
+        (void)hipEventSynchronize(last_ev);
+        ev_recorded = false;
+    }
+}
+
+nd_status Net::touch(hipStream_t st) {
+    hipError_t e = hipEventRecord(last_ev, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ev_recorded = true;
+    return ND_OK;
+}
+
+void Net::drop_graphs() {
+    for (auto& g : solo_graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
 Net::~Net() {
+    quiesce();
+    drop_graphs();
     for (void* q : allocs) (void)hipFree(q);
+    if (status_host) (void)hipHostFree(status_host);
+    if (last_ev) (void)hipEventDestroy(last_ev);
 }
 
 static void derive_params(const nd_problem* p, NetDesc& d) {
@@ -372,9 +406,7 @@ nd_status Net::create(const nd_problem* pr) {
     prob.col = nullptr;
     prob.weight = nullptr;
     prob.per_elem = nullptr;
-    cfg = default_config(pr);
-    nd_kernel_config tuned;
-    if (tuned_config(pr, &tuned)) cfg = tuned;
+    cfg = config_for(pr);
     const int64_t V = nvars_of(pr->model), n = pr->n, kb = bulk_bytes(pr->precision);
     std::memset(&tmpl, 0, sizeof tmpl);
     NetDesc& d = tmpl;
@@ -462,13 +494,20 @@ nd_status Net::create(const nd_problem* pr) {
     }
     if ((s = alloc((void**)&solo_desc, sizeof(NetDesc)))) return s;
     if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
+    if ((s = alloc((void**)&status_dev, sizeof(int32_t)))) return s;
+    HIPC(hipMemset(status_dev, 0, sizeof(int32_t)));
+    HIPC(hipHostMalloc((void**)&status_host, sizeof(int32_t)));
+    *status_host = 0;
+    HIPC(hipEventCreateWithFlags(&last_ev, hipEventDisableTiming));
+    d.status = status_dev;
     return apply_config(cfg);
 }
 
 // (Re)build everything that depends on the kernel configuration: the work
 // decomposition, the per-work-item sum buffers and the single-network work map.
 nd_status Net::apply_config(const nd_kernel_config& c) {
-    (void)hipDeviceSynchronize();
+    quiesce();  // the buffers below may be in use by enqueued work
+    drop_graphs();
     auto release = [&](void*& q) {
         if (!q) return;
         (void)hipFree(q);
@@ -575,7 +614,6 @@ NetDesc Net::run_desc(double dt, int64_t steps) const {
     d.g0 = 0;
     d.nsteps = steps;
     d.ypar = ypar;
-    d.status = 0;
     return d;
 }
 
@@ -710,7 +748,117 @@ nd_status capture_chunk(const Group& g, int K, hipGraphExec_t* out) {
 // State values per launch from which a group runs without graph capture.
 constexpr int64_t kEagerValues = int64_t(1) << 20;
 
-// Run a set of networks (possibly of different classes) for their own step counts.
+__global__ void k_put_desc(NetDesc* dst, NetDesc d) { *dst = d; }
+__global__ void k_clear_status(int32_t* status) { *status = 0; }
+
+hipError_t put_desc(NetDesc* dst, const NetDesc& d, hipStream_t st) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(1), 0, st, dst, d);
+    return hipGetLastError();
+}
+
+hipError_t clear_status(int32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, st, status);
+    return hipGetLastError();
+}
+
+// Pinned host staging for the descriptor tables and work maps of batched runs.
+// A block is handed out again only after the event recorded behind its upload
+// has completed, so a run returns without waiting for the device and the host
+// never rewrites a block a pending copy still reads.
+namespace {
+struct Staging {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool busy = false;      // handed out, upload not yet recorded
+    bool pending = false;   // an upload from it may still be in flight
+};
+std::mutex g_stage_mu;
+std::vector<std::unique_ptr<Staging>> g_stage;
+
+// Graph executables of batched runs, destroyed once their last replay is done.
+struct DeadGraph {
+    hipGraphExec_t exec;
+    hipEvent_t ev;
+};
+std::mutex g_dead_mu;
+std::vector<DeadGraph> g_dead;
+
+void reap_graphs() {
+    std::lock_guard<std::mutex> lk(g_dead_mu);
+    std::vector<DeadGraph> keep;
+    for (const DeadGraph& d : g_dead) {
+        if (hipEventQuery(d.ev) == hipSuccess) {
+            (void)hipGraphExecDestroy(d.exec);
+            (void)hipEventDestroy(d.ev);
+        } else {
+            keep.push_back(d);
+        }
+    }
+    g_dead.swap(keep);
+}
+
+nd_status retire_graph(hipGraphExec_t exec, hipStream_t st) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e != hipSuccess) {  // fall back to waiting here
+        (void)hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(exec);
+        return hip_fail(e, "graph retirement event");
+    }
+    std::lock_guard<std::mutex> lk(g_dead_mu);
+    g_dead.push_back({exec, ev});
+    return ND_OK;
+}
+
+nd_status staging_get(size_t bytes, Staging** out) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (auto& b : g_stage) {
+        if (b->busy || b->cap < bytes) continue;
+        if (b->pending) {
+            if (hipEventQuery(b->ev) != hipSuccess) continue;
+            b->pending = false;
+        }
+        b->busy = true;
+        *out = b.get();
+        return ND_OK;
+    }
+    auto b = std::make_unique<Staging>();
+    b->cap = std::max<size_t>(bytes, 64 * 1024);
+    hipError_t e = hipHostMalloc(&b->p, b->cap);
+    if (e != hipSuccess) return hip_fail(e, "hipHostMalloc (staging)");
+    e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipHostFree(b->p);
+        return hip_fail(e, "hipEventCreate (staging)");
+    }
+    b->busy = true;
+    *out = b.get();
+    g_stage.push_back(std::move(b));
+    return ND_OK;
+}
+
+// The uploads from `b` are enqueued on st: record that and release the block.
+nd_status staging_put(Staging* b, hipStream_t st) {
+    hipError_t e = hipEventRecord(b->ev, st);
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    b->busy = false;
+    b->pending = true;
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        b->pending = false;
+        return hip_fail(e, "hipEventRecord (staging)");
+    }
+    return ND_OK;
+}
+}  // namespace
+
+// Run a set of networks (possibly of different classes) for their own step
+// counts.  Everything is enqueued on st and the call returns without waiting
+// for the device: descriptors of a single network travel as a kernel argument,
+// those of batches through pinned staging blocks; each network records an event
+// behind its work so that reconfiguring or destroying it waits for exactly that.
 nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t* steps, const nd_observe* obs,
                    hipStream_t st) {
     // validate and prepare observables
@@ -721,6 +869,7 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         for (int k = 0; k < i; ++k)
             if (nets[k] == nets[i]) return fail(ND_ERR_INVALID_ARG, "a handle appears twice in one batch");
     }
+    reap_graphs();
     nd_status s;
     for (int i = 0; i < count; ++i)
         if ((s = nets[i]->prepare_observe(steps[i], obs ? &obs[i] : nullptr))) return s;
@@ -746,38 +895,49 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         g.h = std::get<5>(kv.first);
         g.block = std::get<6>(kv.first);
         g.ndesc = (int)idx.size();
-        int64_t maxsteps = 0;
-        std::vector<NetDesc> descs;
-        std::vector<int2> work;
+        int64_t maxsteps = 0, nwork = 0;
         g.mv = false;
-        for (int q = 0; q < (int)idx.size(); ++q) {
-            Net* n = nets[idx[q]];
-            descs.push_back(n->run_desc(dt[idx[q]], steps[idx[q]]));
-            g.mv = g.mv || n->mv_start >= 0;
-            n->append_work(q, work);
-            maxsteps = std::max(maxsteps, steps[idx[q]]);
+        for (int q : idx) {
+            g.mv = g.mv || nets[q]->mv_start >= 0;
+            nwork += nets[q]->work_items();
+            maxsteps = std::max(maxsteps, steps[q]);
         }
         const bool solo = idx.size() == 1;
         void* scratch = nullptr;
+        hipError_t e;
         if (solo) {
             Net* n = nets[idx[0]];
             g.desc = n->solo_desc;
             g.work = n->solo_work;
             g.nwork = n->solo_count;
+            if ((e = put_desc(g.desc, n->run_desc(dt[idx[0]], steps[idx[0]]), st)) != hipSuccess)
+                return hip_fail(e, "descriptor upload");
         } else {
-            const size_t bd = descs.size() * sizeof(NetDesc), bw = work.size() * sizeof(int2);
-            HIPC(hipMallocAsync(&scratch, bd + bw + 16, st));
+            const size_t bd = idx.size() * sizeof(NetDesc), bw = (size_t)nwork * sizeof(int2);
+            Staging* sb = nullptr;
+            if ((s = staging_get(bd + bw + 16, &sb))) return s;
+            NetDesc* hd = (NetDesc*)sb->p;
+            int2* hw = (int2*)((char*)sb->p + bd);
+            int w = 0;
+            for (int q = 0; q < (int)idx.size(); ++q) {
+                Net* n = nets[idx[q]];
+                hd[q] = n->run_desc(dt[idx[q]], steps[idx[q]]);
+                const int64_t m = n->work_items();
+                for (int64_t t = 0; t < m; ++t) hw[w++] = make_int2(q, (int)t);
+            }
+            *(int*)((char*)sb->p + bd + bw) = w;
+            e = hipMallocAsync(&scratch, bd + bw + 16, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(scratch, sb->p, bd + bw + 16, hipMemcpyHostToDevice, st);
+            const nd_status sp = staging_put(sb, st);
+            if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+            if (sp) return sp;
             g.desc = (NetDesc*)scratch;
             g.work = (int2*)((char*)scratch + bd);
             g.nwork = (int*)((char*)scratch + bd + bw);
-            HIPC(hipMemcpyAsync(g.work, work.data(), bw, hipMemcpyHostToDevice, st));
-            int nw = (int)work.size();
-            HIPC(hipMemcpyAsync(g.nwork, &nw, sizeof nw, hipMemcpyHostToDevice, st));
         }
-        HIPC(hipMemcpyAsync(g.desc, descs.data(), descs.size() * sizeof(NetDesc), hipMemcpyHostToDevice, st));
         const Net* n0 = nets[idx[0]];
         const int cfg_grid = n0->cfg.grid;
-        g.grid = cfg_grid > 0 ? std::min<int>(cfg_grid, (int)work.size()) : (int)work.size();
+        g.grid = cfg_grid > 0 ? (int)std::min<int64_t>(cfg_grid, nwork) : (int)nwork;
         const int K = std::max(1, n0->cfg.chunk);
         // Replaying a captured chunk saves the host's per-launch cost, which matters
         // for short kernels; groups whose stage kernels are long (many state values
@@ -790,23 +950,38 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
             // one eager chunk covering every network's steps
             if ((s = enqueue_chunk(g, (int)std::min<int64_t>(maxsteps, 1 << 30), st))) return s;
         } else {
-            // capture one K-step chunk and replay it; the descriptors advance on
-            // the device, so every replay continues where the last one stopped
-            hipGraphExec_t exec = nullptr;
-            if ((s = capture_chunk(g, K, &exec))) return s;
+            // replay a captured K-step chunk; the descriptors advance on the
+            // device, so every replay continues where the last one stopped
             const int64_t reps = (maxsteps + K - 1) / K;
-            hipError_t e = hipSuccess;
+            hipGraphExec_t exec = nullptr;
+            Net* so = solo ? nets[idx[0]] : nullptr;
+            const int slot = g.mv ? 1 : 0;
+            if (so && so->solo_graph[slot] && so->solo_graph_key[slot][0] == K &&
+                so->solo_graph_key[slot][1] == g.grid) {
+                exec = so->solo_graph[slot];
+            } else {
+                if ((s = capture_chunk(g, K, &exec))) return s;
+                if (so) {
+                    if (so->solo_graph[slot]) (void)retire_graph(so->solo_graph[slot], st);
+                    so->solo_graph[slot] = exec;
+                    so->solo_graph_key[slot][0] = K;
+                    so->solo_graph_key[slot][1] = g.grid;
+                }
+            }
+            e = hipSuccess;
             for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(exec, st);
-            hipError_t e2 = hipStreamSynchronize(st);
-            (void)hipGraphExecDestroy(exec);
+            if (!so) {
+                const nd_status rs = retire_graph(exec, st);
+                if (e == hipSuccess && rs) return rs;
+            }
             if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
         }
         if (scratch) HIPC(hipFreeAsync(scratch, st));
-        // pageable sources of the async copies above must stay alive until consumed
-        HIPC(hipStreamSynchronize(st));
     }
-    for (int i = 0; i < count; ++i) nets[i]->ypar ^= (int)(steps[i] & 1);
+    for (int i = 0; i < count; ++i) {
+        nets[i]->ypar ^= (int)(steps[i] & 1);
+        if ((s = nets[i]->touch(st))) return s;
+    }
     return ND_OK;
 }
 
@@ -840,7 +1015,7 @@ nd_status nd_footprint(const nd_problem* p, int64_t* bytes) {
         LinksCompressed lc;
         if ((s = compress_links(p->n, p->row_ptr, p->col, &lc))) return s;
     }
-    *bytes = footprint_bytes(p, default_config(p));
+    *bytes = footprint_bytes(p, config_for(p));
     return ND_OK;
 }
 
@@ -853,7 +1028,18 @@ nd_status nd_set_state(nd_handle h, const double* y, int64_t len, int32_t on_dev
     if (len != want) return fail(ND_ERR_INVALID_ARG, "state length %lld, expected %lld", (long long)len, (long long)want);
     hipStream_t st = (hipStream_t)stream;
     HIPC(hipMemcpyAsync(n->tmpl.y[n->ypar], y, len * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    HIPC(clear_status(n->status_dev, st));  // a new state starts with a clean status word
     if (!on_device) HIPC(hipStreamSynchronize(st));
+    return n->touch(st);
+}
+
+// After the work enqueued on st so far: ND_ERR_NUMERIC when a stage kernel
+// flagged a non-finite state value in this network (synchronises st).
+static nd_status sync_status(Net* n, hipStream_t st, const char* what) {
+    HIPC(hipMemcpyAsync(n->status_host, n->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (*n->status_host)
+        return fail(ND_ERR_NUMERIC, "%s: the state holds a non-finite value (a run produced NaN or Inf)", what);
     return ND_OK;
 }
 
@@ -864,8 +1050,8 @@ nd_status nd_get_state(nd_handle h, double* y, int64_t len, int32_t on_device, v
     if (len != want) return fail(ND_ERR_INVALID_ARG, "state length %lld, expected %lld", (long long)len, (long long)want);
     hipStream_t st = (hipStream_t)stream;
     HIPC(hipMemcpyAsync(y, n->tmpl.y[n->ypar], len * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    if (!on_device) HIPC(hipStreamSynchronize(st));
-    return ND_OK;
+    if (!on_device) return sync_status(n, st, "nd_get_state");
+    return n->touch(st);
 }
 
 nd_status nd_run(nd_handle h, double dt, int64_t steps, const nd_observe* obs, void* stream) {
@@ -899,15 +1085,20 @@ nd_status nd_get_observables(nd_handle h, double* R, int64_t r_len, double* mean
         if (mv_len != n->prob.n) return fail(ND_ERR_INVALID_ARG, "mv_len must equal n");
         HIPC(hipMemcpyAsync(mean_vel, n->mv_dev, mv_len * 8, kind, st));
     }
-    if (!on_device) HIPC(hipStreamSynchronize(st));
-    return ND_OK;
+    if (!on_device) return sync_status(n, st, "nd_get_observables");
+    return n->touch(st);
+}
+
+nd_status nd_sync(nd_handle h, void* stream) {
+    Net* n = as_net(h);
+    if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle");
+    return sync_status(n, (hipStream_t)stream, "nd_sync");
 }
 
 nd_status nd_destroy(nd_handle h) {
     Net* n = as_net(h);
     if (!n) return fail(ND_ERR_INVALID_ARG, "NULL handle");
-    (void)hipDeviceSynchronize();
-    delete n;
+    delete n;  // waits for the work enqueued for this network only
     return ND_OK;
 }
 

@@ -275,6 +275,12 @@ nd_status Server::pump(hipStream_t strm, int64_t* pending) {
         launched = true;
     }
     if (launched) {
+        // the status words of the running requests (a non-finite state fails the
+        // request at this chunk boundary instead of at the end of its horizon)
+        for (Request* r : running)
+            if (!r->cancel)
+                HIPC(hipMemcpyAsync(r->net->status_host, r->net->status_dev, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    strm));
         const double a = now();
         HIPC(hipStreamSynchronize(strm));
         st.gpu_seconds += now() - a;
@@ -292,6 +298,9 @@ nd_status Server::pump(hipStream_t strm, int64_t* pending) {
         }
         if (r->cancel) {
             release(r, ND_REQ_CANCELLED, ND_OK);
+        } else if (launched && *n->status_host) {
+            release(r, ND_REQ_FAILED, fail(ND_ERR_NUMERIC, "request %lld: the state turned non-finite",
+                                           (long long)r->id));
         } else if (n->run_done >= n->run_total) {
             r->y.resize((size_t)nvars_of(r->prob.model) * r->prob.n);
             hipError_t e = hipMemcpy(r->y.data(), n->tmpl.y[n->ypar], r->y.size() * 8, hipMemcpyDeviceToHost);
@@ -387,7 +396,7 @@ nd_status nd_server_submit(nd_server_h h, const nd_problem* p, const double* y0,
     r->dt = dt;
     r->steps = steps;
     if (obs) r->obs = *obs;
-    r->footprint = footprint_bytes(p, default_config(p));
+    r->footprint = footprint_bytes(p, config_for(p));
     if (r->obs.record_every > 0) r->footprint += (steps / r->obs.record_every + 1) * 8;
     if (r->obs.mv_start_step >= 0) r->footprint += p->n * 8;
     std::lock_guard<std::mutex> lk(s->mu);

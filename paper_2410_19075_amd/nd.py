@@ -43,7 +43,8 @@ class nd_kernel_config(ctypes.Structure):
 
 
 class nd_adaptive_stats(ctypes.Structure):
-    _fields_ = [("t", _c_dbl), ("accepted", _c_i64), ("rejected", _c_i64), ("h_next", _c_dbl)]
+    _fields_ = [("t", _c_dbl), ("accepted", _c_i64), ("rejected", _c_i64), ("h_next", _c_dbl),
+                ("failed", _c_i32), ("reserved", _c_i32)]
 
 
 class nd_links_info(ctypes.Structure):
@@ -97,6 +98,7 @@ _sig = {
                           _P(nd_links_info)],
     "nd_get_observables": [_c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_destroy": [_c_vp],
+    "nd_sync": [_c_vp, _c_vp],
     "nd_get_config": [_c_vp, _P(nd_kernel_config)],
     "nd_set_config": [_c_vp, _P(nd_kernel_config)],
     "nd_server_create": [_P(nd_server_config), _P(_c_vp)],
@@ -131,19 +133,50 @@ class NDError(RuntimeError):
         super().__init__(f"{where}: {_lib.nd_status_str(status).decode()} ({status}): {msg}")
 
 
-def _check(status, where):
+def _check(status, where, **extra):
     if status != ND_OK:
-        raise NDError(status, where)
+        err = NDError(status, where)
+        for k, v in extra.items():
+            setattr(err, k, v)
+        raise err
     return status
 
 
-def _ptr(a):
-    """Device or host pointer of a torch tensor / numpy array (None -> NULL)."""
+def _buf(a, what, dtype="float64"):
+    """(pointer, element count, on_device) of a contiguous torch tensor or numpy
+    array of the dtype the C side reads (None -> (None, 0, None)).  The library
+    copies count * sizeof(dtype) bytes, so anything else is refused here."""
     if a is None:
-        return None
+        return None, 0, None
     if hasattr(a, "data_ptr"):
-        return a.data_ptr()
-    return a.ctypes.data
+        import torch
+        if a.dtype != getattr(torch, dtype):
+            raise TypeError(f"{what}: expected a torch.{dtype} tensor, got {a.dtype}")
+        if not a.is_contiguous():
+            raise ValueError(f"{what}: the tensor must be contiguous")
+        return a.data_ptr(), a.numel(), bool(a.is_cuda)
+    if not isinstance(a, np.ndarray):
+        raise TypeError(f"{what}: expected a numpy array or a torch tensor, got {type(a).__name__}")
+    if a.dtype != np.dtype(dtype):
+        raise TypeError(f"{what}: expected a numpy {dtype} array, got {a.dtype}")
+    if not a.flags.c_contiguous:
+        raise ValueError(f"{what}: the array must be C-contiguous")
+    if not a.flags.writeable and what.startswith("out"):
+        raise ValueError(f"{what}: the array must be writeable")
+    return a.ctypes.data, a.size, False
+
+
+def _on_device(what, on_device, *places):
+    """The copy direction of one call: every buffer on the same side, and an
+    explicit on_device that matches where they are."""
+    seen = {p for p in places if p is not None}
+    if len(seen) > 1:
+        raise ValueError(f"{what}: buffers on the host and on the device in one call")
+    where = seen.pop() if seen else False
+    if on_device is not None and bool(on_device) != where:
+        raise ValueError(f"{what}: on_device={int(bool(on_device))} but the buffer is "
+                         f"{'on the device' if where else 'in host memory'}")
+    return int(where)
 
 
 def _stream(stream):
@@ -193,15 +226,15 @@ def nd_footprint(p):
 
 
 def nd_set_state(h, y, on_device=None, stream=None):
-    on = int(hasattr(y, "is_cuda") and y.is_cuda) if on_device is None else int(on_device)
-    n = y.numel() if hasattr(y, "numel") else y.size
-    _check(_lib.nd_set_state(h, _ptr(y), n, on, _stream(stream)), "nd_set_state")
+    ptr, n, dev = _buf(y, "nd_set_state y")
+    on = _on_device("nd_set_state", on_device, dev)
+    _check(_lib.nd_set_state(h, ptr, n, on, _stream(stream)), "nd_set_state")
 
 
 def nd_get_state(h, y, on_device=None, stream=None):
-    on = int(hasattr(y, "is_cuda") and y.is_cuda) if on_device is None else int(on_device)
-    n = y.numel() if hasattr(y, "numel") else y.size
-    _check(_lib.nd_get_state(h, _ptr(y), n, on, _stream(stream)), "nd_get_state")
+    ptr, n, dev = _buf(y, "out: nd_get_state y")
+    on = _on_device("nd_get_state", on_device, dev)
+    _check(_lib.nd_get_state(h, ptr, n, on, _stream(stream)), "nd_get_state")
 
 
 def observe(record_every=0, mv_start_step=-1):
@@ -231,7 +264,7 @@ def nd_run_adaptive(handles, t_end, dt0, rtol, atol, max_steps=10 ** 7, stream=N
     d0 = (_c_dbl * k)(*[float(x) for x in dt0])
     st = (nd_adaptive_stats * k)()
     _check(_lib.nd_run_adaptive(hs, k, te, d0, float(rtol), float(atol), int(max_steps), st, _stream(stream)),
-           "nd_run_adaptive")
+           "nd_run_adaptive", stats=list(st))
     return list(st)
 
 
@@ -270,19 +303,19 @@ def nd_run_adaptive_dense(handles, t_end, dt0, rtol, atol, t_out, state_len=0, m
     Y = np.empty((k, ys)) if state_len else None
     _check(_lib.nd_run_adaptive_dense(hs, k, te, d0, float(rtol), float(atol), int(max_steps), float(t_out),
                                       R.ctypes.data, outs, Y.ctypes.data if Y is not None else None, ys, st,
-                                      _stream(stream)), "nd_run_adaptive_dense")
+                                      _stream(stream)), "nd_run_adaptive_dense", stats=list(st))
     return list(st), R, Y
 
 
 def nd_get_observables(h, R=None, mean_vel=None, on_device=None, stream=None):
-    ref = R if R is not None else mean_vel
-    on = int(hasattr(ref, "is_cuda") and ref.is_cuda) if on_device is None else int(on_device)
+    pr, nr, dr = _buf(R, "out: nd_get_observables R")
+    pm, nm, dm = _buf(mean_vel, "out: nd_get_observables mean_vel")
+    on = _on_device("nd_get_observables", on_device, dr, dm)
+    _check(_lib.nd_get_observables(h, pr, nr, pm, nm, on, _stream(stream)), "nd_get_observables")
 
-    def size(a):
-        return 0 if a is None else (a.numel() if hasattr(a, "numel") else a.size)
 
-    _check(_lib.nd_get_observables(h, _ptr(R), size(R), _ptr(mean_vel), size(mean_vel), on, _stream(stream)),
-           "nd_get_observables")
+def nd_sync(h, stream=None):
+    _check(_lib.nd_sync(h, _stream(stream)), "nd_sync")
 
 
 def nd_destroy(h):
@@ -334,8 +367,11 @@ def nd_server_info(s, rid):
 
 
 def nd_server_result(s, rid, y, R=None):
-    _check(_lib.nd_server_result(s, int(rid), _ptr(y), y.size, _ptr(R), 0 if R is None else R.size),
-           "nd_server_result")
+    py, ny, dy = _buf(y, "out: nd_server_result y")
+    pr, nr, dr = _buf(R, "out: nd_server_result R")
+    if dy or dr:
+        raise ValueError("nd_server_result copies into host memory (numpy arrays)")
+    _check(_lib.nd_server_result(s, int(rid), py, ny, pr, nr), "nd_server_result")
 
 
 def nd_server_cancel(s, rid):

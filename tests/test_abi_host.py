@@ -287,3 +287,31 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     assert out[0].split() == ["0", "6", "1", "0"]
     assert out[1].startswith("-1 invalid argument")
+
+
+@pytest.mark.parametrize("bad", ["float32", "strided", "int64", "list"])
+def test_binding_refuses_buffers_the_library_would_overrun(bad):
+    """The C side copies len * 8 bytes of FP64, so the binding refuses anything
+    that is not a contiguous float64 buffer before the call (no handle needed)."""
+    from paper_2410_19075_amd import nd
+    a = {"float32": np.zeros(8, dtype=np.float32), "strided": np.zeros(16)[::2],
+         "int64": np.zeros(8, dtype=np.int64), "list": [0.0] * 8}[bad]
+    for call in (lambda: nd.nd_get_state(None, a), lambda: nd.nd_set_state(None, a),
+                 lambda: nd.nd_get_observables(None, R=a), lambda: nd.nd_server_result(None, 1, a)):
+        with pytest.raises((TypeError, ValueError)):
+            call()
+
+
+def test_binding_refuses_mixed_or_mislabelled_locations():
+    import torch
+    from paper_2410_19075_amd import nd
+    host = np.zeros(8)
+    with pytest.raises(ValueError):
+        nd.nd_get_state(None, host, on_device=1)
+    with pytest.raises(TypeError):
+        nd.nd_set_state(None, torch.zeros(8, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        nd.nd_set_state(None, torch.zeros(8, 2, dtype=torch.float64).t())
+    assert nd._on_device("x", None, False, None) == 0
+    with pytest.raises(ValueError):
+        nd._on_device("x", None, False, True)

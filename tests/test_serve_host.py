@@ -76,3 +76,23 @@ def test_tune_cache_roundtrip(tmp_path):
     with pytest.raises(nd.NDError):
         nd.nd_tune_load(str(bad))
     nd.nd_tune_clear()
+
+
+def test_footprint_follows_the_tuned_configuration(tmp_path):
+    """nd_footprint (and the server's admission) sizes a problem with the
+    configuration nd_create will use: a cached autotuner entry changes the tile
+    count of a ring, and with it the per-tile sum buffers."""
+    n, P = 1 << 16, 1 << 13
+    p = nd.problem(nd.ND_FHN, nd.ND_RING, n, [0.05, 0.5, 0.1, 1.47], radius=P)
+    nd.nd_tune_clear()
+    base = nd.nd_footprint(p)
+    f = tmp_path / "tune.txt"
+    # width bucket floor(8 P / n) = 1, log2 n = 16; the same entry for a host without a device
+    f.write_text("".join(f"{arch} 1 0 0 16 1 0 128 64 0 64 0 0\n" for arch in ("unknown", "gfx950")))
+    nd.nd_tune_load(str(f))
+    try:
+        tuned = nd.nd_footprint(p)
+    finally:
+        nd.nd_tune_clear()
+    # tiles of 128 instead of 512: three more per-tile pairs of doubles per 128 elements x 3 buffers
+    assert tuned - base == 3 * 2 * 8 * (n // 128 - n // 512)
