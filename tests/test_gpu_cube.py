@@ -153,15 +153,69 @@ def test_cube_batch_equals_solo(nd):
             nd.nd_destroy(hh)
 
 
-def test_cube_full_200_random_state_one_step(nd):
-    """The benchmark's workload at full size and in its launch configuration:
-    200^3, h = 4, uniform phases with a planted coherent ball, one step, every
-    element against the oracle (about half a minute of oracle time)."""
-    print("case full 200^3 cube, one step", flush=True)
+@pytest.fixture(scope="module")
+def cube200_one_step():
+    """The benchmark's 200^3 state (h = 4, uniform phases with a planted coherent
+    ball) and the oracle's result after one step (about half a minute of oracle
+    time), shared by the FP64 and FP32-bulk full-size tests."""
     n1 = 200
     y0 = inputs.cube_phases_with_patch(1000, n1)
     prm = [0.0, 1.0, 0.8]
-    y, R, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm), y0, 0.05, 1, record_every=1)
     ref, Rref, _ = O.run(O.cube(n1, 4, prm), y0, 0.05, 1, record_every=1)
+    return n1, prm, y0, ref, Rref
+
+
+def test_cube_full_200_random_state_one_step(nd, cube200_one_step):
+    """The benchmark's workload at full size and in its launch configuration:
+    200^3, h = 4, one step, every element against the oracle."""
+    print("case full 200^3 cube, one step", flush=True)
+    n1, prm, y0, ref, Rref = cube200_one_step
+    y, R, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm), y0, 0.05, 1, record_every=1)
     assert rel(y, ref) < 1e-12
     assert np.max(np.abs(R - Rref)) < 1e-12
+
+
+def test_cube_full_200_fp32_bulk_one_step(nd, cube200_one_step):
+    """FP32-bulk at full size in the benchmark's launch configuration (the
+    default tiling with its two-plane prefetch), one step, every element against
+    the oracle."""
+    print("case full 200^3 cube fp32-bulk, one step", flush=True)
+    n1, prm, y0, ref, Rref = cube200_one_step
+    y, R, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm, prec=1), y0, 0.05, 1, record_every=1)
+    e = rel(y, ref)
+    print(f"cube 200^3 fp32-bulk one-step error {e:.3e}")
+    assert e < 1e-4
+    assert np.max(np.abs(R - Rref)) < 1e-4
+
+
+def test_cube_fp32_bulk_benchmark_tiling_200_steps(nd):
+    """FP32-bulk over the 200-step horizon against the oracle, with the tile
+    extents the 200^3 lattice runs with (25 x 20 columns per work item) on a
+    30^3 lattice, so the same kernel shape meets ragged tiles in x and y and
+    ragged z runs (tile_z = 13)."""
+    print("case cube 30^3 fp32-bulk with the 200^3 tiling, 200 steps", flush=True)
+    n1, h, prm = 30, 4, [0.0, 1.0, 0.8]
+    y0 = inputs.cube_phases_with_patch(77, n1)
+    cfg = dict(tile=25, tile_y=20, tile_z=13)
+    y, R, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, h, prm, prec=1), y0, 0.05, 200, cfg=cfg, record_every=1)
+    ref, Rref, _ = O.run(O.cube(n1, h, prm), y0, 0.05, 200, record_every=1)
+    e = rel(y, ref)
+    print(f"cube 30^3 fp32-bulk 200-step error {e:.3e}")
+    assert e < 1e-4
+    assert np.max(np.abs(R - Rref)) < 1e-4
+
+
+def test_cube_full_200_fp32_bulk_200_steps_against_fp64(nd):
+    """FP32-bulk at full size over the 200-step horizon against the FP64 path
+    (itself held to the oracle at this size by the one-step test and by the
+    plane-wave closed forms): the oracle's O(N L) sums cannot follow 200 steps
+    of 8e6 elements."""
+    print("case full 200^3 cube fp32-bulk vs fp64, 200 steps", flush=True)
+    n1, prm = 200, [0.0, 1.0, 0.8]
+    y0 = inputs.cube_phases_with_patch(1001, n1)
+    y64, R64, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm), y0, 0.05, 200, record_every=1)
+    y32, R32, _ = run_cfg(nd, cube_problem(nd, (n1,) * 3, 4, prm, prec=1), y0, 0.05, 200, record_every=1)
+    e = rel(y32, y64)
+    print(f"cube 200^3 fp32-bulk vs fp64 after 200 steps {e:.3e}")
+    assert e < 1e-4
+    assert np.max(np.abs(R32 - R64)) < 1e-4

@@ -133,9 +133,57 @@ def test_hh_fp32_bulk(nd):
     assert e < 1e-4
 
 
-def test_hh_full_size_two_steps(nd):
+def test_hh_fp32_bulk_1e5_deg100_200_steps(nd):
+    """FP32-bulk over the 200-step horizon at the benchmark's out-degree (10^5
+    neurons, 10^7 synapses; the launch configuration of the 10^6 network:
+    source blocks per XCD, 256 rows per work item, 8 edges per thread)
+    against the oracle."""
+    print("case hh 1e5 x 100 fp32-bulk, 200 steps", flush=True)
+    y, ref = hh_case(nd, 100000, 100, 9, 200, prec=1)
+    e = normwise(y, ref)
+    print(f"hh 1e5 fp32-bulk 200-step error {e:.3e}")
+    assert e < 1e-4
+
+
+@pytest.fixture(scope="module")
+def hh_full():
+    """The benchmark's network (10^6 neurons, out-degree 100) and the oracle's
+    state after two steps, shared by the FP64 and FP32-bulk full-size tests."""
+    n, deg, seed = 1000000, 100, 1
+    rp, col, w = inputs.random_out_graph(seed, n, deg)
+    iapp = inputs.hh_iapp(seed, n)
+    y0 = inputs.hh_state(seed, n)
+    ref, _, _ = O.run(O.csr(n, rp, col, w, HH_PRM, iapp), y0, 0.01, 2)
+    return n, rp, col, w, iapp, y0, ref
+
+
+def hh_run(nd, net, prec, steps):
+    n, rp, col, w, iapp, y0, _ = net
+    p = nd.problem(nd.ND_HH, nd.ND_CSR, n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=w, per_elem=iapp)
+    y, _, _ = nd.simulate(p, y0, 0.01, steps)
+    return y
+
+
+def test_hh_full_size_two_steps(nd, hh_full):
     """The benchmark's workload at full size and in its launch configuration:
     10^6 neurons, out-degree 100 (10^8 synapses), two steps against the oracle."""
     print("case full HH 1e6 x 100, two steps", flush=True)
-    y, ref = hh_case(nd, 1000000, 100, 1, 2)
-    assert normwise(y, ref) < 1e-12
+    assert normwise(hh_run(nd, hh_full, 0, 2), hh_full[-1]) < 1e-12
+
+
+def test_hh_full_size_fp32_bulk_two_steps(nd, hh_full):
+    """FP32-bulk at full size (FP32 weights and activations, FP64 synaptic sums
+    and state), two steps against the oracle."""
+    print("case full HH 1e6 x 100 fp32-bulk, two steps", flush=True)
+    e = normwise(hh_run(nd, hh_full, 1, 2), hh_full[-1])
+    print(f"hh 1e6 fp32-bulk two-step error {e:.3e}")
+    assert e < 1e-4
+
+
+def test_hh_full_size_fp32_bulk_200_steps_against_fp64(nd, hh_full):
+    """FP32-bulk at full size over the 200-step horizon against the FP64 path,
+    which the two-step oracle test holds at this size."""
+    print("case full HH 1e6 x 100 fp32-bulk vs fp64, 200 steps", flush=True)
+    e = normwise(hh_run(nd, hh_full, 1, 200), hh_run(nd, hh_full, 0, 200))
+    print(f"hh 1e6 fp32-bulk vs fp64 after 200 steps {e:.3e}")
+    assert e < 1e-4

@@ -133,3 +133,89 @@ def test_fp32_bulk_long_horizon_links_small_world(nd):
     assert np.all(np.isfinite(a32[0])) and np.all(np.isfinite(a32[1]))
     assert err[0] <= max(1e-3, 2 * floor[0])
     assert err[1] <= max(1e-3, 2 * floor[1])
+
+
+def test_fp32_bulk_long_horizon_cube_200(nd):
+    """The 3D lattice benchmark (200^3, h = 4, alpha = 0.8, uniform phases with a
+    planted coherent ball, dt = 0.05) over its full 2000-step horizon: FP32-bulk
+    against FP64 on the second-half mean of R(t), the mean-phase-velocity
+    profile and max |dR|, with the FP64 floor from another tiling (another
+    summation order)."""
+    from paper_2410_19075_amd import inputs
+    print("case cube 200^3 long horizon, 2000 steps", flush=True)
+    n1, steps = 200, 2000
+    n = n1 ** 3
+    y0 = inputs.cube_phases_with_patch(1002, n1)
+    mk = lambda prec: nd.problem(nd.ND_KURAMOTO, nd.ND_CUBE3D, n, [0.0, 1.0, 0.8], precision=prec, radius=4,
+                                 dims=(n1,) * 3)
+    half = steps // 2
+    a64 = run_cfg(nd, mk(0), y0, steps, 0.05, half)
+    b64 = run_cfg(nd, mk(0), y0, steps, 0.05, half, dict(tile=20, tile_y=20, tile_z=50))
+    a32 = run_cfg(nd, mk(1), y0, steps, 0.05, half)
+    floor, err = stats_gap(a64, b64, half), stats_gap(a64, a32, half)
+    print(f"cube 200^3: fp64 floor <R> {floor[0]:.2e} mv-rms {floor[1]:.2e} max|dR| {floor[2]:.2e}; "
+          f"fp32-bulk <R> {err[0]:.2e} mv-rms {err[1]:.2e} max|dR| {err[2]:.2e}")
+    assert np.all(np.isfinite(a32[0])) and np.all(np.isfinite(a32[1]))
+    assert err[0] <= max(1e-3, 2 * floor[0])
+    assert err[1] <= max(1e-3, 2 * floor[1])
+    assert err[2] <= max(1e-3, 2 * floor[2])
+
+
+def hh_segments(nd, p, y0, steps, segs):
+    """Run in segments; at every checkpoint the population mean of V and the
+    fraction of neurons above -20 mV (in a spike)."""
+    h = nd.nd_create(p)
+    try:
+        nd.nd_set_state(h, y0, on_device=0)
+        y = np.empty_like(y0)
+        n = p.n
+        mv, frac = [], []
+        for _ in range(segs):
+            nd.nd_run(h, 0.01, steps // segs)
+            nd.nd_get_state(h, y, on_device=0)
+            mv.append(float(np.mean(y[:n])))
+            frac.append(float(np.mean(y[:n] > -20.0)))
+        return y, np.array(mv), np.array(frac)
+    finally:
+        nd.nd_destroy(h)
+
+
+def test_fp32_bulk_long_horizon_hh_1e6(nd):
+    """The Hodgkin-Huxley benchmark (10^6 neurons, out-degree 100) over its full
+    5000-step horizon: FP32-bulk against FP64 on population statistics (the
+    second-half means of <V> relative to its scale and of the fraction of
+    neurons in a spike, sampled every 250 steps) and on the final state
+    normwise, each within max(1e-3, 2 x the FP64 floor), the floor being FP64
+    against FP64 with one element moved by one ulp. The order parameter and
+    phase velocities are not defined for this model."""
+    from paper_2410_19075_amd import inputs
+    print("case hh 1e6 long horizon, 5000 steps", flush=True)
+    HH_PRM = [1.0, 120.0, 36.0, 0.3, 50.0, -77.0, -54.387, 0.0, 0.0, 2.0]
+    n, deg, seed, steps, segs = 1000000, 100, 3, 5000, 20
+    rp, col, w = inputs.random_out_graph(seed, n, deg)
+    iapp = inputs.hh_iapp(seed, n)
+    y0 = inputs.hh_state(seed, n)
+    y1 = y0.copy()
+    y1[123] = np.nextafter(y1[123], np.inf)
+    mk = lambda prec: nd.problem(nd.ND_HH, nd.ND_CSR, n, HH_PRM, precision=prec, row_ptr=rp, col=col, weight=w,
+                                 per_elem=iapp)
+    a64 = hh_segments(nd, mk(0), y0, steps, segs)
+    b64 = hh_segments(nd, mk(0), y1, steps, segs)
+    a32 = hh_segments(nd, mk(1), y0, steps, segs)
+
+    def gap(a, b):
+        ya, mva, fa = a
+        yb, mvb, fb = b
+        s = segs // 2
+        dmv = abs(mva[s:].mean() - mvb[s:].mean()) / abs(mva[s:].mean())
+        dfr = abs(fa[s:].mean() - fb[s:].mean())
+        dy = max(np.max(np.abs(ya[v * n:(v + 1) * n] - yb[v * n:(v + 1) * n])) /
+                 np.max(np.abs(ya[v * n:(v + 1) * n])) for v in range(4))
+        return dmv, dfr, dy
+
+    floor, err = gap(a64, b64), gap(a64, a32)
+    print(f"hh 1e6: fp64 floor <V> {floor[0]:.2e} spiking {floor[1]:.2e} state {floor[2]:.2e}; "
+          f"fp32-bulk <V> {err[0]:.2e} spiking {err[1]:.2e} state {err[2]:.2e}")
+    assert np.all(np.isfinite(a32[0]))
+    for e, f in zip(err, floor):
+        assert e <= max(1e-3, 2 * f)

@@ -107,17 +107,95 @@ def test_twisted_state_rotates_rigidly_on_gpu(nd, q):
     assert np.max(np.abs(R - (1.0 if q == 0 else 0.0))) < 1e-12
 
 
-def test_fhn_ring_fp64_parity_65536(nd):
-    """FitzHugh-Nagumo ring at the full width N=65536, P=floor(0.35N): a few
-    steps against the oracle (the oracle's cost is O(N P) per stage)."""
+@pytest.fixture(scope="module")
+def fhn65536_three_steps():
+    """FitzHugh-Nagumo ring at the benchmark's width N = 65536, P = floor(0.35 N),
+    and the oracle's result after three steps (its cost is O(N P) per stage),
+    shared by the FP64 and FP32-bulk full-width tests."""
     n = 65536
     P = int(0.35 * n)
     y0 = inputs.fhn_circle(1, n)
+    ref, Rref, _ = O.run(O.ring(O.FHN, n, P, FHN_PRM), y0, 0.01, 3, record_every=1)
+    return n, P, y0, ref, Rref
+
+
+def test_fhn_ring_fp64_parity_65536(nd, fhn65536_three_steps):
+    """FitzHugh-Nagumo ring at the full width: three steps against the oracle."""
+    n, P, y0, ref, Rref = fhn65536_three_steps
     print("case fhn c2-shape", flush=True)
     y, R, _ = ring_case(nd, nd.ND_FHN, n, P, FHN_PRM, nd.ND_FP64, y0, 0.01, 3, record_every=1)
-    ref, Rref, _ = O.run(O.ring(O.FHN, n, P, FHN_PRM), y0, 0.01, 3, record_every=1)
     assert normwise(y, ref, 2) < 1e-12
     assert np.max(np.abs(R - Rref)) < 1e-12
+
+
+def test_fhn_ring_fp32_bulk_65536(nd, fhn65536_three_steps):
+    """FP32-bulk at the full width in the benchmark's launch configuration
+    (tiles of 512): three steps against the oracle."""
+    n, P, y0, ref, Rref = fhn65536_three_steps
+    print("case fhn c2-shape fp32-bulk", flush=True)
+    y, R, _ = ring_case(nd, nd.ND_FHN, n, P, FHN_PRM, nd.ND_FP32_BULK, y0, 0.01, 3, record_every=1)
+    e = normwise(y, ref, 2)
+    print(f"fhn 65536 fp32-bulk 3-step error {e:.3e}")
+    assert e < 1e-4
+    assert np.max(np.abs(R - Rref)) < 1e-4
+
+
+def batch_run(nd, probs, states, dt, steps, record_every=1):
+    hs = []
+    try:
+        for p, y0 in zip(probs, states):
+            hs.append(nd.nd_create(p))
+            nd.nd_set_state(hs[-1], y0, on_device=0)
+        nd.nd_run_batch(hs, [dt] * len(hs), [steps] * len(hs), [nd.observe(record_every, -1)] * len(hs))
+        out = []
+        for h, y0 in zip(hs, states):
+            y = np.empty_like(y0)
+            nd.nd_get_state(h, y, on_device=0)
+            R = np.empty(steps // record_every + 1)
+            nd.nd_get_observables(h, R=R, on_device=0)
+            out.append((y, R))
+        return out
+    finally:
+        for h in hs:
+            nd.nd_destroy(h)
+
+
+def test_fhn_fp32_bulk_tiled_batch_200_steps(nd):
+    """FP32-bulk over the 200-step horizon on the tiled ring path the benchmark
+    uses (rings above 4096 elements, tiles of 512, several rings in one batched
+    launch): two FitzHugh-Nagumo rings of 8192 and 8000 elements (a ragged last
+    tile), P = floor(0.35 N), each against the oracle."""
+    print("case fhn fp32-bulk tiled batch, 200 steps", flush=True)
+    ns = [8192, 8000]
+    probs = [nd.problem(nd.ND_FHN, nd.ND_RING, n, FHN_PRM, precision=nd.ND_FP32_BULK, radius=int(0.35 * n))
+             for n in ns]
+    states = [inputs.fhn_circle(40 + i, n) for i, n in enumerate(ns)]
+    got = batch_run(nd, probs, states, 0.01, 200)
+    for n, y0, (y, R) in zip(ns, states, got):
+        ref, Rref, _ = O.run(O.ring(O.FHN, n, int(0.35 * n), FHN_PRM), y0, 0.01, 200, record_every=1)
+        e = normwise(y, ref, 2)
+        print(f"fhn {n} fp32-bulk 200-step error {e:.3e}")
+        assert e < 1e-4
+        assert np.max(np.abs(R - Rref)) < 1e-4
+
+
+def test_fhn_65536_fp32_bulk_200_steps_against_fp64(nd):
+    """FP32-bulk at the benchmark's width and launch configuration (a batch of
+    rings of 65536, tiles of 512) over the 200-step horizon, against the FP64
+    path, which the three-step oracle test holds at this width (the oracle's
+    O(N P) sums cannot follow 200 steps here)."""
+    print("case fhn 65536 fp32-bulk vs fp64 batch, 200 steps", flush=True)
+    n = 65536
+    P = int(0.35 * n)
+    states = [inputs.fhn_circle(50 + i, n) for i in range(2)]
+    mk = lambda prec: nd.problem(nd.ND_FHN, nd.ND_RING, n, FHN_PRM, precision=prec, radius=P)
+    r64 = batch_run(nd, [mk(nd.ND_FP64)] * 2, states, 0.01, 200)
+    r32 = batch_run(nd, [mk(nd.ND_FP32_BULK)] * 2, states, 0.01, 200)
+    for (y64, R64), (y32, R32) in zip(r64, r32):
+        e = normwise(y32, y64, 2)
+        print(f"fhn 65536 fp32-bulk vs fp64 after 200 steps {e:.3e}")
+        assert e < 1e-4
+        assert np.max(np.abs(R32 - R64)) < 1e-4
 
 
 @pytest.mark.parametrize("model", ["kur", "fhn"])
