@@ -180,6 +180,26 @@ nd_status nd_run(nd_handle h, double dt, int64_t steps, const nd_observe* obs, v
 nd_status nd_run_batch(const nd_handle* hs, int32_t count, const double* dt, const int64_t* steps,
                        const nd_observe* obs, void* stream);
 
+/* Integrate several networks exactly as nd_run_batch does (same kernels, same results, bitwise),
+ * without allocating anything: for callers that cannot allocate device or host memory, such as
+ * code under HIP graph capture, tight serving loops and harnesses that forbid hipMalloc.  The
+ * descriptor tables and work maps that nd_run_batch places in memory taken per call live here in
+ * one fixed device array of ND_NOALLOC_SCRATCH_BYTES that the library reserves on every GPU it
+ * runs on (held until the process ends): at most ND_NOALLOC_MAX_NETS networks and
+ * ND_NOALLOC_MAX_WORK work items (nd_get_config: ring tiles, lattice tiles, CSR row blocks x 8,
+ * compressed-matrix row blocks) per call; larger calls return ND_ERR_INVALID_ARG and enqueue
+ * nothing.  Every call on one GPU uses that GPU's array and leaves its contents behind, so calls
+ * whose device work overlaps on one GPU (unordered streams, concurrent threads) race: order them
+ * on one stream.  Observables are recorded only into buffers that an earlier nd_run or
+ * nd_run_batch of the same network sized (R of at least steps/record_every + 1 values, the mean
+ * phase velocity); otherwise ND_ERR_INVALID_ARG.  Chunks are launched directly on `stream` (no
+ * graph is captured or replayed).  Asynchronous like nd_run_batch. */
+#define ND_NOALLOC_MAX_NETS 256
+#define ND_NOALLOC_MAX_WORK 262144
+#define ND_NOALLOC_SCRATCH_BYTES 2359296
+nd_status nd_run_batch_noalloc(const nd_handle* hs, int32_t count, const double* dt, const int64_t* steps,
+                               const nd_observe* obs, void* stream);
+
 /* Copy the current state out (nvars*n doubles). */
 nd_status nd_get_state(nd_handle h, double* y, int64_t len, int32_t on_device, void* stream);
 

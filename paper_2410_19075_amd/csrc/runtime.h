@@ -61,7 +61,7 @@ struct Net {
     nd_status apply_config(const nd_kernel_config& c);
     int64_t work_items() const;
     void append_work(int desc_index, std::vector<int2>& wk) const;
-    nd_status prepare_observe(int64_t steps, const nd_observe* obs);
+    nd_status prepare_observe(int64_t steps, const nd_observe* obs, bool may_alloc = true);
     NetDesc run_desc(double dt, int64_t steps) const;
     // chunked runs (serving): the run's step counter lives on the host and each
     // chunk's descriptor starts where the previous chunk stopped

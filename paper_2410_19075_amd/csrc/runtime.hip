@@ -568,7 +568,7 @@ void Net::append_work(int desc_index, std::vector<int2>& wk) const {
     for (int64_t t = 0; t < m; ++t) wk.push_back(make_int2(desc_index, (int)t));
 }
 
-nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs) {
+nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs, bool may_alloc) {
     last_steps = steps;
     r_every = 0;
     mv_start = -1;
@@ -583,6 +583,10 @@ nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs) {
     nd_status s;
     if (want_r) {
         const int64_t len = steps / obs->record_every + 1;
+        if (len > R_cap && !may_alloc)
+            return fail(ND_ERR_INVALID_ARG,
+                        "recording %lld values of R needs a buffer an earlier run sized (it holds %lld)",
+                        (long long)len, (long long)R_cap);
         if (len > R_cap) {
             if (R_dev) {
                 (void)hipFree(R_dev);
@@ -594,6 +598,8 @@ nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs) {
         r_every = obs->record_every;
     }
     if (want_mv) {
+        if (!mv_dev && !may_alloc)
+            return fail(ND_ERR_INVALID_ARG, "recording the mean phase velocity needs a buffer an earlier run sized");
         if (!mv_dev && (s = alloc((void**)&mv_dev, prob.n * 8))) return s;
         mv_start = obs->mv_start_step;
     }
@@ -985,6 +991,163 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
     return ND_OK;
 }
 
+// ------------------------------------------------- runs that allocate nothing
+// nd_run_batch_noalloc keeps the descriptor tables, the per-group work counts and
+// the work maps in `scratch`, one fixed array per GPU, instead of memory taken per
+// call.  Layout: ND_NOALLOC_MAX_NETS descriptors, then ND_NOALLOC_MAX_NETS work
+// counts, then ND_NOALLOC_MAX_WORK work items; a call lays its groups out one
+// after the other.  Host code reaches the array only through the address
+// hipGetSymbolAddress returns for the current device (the symbol itself is a
+// host-side stand-in, not a device address).
+constexpr size_t kNaDescBytes = ((size_t)ND_NOALLOC_MAX_NETS * sizeof(NetDesc) + 255) / 256 * 256;
+constexpr size_t kNaCountBytes = ((size_t)ND_NOALLOC_MAX_NETS * sizeof(int) + 255) / 256 * 256;
+constexpr size_t kNaBytes = kNaDescBytes + kNaCountBytes + (size_t)ND_NOALLOC_MAX_WORK * sizeof(int2);
+static_assert(kNaBytes <= (size_t)ND_NOALLOC_SCRATCH_BYTES, "scratch layout exceeds its stated size");
+static __device__ __align__(256) unsigned char scratch[ND_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_na_mu;
+static unsigned char* g_na_ptr[kNaMaxDevices] = {};
+
+// The scratch array's device address on the current device, looked up once per
+// device (with that device current) and kept.
+static nd_status noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    HIPC(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return fail(ND_ERR_UNSUPPORTED, "device %d beyond %d devices", dev, kNaMaxDevices);
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (no-allocation scratch)");
+        g_na_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_na_ptr[dev];
+    return ND_OK;
+}
+
+// Work map of one group, built on the device from its descriptors (the same
+// order as the host-built map of nd_run_batch: networks in turn, tiles ascending).
+__global__ void k_noalloc_work(const NetDesc* D, int ndesc, int2* work, int* nwork) {
+    __shared__ int off[ND_NOALLOC_MAX_NETS + 1];
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int q = 0; q < ndesc; ++q) {
+            off[q] = o;
+            o += D[q].G;
+        }
+        off[ndesc] = o;
+        *nwork = o;
+    }
+    __syncthreads();
+    for (int q = 0; q < ndesc; ++q) {
+        const int G = off[q + 1] - off[q];
+        for (int t = threadIdx.x; t < G; t += blockDim.x) work[off[q] + t] = make_int2(q, t);
+    }
+}
+
+// nd_run_batch without allocation: the same groups, descriptors, work maps and
+// kernels as run_nets, with the tables in `scratch`, descriptors passed to the
+// device as kernel arguments and chunks launched eagerly (no graph capture).
+// Fixed-size host arrays only; nothing is allocated on the success path.
+static nd_status run_nets_noalloc(Net* const* nets, int count, const double* dt, const int64_t* steps,
+                                  const nd_observe* obs, hipStream_t st) {
+    if (count > ND_NOALLOC_MAX_NETS)
+        return fail(ND_ERR_INVALID_ARG, "%d networks, the no-allocation run takes at most %d", count,
+                    ND_NOALLOC_MAX_NETS);
+    int64_t total_work = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!nets[i]) return fail(ND_ERR_INVALID_ARG, "handle %d is NULL", i);
+        if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(ND_ERR_INVALID_ARG, "dt must be finite and > 0");
+        if (steps[i] < 0) return fail(ND_ERR_INVALID_ARG, "steps must be >= 0");
+        for (int k = 0; k < i; ++k)
+            if (nets[k] == nets[i]) return fail(ND_ERR_INVALID_ARG, "a handle appears twice in one batch");
+        if (steps[i] > 0) total_work += nets[i]->work_items();
+    }
+    if (total_work > ND_NOALLOC_MAX_WORK)
+        return fail(ND_ERR_INVALID_ARG, "%lld work items, the no-allocation run takes at most %d",
+                    (long long)total_work, ND_NOALLOC_MAX_WORK);
+    unsigned char* base = nullptr;
+    nd_status s = noalloc_scratch(&base);
+    if (s) return s;
+    for (int i = 0; i < count; ++i)
+        if ((s = nets[i]->prepare_observe(steps[i], obs ? &obs[i] : nullptr, false))) return s;
+    NetDesc* descs = (NetDesc*)base;
+    int* counts = (int*)(base + kNaDescBytes);
+    int2* works = (int2*)(base + kNaDescBytes + kNaCountBytes);
+    // groups of one kernel class, in order of first appearance
+    int key[ND_NOALLOC_MAX_NETS][7];
+    int grp[ND_NOALLOC_MAX_NETS];
+    int ngroups = 0;
+    for (int i = 0; i < count; ++i) {
+        grp[i] = -1;
+        if (steps[i] == 0) continue;
+        const Net* n = nets[i];
+        const bool lattice = n->prob.topo == ND_CUBE3D || n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D;
+        const bool ball = n->prob.topo == ND_BALL3D || n->prob.topo == ND_DISK2D;
+        const int k[7] = {n->prob.model, n->prob.topo, n->prob.precision, n->cfg.tile, n->cfg.tile_y,
+                          lattice ? (int)n->prob.radius : 0, ball ? n->cfg.block : 0};
+        int gi = 0;
+        while (gi < ngroups && std::memcmp(key[gi], k, sizeof k) != 0) ++gi;
+        if (gi == ngroups) std::memcpy(key[ngroups++], k, sizeof k);
+        grp[i] = gi;
+    }
+    int dnext = 0;
+    int64_t wnext = 0;
+    hipError_t e;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        Group g{};
+        g.model = key[gi][0];
+        g.topo = key[gi][1];
+        g.prec = key[gi][2];
+        g.tile = key[gi][3];
+        g.tile_y = key[gi][4];
+        g.h = key[gi][5];
+        g.block = key[gi][6];
+        g.desc = descs + dnext;
+        g.work = works + wnext;
+        g.nwork = counts + gi;
+        g.mv = false;
+        int64_t maxsteps = 0, nwork = 0, values = 0;
+        int first = -1;
+        for (int i = 0; i < count; ++i) {
+            if (grp[i] != gi) continue;
+            if (first < 0) first = i;
+            const Net* n = nets[i];
+            if ((e = put_desc(g.desc + g.ndesc, n->run_desc(dt[i], steps[i]), st)) != hipSuccess)
+                return hip_fail(e, "descriptor upload");
+            ++g.ndesc;
+            g.mv = g.mv || n->mv_start >= 0;
+            nwork += n->work_items();
+            values += n->prob.n * nvars_of(n->prob.model);
+            maxsteps = std::max(maxsteps, steps[i]);
+        }
+        hipLaunchKernelGGL(k_noalloc_work, dim3(1), dim3(256), 0, st, g.desc, g.ndesc, g.work, g.nwork);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "work map");
+        dnext += g.ndesc;
+        wnext += nwork;
+        const Net* n0 = nets[first];
+        const int cfg_grid = n0->cfg.grid;
+        g.grid = cfg_grid > 0 ? (int)std::min<int64_t>(cfg_grid, nwork) : (int)nwork;
+        // the chunking of nd_run_batch: one chunk, or chunks of K steps where that
+        // call replays a captured K-step graph (here launched directly)
+        const int K = std::max(1, n0->cfg.chunk);
+        const bool eager = values >= kEagerValues && !(g.topo == ND_RING && g.tile < 0);
+        if (maxsteps <= K || !graphs_enabled() || eager) {
+            if ((s = enqueue_chunk(g, (int)std::min<int64_t>(maxsteps, 1 << 30), st))) return s;
+        } else {
+            const int64_t reps = (maxsteps + K - 1) / K;
+            for (int64_t r = 0; r < reps; ++r)
+                if ((s = enqueue_chunk(g, K, st))) return s;
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        nets[i]->ypar ^= (int)(steps[i] & 1);
+        if ((s = nets[i]->touch(st))) return s;
+    }
+    return ND_OK;
+}
+
 }  // namespace nd
 
 // =================================================================== C ABI
@@ -1066,6 +1229,17 @@ nd_status nd_run_batch(const nd_handle* hs, int32_t count, const double* dt, con
     std::vector<Net*> nets(count);
     for (int i = 0; i < count; ++i) nets[i] = as_net(hs[i]);
     return run_nets(nets.data(), count, dt, steps, obs, (hipStream_t)stream);
+}
+
+nd_status nd_run_batch_noalloc(const nd_handle* hs, int32_t count, const double* dt, const int64_t* steps,
+                               const nd_observe* obs, void* stream) {
+    if (!hs || !dt || !steps || count < 0) return fail(ND_ERR_INVALID_ARG, "bad batch arguments");
+    if (count > ND_NOALLOC_MAX_NETS)
+        return fail(ND_ERR_INVALID_ARG, "%d networks, the no-allocation run takes at most %d", count,
+                    ND_NOALLOC_MAX_NETS);
+    Net* nets[ND_NOALLOC_MAX_NETS];
+    for (int i = 0; i < count; ++i) nets[i] = as_net(hs[i]);
+    return run_nets_noalloc(nets, count, dt, steps, obs, (hipStream_t)stream);
 }
 
 nd_status nd_get_observables(nd_handle h, double* R, int64_t r_len, double* mean_vel, int64_t mv_len,

@@ -20,6 +20,7 @@ ND_ERR_UNSUPPORTED = -6
 ND_KURAMOTO, ND_FHN, ND_HH, ND_KURAMOTO_INERTIA = 0, 1, 2, 3
 ND_RING, ND_CUBE3D, ND_CSR, ND_BALL3D, ND_DISK2D, ND_LINKS = 0, 1, 2, 3, 4, 5
 ND_FP64, ND_FP32_BULK = 0, 1
+ND_NOALLOC_MAX_NETS, ND_NOALLOC_MAX_WORK = 256, 262144  # nd_run_batch_noalloc limits (include/nd.h)
 ND_MAX_PARAMS = 12
 NVARS = {ND_KURAMOTO: 1, ND_FHN: 2, ND_HH: 4, ND_KURAMOTO_INERTIA: 2}
 
@@ -89,6 +90,7 @@ _sig = {
     "nd_set_state": [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp],
     "nd_run": [_c_vp, _c_dbl, _c_i64, _P(nd_observe), _c_vp],
     "nd_run_batch": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_i64), _P(nd_observe), _c_vp],
+    "nd_run_batch_noalloc": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_i64), _P(nd_observe), _c_vp],
     "nd_run_adaptive": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _P(nd_adaptive_stats),
                         _c_vp],
     "nd_run_adaptive_dense": [_P(_c_vp), _c_i32, _P(_c_dbl), _P(_c_dbl), _c_dbl, _c_dbl, _c_i64, _c_dbl, _c_vp,
@@ -253,6 +255,17 @@ def nd_run_batch(handles, dts, steps, obs=None, stream=None):
     ss = (_c_i64 * k)(*[int(x) for x in steps])
     oo = (nd_observe * k)(*obs) if obs is not None else None
     _check(_lib.nd_run_batch(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch")
+
+
+def nd_run_batch_noalloc(handles, dts, steps, obs=None, stream=None):
+    """nd_run_batch without any allocation (descriptor tables in the library's
+    fixed per-GPU array; see include/nd.h)."""
+    k = len(handles)
+    hs = (_c_vp * k)(*handles)
+    dd = (_c_dbl * k)(*[float(x) for x in dts])
+    ss = (_c_i64 * k)(*[int(x) for x in steps])
+    oo = (nd_observe * k)(*obs) if obs is not None else None
+    _check(_lib.nd_run_batch_noalloc(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch_noalloc")
 
 
 def nd_run_adaptive(handles, t_end, dt0, rtol, atol, max_steps=10 ** 7, stream=None):
