@@ -386,9 +386,8 @@ static int validate(const orc_net* m) {
         int64_t side = 2 * m->radius + 1;
         if (m->radius < 1 || m->n1 < side || m->n2 < side || m->n3 < side) return ORC_EINVAL;
         if (m->n1 * m->n2 * m->n3 != m->n) return ORC_EINVAL;
-    } else if (m->topo == ORC_CSR) {
-        if (!m->row_ptr || !m->col || !m->w || !m->per_elem) return ORC_EINVAL;
-    } else if (m->topo == ORC_LINKS) {
+    } else if (m->topo == ORC_CSR || m->topo == ORC_LINKS) {
+        if (m->topo == ORC_CSR && (!m->col || !m->w || !m->per_elem)) return ORC_EINVAL;
         if (!m->row_ptr || m->row_ptr[0] != 0) return ORC_EINVAL;
         for (int64_t i = 0; i < m->n; ++i) {
             if (m->row_ptr[i + 1] < m->row_ptr[i]) return ORC_EINVAL;
