@@ -363,8 +363,11 @@ typedef struct nd_server_counters {
     int64_t submitted, completed, failed, cancelled, queued, running;
     int64_t bytes_in_use;  /* footprint of the running requests */
     int64_t chunks;        /* chunks launched */
-    double gpu_seconds;    /* time spent waiting for chunks */
+    double gpu_seconds;    /* device time of the completed chunks (events around each chunk) */
     int64_t osc_steps;     /* element-steps completed */
+    double active_seconds; /* wall time between pumps during which requests were admitted or chunks
+                              in flight; gpu_seconds / active_seconds is the device's busy share
+                              while there was work (the rest: host gaps between chunks) */
 } nd_server_counters;
 
 nd_status nd_server_create(const nd_server_config* cfg, nd_server_h* out);
@@ -376,9 +379,13 @@ nd_status nd_server_now(nd_server_h s, double* seconds);
  * non-finite y0; the request then does not exist.  Never touches the GPU. */
 nd_status nd_server_submit(nd_server_h s, const nd_problem* p, const double* y0, int64_t len, double dt,
                            int64_t steps, const nd_observe* obs, double arrival, nd_req* id);
-/* One scheduling cycle on `stream`: admit from the queue, run one chunk of every admitted request,
- * wait for it, retire finished requests (results copied to host memory).  *pending receives the
- * number of queued + running requests afterwards. */
+/* One scheduling cycle on `stream`: retire the requests whose last chunk has completed (results
+ * copied to host memory on a copy stream of the server), admit from the queue (device memory from
+ * the stream-ordered pool, initial state uploaded on the copy stream), enqueue the next chunk of
+ * every admitted request with steps left, and wait for the chunk before it, so one chunk stays
+ * queued behind the running one and the host's work overlaps the device's.  The first
+ * admission creates the server's device resources.  *pending receives the number of queued + running
+ * requests afterwards. */
 nd_status nd_server_pump(nd_server_h s, void* stream, int64_t* pending);
 nd_status nd_server_info(nd_server_h s, nd_req id, nd_request_info* info);
 /* Final state (len = nvars*n) and R (r_len = steps/record_every + 1, or NULL / 0) of a done request. */

@@ -49,6 +49,11 @@ struct Net {
     hipGraphExec_t solo_graph[2] = {nullptr, nullptr};
     int solo_graph_key[2][2] = {{0, 0}, {0, 0}};
     std::vector<void*> allocs;
+    // Stream-ordered mode (networks the server owns): buffers come from the device's
+    // stream-ordered pool (hipMallocAsync / hipFreeAsync on `astream`), set-up copies
+    // are enqueued on it, and the pinned status word is supplied by the owner.
+    hipStream_t astream = nullptr;
+    bool own_status_host = true;
 
     ~Net();
     // wait until the device no longer uses this network's buffers

@@ -332,7 +332,7 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
 nd_status Net::alloc(void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(ptr, bytes);
+    hipError_t e = astream ? hipMallocAsync(ptr, bytes, astream) : hipMalloc(ptr, bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
     allocs.push_back(*ptr);
     return ND_OK;
@@ -361,11 +361,26 @@ void Net::drop_graphs() {
 }
 
 Net::~Net() {
-    quiesce();
-    drop_graphs();
-    for (void* q : allocs) (void)hipFree(q);
-    if (status_host) (void)hipHostFree(status_host);
+    if (astream) {
+        // the owner has seen the network's last work complete; the frees are
+        // ordered on astream (no device-wide synchronisation)
+        drop_graphs();
+        for (void* q : allocs) (void)hipFreeAsync(q, astream);
+    } else {
+        quiesce();
+        drop_graphs();
+        for (void* q : allocs) (void)hipFree(q);
+    }
+    if (status_host && own_status_host) (void)hipHostFree(status_host);
     if (last_ev) (void)hipEventDestroy(last_ev);
+}
+
+// Host-to-device copy of set-up data (sources are host temporaries): synchronous,
+// or on astream, waiting for that stream only, not for the device.
+static hipError_t setup_copy(hipStream_t astream, void* dst, const void* src, size_t bytes) {
+    if (!astream) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, astream);
+    return e != hipSuccess ? e : hipStreamSynchronize(astream);
 }
 
 static void derive_params(const nd_problem* p, NetDesc& d) {
@@ -457,18 +472,18 @@ nd_status Net::create(const nd_problem* pr) {
         if ((s = alloc((void**)&d.iapp, n * 8))) return s;
         for (int b = 0; b < 2; ++b)
             if ((s = alloc(&d.sx[b], n * kb))) return s;
-        HIPC(hipMemcpy((void*)d.row_ptr, bptr.data(), bptr.size() * 8, hipMemcpyHostToDevice));
+        HIPC(setup_copy(astream, (void*)d.row_ptr, bptr.data(), bptr.size() * 8));
         if (nnz > 0) {
-            HIPC(hipMemcpy((void*)d.col, col2.data(), nnz * 4, hipMemcpyHostToDevice));
+            HIPC(setup_copy(astream, (void*)d.col, col2.data(), nnz * 4));
             if (kb == 8) {
-                HIPC(hipMemcpy((void*)d.w, w2.data(), nnz * 8, hipMemcpyHostToDevice));
+                HIPC(setup_copy(astream, (void*)d.w, w2.data(), nnz * 8));
             } else {
                 std::vector<float> wf(nnz);
                 for (int64_t e = 0; e < nnz; ++e) wf[e] = (float)w2[e];
-                HIPC(hipMemcpy((void*)d.w, wf.data(), nnz * 4, hipMemcpyHostToDevice));
+                HIPC(setup_copy(astream, (void*)d.w, wf.data(), nnz * 4));
             }
         }
-        HIPC(hipMemcpy((void*)d.iapp, pr->per_elem, n * 8, hipMemcpyHostToDevice));
+        HIPC(setup_copy(astream, (void*)d.iapp, pr->per_elem, n * 8));
     }
     if (pr->topo == ND_LINKS) {
         LinksCompressed lc;
@@ -486,17 +501,17 @@ nd_status Net::create(const nd_problem* pr) {
         for (int b = 0; b < 2; ++b)
             if ((s = alloc(&d.sx[b], n * (int64_t)links_map_bytes(pr->model, pr->precision)))) return s;
         d.lnv = (int32_t)lc.V.size();
-        HIPC(hipMemcpy((void*)d.lrow, lc.C.data(), n * 4, hipMemcpyHostToDevice));
-        if (!lc.V.empty()) HIPC(hipMemcpy((void*)d.lvpos, lc.V.data(), lc.V.size() * 4, hipMemcpyHostToDevice));
-        HIPC(hipMemcpy((void*)d.ldptr, f.dptr.data(), (K + 1) * 4, hipMemcpyHostToDevice));
-        if (!f.dsig.empty()) HIPC(hipMemcpy((void*)d.ldpos, f.dsig.data(), f.dsig.size() * 4, hipMemcpyHostToDevice));
-        HIPC(hipMemcpy((void*)d.linv, f.inv.data(), K * 8, hipMemcpyHostToDevice));
+        HIPC(setup_copy(astream, (void*)d.lrow, lc.C.data(), n * 4));
+        if (!lc.V.empty()) HIPC(setup_copy(astream, (void*)d.lvpos, lc.V.data(), lc.V.size() * 4));
+        HIPC(setup_copy(astream, (void*)d.ldptr, f.dptr.data(), (K + 1) * 4));
+        if (!f.dsig.empty()) HIPC(setup_copy(astream, (void*)d.ldpos, f.dsig.data(), f.dsig.size() * 4));
+        HIPC(setup_copy(astream, (void*)d.linv, f.inv.data(), K * 8));
     }
     if ((s = alloc((void**)&solo_desc, sizeof(NetDesc)))) return s;
     if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
     if ((s = alloc((void**)&status_dev, sizeof(int32_t)))) return s;
-    HIPC(hipMemset(status_dev, 0, sizeof(int32_t)));
-    HIPC(hipHostMalloc((void**)&status_host, sizeof(int32_t)));
+    HIPC(astream ? hipMemsetAsync(status_dev, 0, sizeof(int32_t), astream) : hipMemset(status_dev, 0, sizeof(int32_t)));
+    if (own_status_host) HIPC(hipHostMalloc((void**)&status_host, sizeof(int32_t)));
     *status_host = 0;
     HIPC(hipEventCreateWithFlags(&last_ev, hipEventDisableTiming));
     d.status = status_dev;
@@ -555,9 +570,9 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
     std::vector<int2> wk;
     append_work(0, wk);
     if ((s = alloc((void**)&solo_work, wk.size() * sizeof(int2)))) return s;
-    HIPC(hipMemcpy(solo_work, wk.data(), wk.size() * sizeof(int2), hipMemcpyHostToDevice));
+    HIPC(setup_copy(astream, solo_work, wk.data(), wk.size() * sizeof(int2)));
     int cnt[2] = {(int)wk.size(), 1};
-    HIPC(hipMemcpy(solo_count, cnt, sizeof cnt, hipMemcpyHostToDevice));
+    HIPC(setup_copy(astream, solo_count, cnt, sizeof cnt));
     return ND_OK;
 }
 

@@ -65,7 +65,7 @@ class nd_request_info(ctypes.Structure):
 class nd_server_counters(ctypes.Structure):
     _fields_ = [("submitted", _c_i64), ("completed", _c_i64), ("failed", _c_i64), ("cancelled", _c_i64),
                 ("queued", _c_i64), ("running", _c_i64), ("bytes_in_use", _c_i64), ("chunks", _c_i64),
-                ("gpu_seconds", _c_dbl), ("osc_steps", _c_i64)]
+                ("gpu_seconds", _c_dbl), ("osc_steps", _c_i64), ("active_seconds", _c_dbl)]
 
 
 ND_REQ_QUEUED, ND_REQ_RUNNING, ND_REQ_DONE, ND_REQ_FAILED, ND_REQ_CANCELLED = range(5)
