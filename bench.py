@@ -390,6 +390,21 @@ def roofline(wl, args, prec, ev_total, cfg):
             "bytes_per_launch": per_launch, "avg_launch_us": stage_s * 1e6}
 
 
+LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 bytes per clock x 2.4 GHz
+
+
+def lds_roofline(wl, args, ev_total):
+    """The ball kernel's prefix reads against the LDS bandwidth: every output adds,
+    per (dy, dz) run of the ball, the difference of two 16-byte prefix values."""
+    P = args.radius
+    runs = sum(1 for dz in range(-P, P + 1) for dy in range(-P, P + 1) if dz * dz + dy * dy <= P * P)
+    per_launch = args.batch * wl.n * 2 * runs * 16
+    stage_s = ev_total / (4 * args.horizon * args.steps)
+    achieved = per_launch / stage_s / 1e9
+    return {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS,
+            "bytes_per_launch": per_launch, "reads_per_output": 2 * runs}
+
+
 # ------------------------------------------------------------------- serving
 def serve_requests(args):
     """The request stream: model, N, P, alpha, horizon, seed and arrival gap per request."""
@@ -724,6 +739,8 @@ def main():
         "state_finite": finite,
         "roofline": roofline(wl, args, 0, ev_total, cfg),
     }
+    if args.workload == "ball":
+        out["lds_roofline"] = lds_roofline(wl, args, ev_total)
     if not args.no_fp32:
         wall32, times32, ev32, fin32, cfg32 = run(nd, torch, wl, args, nd.ND_FP32_BULK, stream)
         v32 = osc_per_step * args.steps / wall32
