@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,13 @@ nd_kernel_config config_for(const nd_problem* p);
 int ring_block(int tile);
 int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c);
 
+// An event recorded once behind a batch's work and shared by its networks (one
+// record per batch instead of one per network).
+struct RunEvent {
+    hipEvent_t ev = nullptr;
+    ~RunEvent();
+};
+
 // A network handle (nd_handle).
 struct Net {
     nd_problem prob{};        // copy without host pointers
@@ -42,7 +50,8 @@ struct Net {
     int* solo_count = nullptr;
     int32_t* status_dev = nullptr;   // status word the stage kernels flag (non-finite state)
     int32_t* status_host = nullptr;  // pinned copy, read after a synchronising call
-    hipEvent_t last_ev = nullptr;    // recorded after the last work enqueued for this network
+    hipEvent_t last_ev = nullptr;    // recorded after the last work enqueued for this network alone
+    std::shared_ptr<RunEvent> batch_ev;  // else the event of the batch that last ran it
     bool ev_recorded = false;
     // chunk graph of this network alone, replayed by every nd_run with the same
     // chunk length, grid and mean-velocity setting (rebuilt when the config changes)
@@ -60,6 +69,8 @@ struct Net {
     void quiesce();
     // mark the network's buffers as used by the work enqueued on st so far
     nd_status touch(hipStream_t st);
+    // the same, through an event already recorded behind a batch holding this network
+    void touch_shared(const std::shared_ptr<RunEvent>& ev);
     void drop_graphs();
     nd_status alloc(void** ptr, size_t bytes);
     nd_status create(const nd_problem* p);

@@ -338,18 +338,29 @@ nd_status Net::alloc(void** ptr, size_t bytes) {
     return ND_OK;
 }
 
+RunEvent::~RunEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+}
+
 void Net::quiesce() {
     if (ev_recorded) {
-        (void)hipEventSynchronize(last_ev);
+        (void)hipEventSynchronize(batch_ev ? batch_ev->ev : last_ev);
         ev_recorded = false;
     }
+    batch_ev.reset();
 }
 
 nd_status Net::touch(hipStream_t st) {
+    batch_ev.reset();
     hipError_t e = hipEventRecord(last_ev, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     ev_recorded = true;
     return ND_OK;
+}
+
+void Net::touch_shared(const std::shared_ptr<RunEvent>& ev) {
+    batch_ev = ev;
+    ev_recorded = true;
 }
 
 void Net::drop_graphs() {
@@ -887,8 +898,12 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         if (!nets[i]) return fail(ND_ERR_INVALID_ARG, "handle %d is NULL", i);
         if (!(dt[i] > 0.0) || !std::isfinite(dt[i])) return fail(ND_ERR_INVALID_ARG, "dt must be finite and > 0");
         if (steps[i] < 0) return fail(ND_ERR_INVALID_ARG, "steps must be >= 0");
-        for (int k = 0; k < i; ++k)
-            if (nets[k] == nets[i]) return fail(ND_ERR_INVALID_ARG, "a handle appears twice in one batch");
+    }
+    {
+        std::vector<Net*> sorted(nets, nets + count);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(ND_ERR_INVALID_ARG, "a handle appears twice in one batch");
     }
     reap_graphs();
     nd_status s;
@@ -999,10 +1014,13 @@ nd_status run_nets(Net* const* nets, int count, const double* dt, const int64_t*
         }
         if (scratch) HIPC(hipFreeAsync(scratch, st));
     }
-    for (int i = 0; i < count; ++i) {
-        nets[i]->ypar ^= (int)(steps[i] & 1);
-        if ((s = nets[i]->touch(st))) return s;
-    }
+    for (int i = 0; i < count; ++i) nets[i]->ypar ^= (int)(steps[i] & 1);
+    if (count == 1) return nets[0]->touch(st);
+    // one event behind the whole batch, shared by its networks
+    auto ev = std::make_shared<RunEvent>();
+    HIPC(hipEventCreateWithFlags(&ev->ev, hipEventDisableTiming));
+    HIPC(hipEventRecord(ev->ev, st));
+    for (int i = 0; i < count; ++i) nets[i]->touch_shared(ev);
     return ND_OK;
 }
 

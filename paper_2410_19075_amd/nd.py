@@ -248,24 +248,30 @@ def nd_run(h, dt, steps, obs=None, stream=None):
                        _stream(stream)), "nd_run")
 
 
-def nd_run_batch(handles, dts, steps, obs=None, stream=None):
+def _batch_args(handles, dts, steps, obs):
+    """Handle, dt and step arrays of a batch call (numpy buffers: a per-element
+    ctypes conversion costs about a millisecond for thousands of networks)."""
     k = len(handles)
-    hs = (_c_vp * k)(*handles)
-    dd = (_c_dbl * k)(*[float(x) for x in dts])
-    ss = (_c_i64 * k)(*[int(x) for x in steps])
+    hs = np.asarray([0 if h is None else h for h in handles], dtype=np.uintp)
+    dd = np.ascontiguousarray(dts, dtype=np.float64)
+    ss = np.ascontiguousarray(steps, dtype=np.int64)
+    if dd.shape != (k,) or ss.shape != (k,):
+        raise ValueError("dts and steps need one entry per handle")
     oo = (nd_observe * k)(*obs) if obs is not None else None
-    _check(_lib.nd_run_batch(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch")
+    return (k, hs, dd, ss, oo, hs.ctypes.data_as(_P(_c_vp)), dd.ctypes.data_as(_P(_c_dbl)),
+            ss.ctypes.data_as(_P(_c_i64)))
+
+
+def nd_run_batch(handles, dts, steps, obs=None, stream=None):
+    k, _h, _d, _s, oo, hp, dp, sp = _batch_args(handles, dts, steps, obs)
+    _check(_lib.nd_run_batch(hp, k, dp, sp, oo, _stream(stream)), "nd_run_batch")
 
 
 def nd_run_batch_noalloc(handles, dts, steps, obs=None, stream=None):
     """nd_run_batch without any allocation (descriptor tables in the library's
     fixed per-GPU array; see include/nd.h)."""
-    k = len(handles)
-    hs = (_c_vp * k)(*handles)
-    dd = (_c_dbl * k)(*[float(x) for x in dts])
-    ss = (_c_i64 * k)(*[int(x) for x in steps])
-    oo = (nd_observe * k)(*obs) if obs is not None else None
-    _check(_lib.nd_run_batch_noalloc(hs, k, dd, ss, oo, _stream(stream)), "nd_run_batch_noalloc")
+    k, _h, _d, _s, oo, hp, dp, sp = _batch_args(handles, dts, steps, obs)
+    _check(_lib.nd_run_batch_noalloc(hp, k, dp, sp, oo, _stream(stream)), "nd_run_batch_noalloc")
 
 
 def nd_run_adaptive(handles, t_end, dt0, rtol, atol, max_steps=10 ** 7, stream=None):
