@@ -112,7 +112,7 @@ def parse():
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-z", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="persistent grid override (0 = one block per work item)")
-    ap.add_argument("--block", type=int, default=0, help="ball: workgroup size override (256 or 1024)")
+    ap.add_argument("--block", type=int, default=0, help="ball: workgroup size override (256 or 1024: gather form; 512: plane-scatter form)")
     ap.add_argument("--chunk", type=int, default=0, help="steps per captured graph chunk (0 = default)")
     ap.add_argument("--hmin", type=float, default=1e3, help="serve: shortest horizon (RK4 steps)")
     ap.add_argument("--hmax", type=float, default=1e5, help="serve: longest horizon (RK4 steps)")
@@ -209,6 +209,14 @@ class Workload:
             from paper_2410_19075_amd import inputs
             self.graph = inputs.random_out_graph(1, self.n, 100)
             self.iapp = inputs.hh_iapp(1, self.n)
+
+    def kernel_form(self, cfg):
+        """Ball workloads: the plane-scatter form runs where the configuration's
+        workgroup is 512 threads."""
+        if self.a.workload == "ball" and cfg.get("block") == 512:
+            self.kernel = "k_ball_scatter<inertia>"
+            self.prof = (f"ball_scatter_inertia_{self.n1}cubed_p{self.a.radius}.md", "k_ball_scatter",
+                         ["ball.hip", "models.h", "nd_dev.h", "runtime.hip"])
 
     def problem(self, prec):
         nd, w = self.nd, self.a.workload
@@ -393,16 +401,36 @@ def roofline(wl, args, prec, ev_total, cfg):
 LDS_PEAK_GBS = 256 * 128 * 2.4  # 256 CUs x 128 bytes per clock x 2.4 GHz
 
 
-def lds_roofline(wl, args, ev_total):
-    """The ball kernel's prefix reads against the LDS bandwidth: every output adds,
-    per (dy, dz) run of the ball, the difference of two 16-byte prefix values."""
-    P = args.radius
-    runs = sum(1 for dz in range(-P, P + 1) for dy in range(-P, P + 1) if dz * dz + dy * dy <= P * P)
-    per_launch = args.batch * wl.n * 2 * runs * 16
+def ball_prefix_reads(P, n1, n3, cfg):
+    """16-byte prefix reads of one ball stage launch over an n1 x n1 x n3 lattice.
+    Gather form: every output reads two prefix values per (dy, dz) run of the
+    ball.  Plane-scatter form (block 512): per mapped plane every output thread
+    reads two values per (|dz|, dy) run pair whose two output planes include one
+    of its work item's outputs (the pair serves dz and -dz)."""
+    rz = [int(np.floor(np.sqrt(P * P - a * a) + 1e-9)) for a in range(P + 1)]
+    if cfg.get("block") != 512:
+        runs = sum(2 * rz[abs(dz)] + 1 for dz in range(-P, P + 1))
+        return n1 * n1 * n3 * 2 * runs
+    cx, cy, cz = cfg["tile"], cfg["tile_y"], cfg["tile_z"]
+    per_thread = 0
+    for z0 in range(0, n3, cz):
+        nz = min(cz, n3 - z0)
+        for q in range(nz + 2 * P):
+            for a in range(P + 1):
+                o1, o2 = q - P - a, q - P + a
+                if 0 <= o1 < nz or (a > 0 and 0 <= o2 < nz):
+                    per_thread += 2 * (2 * rz[a] + 1)
+    return n1 * n1 * per_thread  # every xy column is one output thread of one tile
+
+
+def lds_roofline(wl, args, ev_total, cfg):
+    """The ball kernel's prefix reads against the LDS bandwidth (16 bytes each)."""
+    reads = args.batch * ball_prefix_reads(args.radius, wl.n1, wl.n1, cfg)
+    per_launch = reads * 16
     stage_s = ev_total / (4 * args.horizon * args.steps)
     achieved = per_launch / stage_s / 1e9
     return {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS,
-            "bytes_per_launch": per_launch, "reads_per_output": 2 * runs}
+            "bytes_per_launch": per_launch, "reads_per_output": reads / (args.batch * wl.n)}
 
 
 # ------------------------------------------------------------------- serving
@@ -717,6 +745,7 @@ def main():
     wl = Workload(args, nd)
     osc_per_step = args.batch * wl.n * args.horizon
     wall, times, ev_total, finite, cfg = run(nd, torch, wl, args, nd.ND_FP64, stream)
+    wl.kernel_form(cfg)
     value = osc_per_step * args.steps / wall
     out = {
         "metric": "oscillator-steps/s",
@@ -740,7 +769,7 @@ def main():
         "roofline": roofline(wl, args, 0, ev_total, cfg),
     }
     if args.workload == "ball":
-        out["lds_roofline"] = lds_roofline(wl, args, ev_total)
+        out["lds_roofline"] = lds_roofline(wl, args, ev_total, cfg)
     if not args.no_fp32:
         wall32, times32, ev32, fin32, cfg32 = run(nd, torch, wl, args, nd.ND_FP32_BULK, stream)
         v32 = osc_per_step * args.steps / wall32

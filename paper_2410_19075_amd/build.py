@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libnd.so")
 
-SOURCES = ["ring.hip", "cube.hip", "csr.hip", "runtime.hip", "serve.hip", "tune.hip", "dopri.hip", "links.hip"]
+SOURCES = ["ring.hip", "cube.hip", "csr.hip", "runtime.hip", "serve.hip", "tune.hip", "dopri.hip", "links.hip", "ball.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -146,6 +146,18 @@ bool cube_select(int model, int prec, int h, CubeLaunch* out);
 constexpr int kBallMaxP = 8;
 bool ball_select(int model, int prec, int block, CubeLaunch* out);
 size_t ball_smem_bytes(int P, int pz, int cx, int cy);
+// Ball in plane-scatter form (ball.hip): 3D balls of the radii it is built for,
+// workgroups of kBallScatterBlock threads (config block = kBallScatterBlock
+// selects it), halo rows of HX = cx + 2P <= 64 lanes, HY = cy + 2P <= 32, one
+// output per thread, two prefix planes in LDS (ball_scatter_smem_bytes).
+constexpr int kBallScatterBlock = 512;
+constexpr int kBallScatterPairedMaxP = 6;  // radii built for two workgroups per CU
+bool ball_scatter_available(int P);
+bool ball_scatter_select(int model, int prec, int P, CubeLaunch* out);
+size_t ball_scatter_smem_bytes(int P, int cx, int cy);
+// The gather form's configuration for a ball or disk problem (the tuner's
+// alternative where the default is the plane-scatter form).
+nd_kernel_config ball_gather_config(const nd_problem* p);
 inline int ball_pz(int topo, int64_t P) { return topo == ND_DISK2D ? 0 : (int)P; }
 constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB per CU, minus statics)
 int64_t ball_points(int64_t P);

@@ -175,7 +175,55 @@ static int ball_runs(int P, int pz) {
 // permitting), a 1024-thread one holds the CU alone.  The estimated time is
 // (rounds of workgroups over the CU slots) x (planes per work item incl. the
 // 2P lead-in) x (halo rows per wave + the outputs' prefix reads / 10).
-static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_, int* bs_) {
+// Plane-scatter form: 512-thread workgroups, two per CU where the radius is
+// built for it and the two prefix planes fit twice in LDS.  Per plane every wave
+// maps up to 4 halo rows (~720 clocks of issue per row and SIMD), then the
+// outputs read two prefix values per (|dz|, dy) run pair: the larger of the
+// pairs' VALU issue (~48 clocks per pair and SIMD) and their LDS traffic (cx*cy
+// outputs x 32 bytes per pair at 128 bytes per clock).  Work items pay the 2P
+// lead-in planes in mapping only; a CU running two work items at once is
+// counted at 0.8 of running them one after the other (measured at P = 6).
+// The default for radii from kBallScatterMinP (at smaller radii the gather
+// form measured faster).
+constexpr int kBallScatterMinP = 3;
+static bool ball_tiles_scatter(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_) {
+    const int P = (int)p->radius;
+    if (p->topo != ND_BALL3D || !ball_scatter_available(P) || P < kBallScatterMinP) return false;
+    const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
+    const int waves = kBallScatterBlock / 64;
+    int pairs = 0;  // runs of dz >= 0 (those of -dz share their reads)
+    for (int dz = 0; dz <= P; ++dz)
+        for (int dy = -P; dy <= P; ++dy) pairs += dz * dz + dy * dy <= P * P;
+    double best = 1e300;
+    bool found = false;
+    for (int cx = 1; cx <= std::min(n1, 64 - 2 * P); ++cx) {
+        for (int cy = 1; cy <= std::min(n2, 4 * waves - 2 * P); ++cy) {
+            if (cx * cy > kBallScatterBlock) break;
+            const size_t sm = ball_scatter_smem_bytes(P, cx, cy);
+            if (sm > kBallSmemMax) break;
+            const int per_cu = P <= kBallScatterPairedMaxP && 2 * sm <= kBallSmemMax ? 2 : 1;
+            const double overlap = per_cu == 2 ? 0.8 : 1.0;
+            const int64_t tiles = (int64_t)((n1 + cx - 1) / cx) * ((n2 + cy - 1) / cy);
+            const double map = 720.0 * ((cy + 2 * P + waves - 1) / waves);
+            const double sums = std::max(48.0 * pairs, (double)cx * cy * pairs * 32.0 / 128.0);
+            for (int zt = 1; zt <= std::min(n3, 256); ++zt) {
+                const int cz = (n3 + zt - 1) / zt;
+                if (zt > 1 && (n3 + cz - 1) / cz != zt) continue;
+                const int64_t rounds = (tiles * zt + (int64_t)cus * per_cu - 1) / ((int64_t)cus * per_cu);
+                const double cost =
+                    (double)rounds * per_cu * overlap * ((cz + 2 * P) * map + cz * sums) - 1e-6 * cx * cy;
+                if (cost < best) {
+                    best = cost;
+                    found = true;
+                    *cx_ = cx, *cy_ = cy, *cz_ = cz;
+                }
+            }
+        }
+    }
+    return found;
+}
+
+static void ball_tiles_gather(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_, int* bs_) {
     const int P = (int)p->radius, pz = ball_pz(p->topo, p->radius);
     const int n1 = (int)p->n1, n2 = (int)p->n2, n3 = (int)p->n3;
     const double reads = 0.1 * ball_runs(P, pz);
@@ -204,6 +252,25 @@ static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz
             }
         }
     }
+}
+
+static void ball_tiles(const nd_problem* p, int cus, int* cx_, int* cy_, int* cz_, int* bs_) {
+    if (ball_tiles_scatter(p, cus, cx_, cy_, cz_)) {
+        *bs_ = kBallScatterBlock;
+        return;
+    }
+    ball_tiles_gather(p, cus, cx_, cy_, cz_, bs_);
+}
+
+nd_kernel_config ball_gather_config(const nd_problem* p) {
+    nd_kernel_config c = default_config(p);
+    int cx, cy, cz, bs;
+    ball_tiles_gather(p, device_cu_count(), &cx, &cy, &cz, &bs);
+    c.tile = cx;
+    c.tile_y = cy;
+    c.tile_z = cz;
+    c.block = bs;
+    return c;
 }
 
 // ------------------------------------------------------------ configuration
@@ -717,9 +784,11 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
             return hip_fail(e, "cube final");
     } else if (g.topo == ND_BALL3D || g.topo == ND_DISK2D) {
         CubeLaunch L;
-        if (!ball_select(g.model, g.prec, g.block, &L))
-            return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d, block %d", g.model, g.block);
-        const size_t smem = ball_smem_bytes(g.h, ball_pz(g.topo, g.h), g.tile, g.tile_y);
+        const bool scatter = g.block == kBallScatterBlock;
+        if (scatter ? !ball_scatter_select(g.model, g.prec, g.h, &L) : !ball_select(g.model, g.prec, g.block, &L))
+            return fail(ND_ERR_UNSUPPORTED, "no ball kernel for model %d, block %d, radius %d", g.model, g.block, g.h);
+        const size_t smem = scatter ? ball_scatter_smem_bytes(g.h, g.tile, g.tile_y)
+                                    : ball_smem_bytes(g.h, ball_pz(g.topo, g.h), g.tile, g.tile_y);
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
                 if ((e = cube_launch_stage(L, grid, g.block, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
@@ -1344,12 +1413,19 @@ nd_status nd_set_config(nd_handle h, const nd_kernel_config* cfg) {
         c.tile = (int32_t)std::min<int64_t>(c.tile, p.n1);
         c.tile_y = (int32_t)std::min<int64_t>(c.tile_y, p.n2);
         c.tile_z = (int32_t)std::min<int64_t>(c.tile_z, p.n3);
-        if (c.block != 256 && c.block != 1024) c.block = 1024;
+        if (c.block == kBallScatterBlock) {
+            if (p.topo != ND_BALL3D || !ball_scatter_available(P))
+                return fail(ND_ERR_INVALID_ARG, "block %d (plane-scatter ball) is not built for this radius or topology",
+                            kBallScatterBlock);
+        } else if (c.block != 256 && c.block != 1024) {
+            c.block = 1024;
+        }
         const int rows = 4 * (c.block / 64);
-        if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > rows || c.tile * c.tile_y > c.block ||
-            ball_smem_bytes(P, pz, c.tile, c.tile_y) > kBallSmemMax)
+        const size_t sm = c.block == kBallScatterBlock ? ball_scatter_smem_bytes(P, c.tile, c.tile_y)
+                                                       : ball_smem_bytes(P, pz, c.tile, c.tile_y);
+        if (c.tile + 2 * P > 64 || c.tile_y + 2 * P > rows || c.tile * c.tile_y > c.block || sm > kBallSmemMax)
             return fail(ND_ERR_INVALID_ARG, "ball tile: need tile+2P <= 64, tile_y+2P <= 4*block/64, "
-                                            "tile*tile_y <= block and the prefix ring within LDS");
+                                            "tile*tile_y <= block and the prefix planes within LDS");
     } else if (p.topo == ND_LINKS) {
         if (c.tile != kLinksRows) return fail(ND_ERR_INVALID_ARG, "links work items hold %d rows (tile must be %d)",
                                               kLinksRows, kLinksRows);

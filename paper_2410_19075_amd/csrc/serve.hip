@@ -152,7 +152,10 @@ nd_status Server::init() {
 }
 
 Server::~Server() {
-    if (cs) (void)hipDeviceSynchronize();
+    // wait for the chunks still in flight (their end events) and the copy stream,
+    // not for the whole device
+    for (auto& f : inflight) (void)hipEventSynchronize(f.end);
+    if (cs) (void)hipStreamSynchronize(cs);
     for (Request* r : running) {
         if (r->net) delete r->net;
         if (r->ready) (void)hipEventDestroy(r->ready);

@@ -86,11 +86,15 @@ static std::vector<nd_kernel_config> candidates(const nd_problem* p) {
             }
         }
     } else if (p->topo == ND_BALL3D || p->topo == ND_DISK2D) {
-        v.push_back(base);  // the cost-model tiling
-        for (int cz : {base.tile_z * 2, (base.tile_z + 1) / 2}) {
-            nd_kernel_config c = base;
-            c.tile_z = (int)std::max<int64_t>(1, std::min<int64_t>(cz, p->n3));
-            v.push_back(c);
+        std::vector<nd_kernel_config> bases{base};  // the cost-model tiling
+        if (base.block == kBallScatterBlock) bases.push_back(ball_gather_config(p));  // and the gather form's
+        for (const nd_kernel_config& b : bases) {
+            v.push_back(b);
+            for (int cz : {b.tile_z * 2, (b.tile_z + 1) / 2}) {
+                nd_kernel_config c = b;
+                c.tile_z = (int)std::max<int64_t>(1, std::min<int64_t>(cz, p->n3));
+                v.push_back(c);
+            }
         }
     } else if (p->topo == ND_LINKS) {
         v.push_back(base);  // one kernel shape

@@ -62,7 +62,7 @@ def case(nd, model, dims, P, seed, steps, prec=0, cfg=None, record_every=0, mv=-
 
 @pytest.mark.parametrize("model", ["kuramoto", "inertia"])
 @pytest.mark.parametrize("dims,P", [((12, 12, 12), 1), ((20, 18, 16), 2), ((13, 14, 15), 3), ((13, 13, 13), 6),
-                                    ((11, 30, 9), 4)])
+                                    ((11, 30, 9), 4), ((15, 11, 12), 5), ((15, 16, 15), 7), ((17, 18, 17), 8)])
 def test_ball_fp64_parity(nd, model, dims, P):
     print(f"case ball {model} dims={dims} P={P}", flush=True)
     y, ref, R, Rref, mv, mvref, nv = case(nd, model, dims, P, sum(dims) + P, 25, record_every=5, mv=10)
@@ -112,6 +112,104 @@ def test_ball_paper_performance_shapes(nd, n1, P, steps):
     y, _, _ = nd.simulate(p, y0, 0.05, steps)
     ref, _, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, steps)
     assert normwise(y, ref, 2) < 1e-12
+
+
+def run_cfg(nd, model, dims, P, seed, steps, prec, cfg):
+    """Final state and R(t) of one run with the given kernel configuration."""
+    n = dims[0] * dims[1] * dims[2]
+    phases = inputs.kuramoto_phases(seed, n)
+    if model == "inertia":
+        y0 = np.concatenate([phases, inputs.uniform_range(seed, inputs.TAG_MISC, n, -0.5, 0.5)])
+        code, prm = nd.ND_KURAMOTO_INERTIA, INERT
+    else:
+        y0, code, prm = phases, nd.ND_KURAMOTO, KUR
+    p = nd.problem(code, nd.ND_BALL3D, n, prm, precision=prec, radius=P, dims=dims)
+    h = nd.nd_create(p)
+    try:
+        c = nd.nd_get_config(h)
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        nd.nd_set_config(h, c)
+        assert nd.nd_get_config(h).block == cfg["block"]
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, 0.05, steps, nd.observe(3, -1))
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+        R = np.empty(steps // 3 + 1)
+        nd.nd_get_observables(h, R=R, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    return y, R
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("model", ["kuramoto", "inertia"])
+@pytest.mark.parametrize("dims,P,scatter,gather", [
+    ((12, 12, 12), 1, dict(tile=12, tile_y=12, tile_z=3, block=512), dict(tile=12, tile_y=12, tile_z=12, block=1024)),
+    ((20, 18, 16), 2, dict(tile=20, tile_y=18, tile_z=5, block=512), dict(tile=20, tile_y=18, tile_z=16, block=1024)),
+    ((20, 18, 16), 2, dict(tile=7, tile_y=5, tile_z=3, block=512), dict(tile=7, tile_y=4, tile_z=7, block=256)),
+    ((13, 14, 15), 6, dict(tile=13, tile_y=14, tile_z=4, block=512), dict(tile=13, tile_y=12, tile_z=15, block=1024)),
+    ((16, 15, 14), 6, dict(tile=5, tile_y=3, tile_z=1, block=512), dict(tile=5, tile_y=7, tile_z=3, block=1024))])
+def test_ball_scatter_matches_gather_bitwise(nd, prec, model, dims, P, scatter, gather):
+    """The plane-scatter form (block 512) adds every output's runs in the
+    gather form's (dz, dy) order, so with the same x tiling (the row prefix
+    sums start at the same halo column) the two give bitwise equal states for
+    any y and z tilings (ragged tiles, z runs shorter than the 2P lead-in); R
+    sums the per-work-item partials in tile order, so it agrees to rounding."""
+    print(f"case ball scatter/gather {model} prec={prec} dims={dims} P={P} {scatter} {gather}", flush=True)
+    ys, Rs = run_cfg(nd, model, dims, P, 21 + P, 7, prec, scatter)
+    yg, Rg = run_cfg(nd, model, dims, P, 21 + P, 7, prec, gather)
+    assert np.array_equal(ys, yg)
+    assert np.max(np.abs(Rs - Rg)) < 1e-13
+
+
+def test_ball_scatter_other_x_tiling(nd):
+    """Different x tilings move the row prefix origins, so the forms then
+    agree to rounding (both are checked against the oracle elsewhere)."""
+    ys, _ = run_cfg(nd, "inertia", (20, 18, 16), 2, 23, 7, 0, dict(tile=7, tile_y=5, tile_z=3, block=512))
+    yg, _ = run_cfg(nd, "inertia", (20, 18, 16), 2, 23, 7, 0, dict(tile=9, tile_y=4, tile_z=7, block=256))
+    assert np.max(np.abs(ys - yg)) < 1e-12
+
+
+@pytest.mark.parametrize("cfg", [dict(tile=1, tile_y=1, tile_z=1, block=512),
+                                 dict(tile=52, tile_y=9, tile_z=2, block=512),
+                                 dict(tile=11, tile_y=20, tile_z=40, grid=5, chunk=2, block=512)])
+def test_ball_scatter_tilings_p6(nd, cfg):
+    """Plane-scatter form at P = 6 against the oracle: single-element tiles
+    (every output plane a lead-in edge case), the widest halo row (HX = 64) and
+    a z run longer than the lattice, under a persistent grid and graph chunks."""
+    print(f"case ball scatter P=6 cfg={cfg}", flush=True)
+    y, ref, _, _, _, _, nv = case(nd, "inertia", (52, 20, 13), 6, 8, 5, cfg=cfg)
+    assert normwise(y, ref, nv) < 1e-12
+
+
+def test_ball_default_config_forms(nd):
+    """Balls of radius 3 and more default to the plane-scatter form (block 512),
+    radius 1 and 2 and the disk to the gather form; the scatter block can be
+    chosen for any ball radius, and is refused for the disk."""
+    def make(topo, P, dims):
+        n = dims[0] * dims[1] * dims[2]
+        return nd.nd_create(nd.problem(nd.ND_KURAMOTO, topo, n, KUR, radius=P, dims=dims))
+    for P in (1, 2, 3, 4, 6, 8):
+        h = make(nd.ND_BALL3D, P, (30, 30, 30))
+        try:
+            c = nd.nd_get_config(h)
+            assert c.block == 512 if P >= 3 else c.block in (256, 1024), (P, c.block)
+            if c.block != 512:
+                c.block, c.tile, c.tile_y = 512, 8, 8
+                nd.nd_set_config(h, c)
+                assert nd.nd_get_config(h).block == 512
+        finally:
+            nd.nd_destroy(h)
+    h = make(nd.ND_DISK2D, 6, (40, 40, 1))
+    try:
+        c = nd.nd_get_config(h)
+        assert c.block in (256, 1024)
+        c.block = 512
+        with pytest.raises(nd.NDError):
+            nd.nd_set_config(h, c)
+    finally:
+        nd.nd_destroy(h)
 
 
 def case2d(nd, model, n1, n2, P, seed, steps, prec=0, cfg=None, record_every=0):
