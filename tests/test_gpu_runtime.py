@@ -87,6 +87,9 @@ def _cases(nd):
                  inputs.kuramoto_phases(25, 14 ** 3), 0.05),
         "ball": (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 12 ** 3, INERT, radius=2, dims=(12,) * 3),
                  np.concatenate([inputs.kuramoto_phases(26, 12 ** 3), np.zeros(12 ** 3)]), 0.05),
+        # radius 3: the plane-scatter form
+        "ball_scatter": (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 13 ** 3, INERT, radius=3, dims=(13,) * 3),
+                         np.concatenate([inputs.kuramoto_phases(28, 13 ** 3), np.zeros(13 ** 3)]), 0.05),
         "links": (nd.problem(nd.ND_FHN, nd.ND_LINKS, 900, FHN_PRM, row_ptr=sw[0], col=sw[1]),
                   inputs.fhn_circle(27, 900), 0.01),
         "csr": (nd.problem(nd.ND_HH, nd.ND_CSR, 500, HH_PRM, row_ptr=rp, col=col, weight=w,
@@ -94,7 +97,7 @@ def _cases(nd):
     }
 
 
-@pytest.mark.parametrize("kind", ["ring_resident", "ring_tiled", "cube", "ball", "links", "csr"])
+@pytest.mark.parametrize("kind", ["ring_resident", "ring_tiled", "cube", "ball", "ball_scatter", "links", "csr"])
 def test_nonfinite_state_is_reported_for_that_network_only(nd, kind):
     """A NaN planted in one network's device state: after a batched run the next
     synchronising call on it returns ND_ERR_NUMERIC, the other network of the

@@ -43,6 +43,9 @@ def cases(nd):
         (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 12 ** 3, [0.0, 0.5, 0.45, 1.0, 0.05], radius=2,
                     dims=(12, 12, 12)),
          np.concatenate([inputs.kuramoto_phases(11, 12 ** 3), np.zeros(12 ** 3)]), 0.05, 40, 4),
+        (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 13 ** 3, [0.0, 0.5, 0.45, 1.0, 0.05], radius=4,
+                    dims=(13, 13, 13)),  # plane-scatter form
+         np.concatenate([inputs.kuramoto_phases(14, 13 ** 3), np.zeros(13 ** 3)]), 0.05, 21, 3),
         (nd.problem(nd.ND_KURAMOTO, nd.ND_DISK2D, 20 * 18, [0.0, 1.0, 0.8], radius=3, dims=(20, 18, 1)),
          inputs.kuramoto_phases(12, 20 * 18), 0.05, 33, 0),
         (nd.problem(nd.ND_FHN, nd.ND_LINKS, 1500, FHN_PRM, row_ptr=sw[0], col=sw[1]), inputs.fhn_circle(13, 1500),

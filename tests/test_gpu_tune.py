@@ -45,3 +45,28 @@ def test_tune_ring_and_cube(nd, tmp_path):
         assert len([l for l in f.read_text().splitlines() if not l.startswith("#")]) == 2
     finally:
         nd.nd_tune_clear()
+
+
+def test_tune_ball_chooses_between_forms(nd):
+    """The tuner times the plane-scatter form's tilings and the gather form's;
+    a network created afterwards uses the winner and matches the oracle."""
+    nd.nd_tune_clear()
+    try:
+        n1, P = 20, 6
+        n = n1 ** 3
+        prm = [0.1, 1.0, 0.45, 1.0, 0.05]
+        p = nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, radius=P, dims=(n1,) * 3)
+        y0 = np.concatenate([inputs.kuramoto_phases(3, n), np.zeros(n)])
+        best, ms = nd.nd_tune(p, y0, 0.05, 2)
+        assert best.block in (256, 512, 1024) and ms > 0
+        h = nd.nd_create(p)
+        try:
+            c = nd.nd_get_config(h)
+            assert (c.block, c.tile, c.tile_y, c.tile_z) == (best.block, best.tile, best.tile_y, best.tile_z)
+        finally:
+            nd.nd_destroy(h)
+        y, _, _ = nd.simulate(p, y0, 0.05, 4)
+        ref, _, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, 4)
+        assert np.max(np.abs(y - ref)) / np.max(np.abs(ref)) < 1e-12
+    finally:
+        nd.nd_tune_clear()
