@@ -63,6 +63,7 @@ struct Net {
     // are enqueued on it, and the pinned status word is supplied by the owner.
     hipStream_t astream = nullptr;
     bool own_status_host = true;
+    int dev = 0;  // device the network's buffers live on
 
     ~Net();
     // wait until the device no longer uses this network's buffers
@@ -73,6 +74,7 @@ struct Net {
     void touch_shared(const std::shared_ptr<RunEvent>& ev);
     void drop_graphs();
     nd_status alloc(void** ptr, size_t bytes);
+    void free_buf(void* ptr);
     nd_status create(const nd_problem* p);
     nd_status apply_config(const nd_kernel_config& c);
     int64_t work_items() const;

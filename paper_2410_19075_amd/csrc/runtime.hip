@@ -396,13 +396,81 @@ int64_t footprint_bytes(const nd_problem* p, const nd_kernel_config& c) {
 }
 
 // -------------------------------------------------------------- allocation
+// Buffers of networks the caller owns come from the device's stream-ordered
+// pool, allocated and freed on a stream of the library's own (one per device,
+// non-blocking, default priority).  A network's buffers are freed only after its
+// own work has completed (its event), so destroying or reconfiguring a network
+// waits for that network alone; hipFree would wait for the whole device.
+constexpr int kMaxDevices = 64;
+static std::mutex g_ls_mu;
+static hipStream_t g_ls[kMaxDevices] = {};
+
+static nd_status lib_stream(int dev, hipStream_t* out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(ND_ERR_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_ls_mu);
+    if (!g_ls[dev]) {
+        int cur = 0;
+        HIPC(hipGetDevice(&cur));
+        if (cur != dev) HIPC(hipSetDevice(dev));
+        const hipError_t e = hipStreamCreateWithFlags(&g_ls[dev], hipStreamNonBlocking);
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate (allocation stream)");
+    }
+    *out = g_ls[dev];
+    return ND_OK;
+}
+
 nd_status Net::alloc(void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 8;
-    hipError_t e = astream ? hipMallocAsync(ptr, bytes, astream) : hipMalloc(ptr, bytes);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    hipError_t e;
+    if (astream) {
+        e = hipMallocAsync(ptr, bytes, astream);
+    } else {
+        hipStream_t ls;
+        const nd_status s = lib_stream(dev, &ls);
+        if (s) return s;
+        // ready for use on any stream once the allocation stream has passed it
+        e = hipMallocAsync(ptr, bytes, ls);
+        if (e == hipSuccess) e = hipStreamSynchronize(ls);
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
     allocs.push_back(*ptr);
     return ND_OK;
+}
+
+// Pinned host words for the networks' status read-backs, carved from blocks
+// that live until the process ends (hipHostFree would wait for the device).
+static std::mutex g_pin_mu;
+static std::vector<int32_t*> g_pin_free;
+
+static nd_status pinned_word(int32_t** out) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (g_pin_free.empty()) {
+        constexpr int kWords = 4096;
+        int32_t* blk = nullptr;
+        HIPC(hipHostMalloc((void**)&blk, kWords * sizeof(int32_t)));
+        for (int i = kWords - 1; i >= 0; --i) g_pin_free.push_back(blk + i);
+    }
+    *out = g_pin_free.back();
+    g_pin_free.pop_back();
+    return ND_OK;
+}
+
+static void pinned_word_put(int32_t* w) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(w);
+}
+
+// Return one of this network's buffers to the pool; the device no longer uses
+// it (the caller has waited for the network's work, or owns astream's order).
+void Net::free_buf(void* q) {
+    if (astream) {
+        (void)hipFreeAsync(q, astream);
+        return;
+    }
+    hipStream_t ls;
+    if (lib_stream(dev, &ls) == ND_OK) (void)hipFreeAsync(q, ls);
 }
 
 RunEvent::~RunEvent() {
@@ -439,17 +507,12 @@ void Net::drop_graphs() {
 }
 
 Net::~Net() {
-    if (astream) {
-        // the owner has seen the network's last work complete; the frees are
-        // ordered on astream (no device-wide synchronisation)
-        drop_graphs();
-        for (void* q : allocs) (void)hipFreeAsync(q, astream);
-    } else {
-        quiesce();
-        drop_graphs();
-        for (void* q : allocs) (void)hipFree(q);
-    }
-    if (status_host && own_status_host) (void)hipHostFree(status_host);
+    // server networks: the owner has seen the last work complete and the frees
+    // are ordered on astream; others: wait for this network's own work
+    if (!astream) quiesce();
+    drop_graphs();
+    for (void* q : allocs) free_buf(q);
+    if (status_host && own_status_host) pinned_word_put(status_host);
     if (last_ev) (void)hipEventDestroy(last_ev);
 }
 
@@ -494,6 +557,7 @@ static void derive_params(const nd_problem* p, NetDesc& d) {
 }
 
 nd_status Net::create(const nd_problem* pr) {
+    HIPC(hipGetDevice(&dev));
     prob = *pr;
     prob.row_ptr = nullptr;
     prob.col = nullptr;
@@ -589,7 +653,7 @@ nd_status Net::create(const nd_problem* pr) {
     if ((s = alloc((void**)&solo_count, 2 * sizeof(int)))) return s;
     if ((s = alloc((void**)&status_dev, sizeof(int32_t)))) return s;
     HIPC(astream ? hipMemsetAsync(status_dev, 0, sizeof(int32_t), astream) : hipMemset(status_dev, 0, sizeof(int32_t)));
-    if (own_status_host) HIPC(hipHostMalloc((void**)&status_host, sizeof(int32_t)));
+    if (own_status_host && (s = pinned_word(&status_host))) return s;
     *status_host = 0;
     HIPC(hipEventCreateWithFlags(&last_ev, hipEventDisableTiming));
     d.status = status_dev;
@@ -603,7 +667,7 @@ nd_status Net::apply_config(const nd_kernel_config& c) {
     drop_graphs();
     auto release = [&](void*& q) {
         if (!q) return;
-        (void)hipFree(q);
+        free_buf(q);
         allocs.erase(std::find(allocs.begin(), allocs.end(), q));
         q = nullptr;
     };
@@ -682,7 +746,8 @@ nd_status Net::prepare_observe(int64_t steps, const nd_observe* obs, bool may_al
                         (long long)len, (long long)R_cap);
         if (len > R_cap) {
             if (R_dev) {
-                (void)hipFree(R_dev);
+                quiesce();  // earlier runs may still record into it
+                free_buf(R_dev);
                 allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)R_dev));
             }
             if ((s = alloc((void**)&R_dev, len * 8))) return s;

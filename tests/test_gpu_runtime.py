@@ -97,6 +97,42 @@ def _cases(nd):
     }
 
 
+def test_destroy_waits_for_that_network_only(nd):
+    """nd_destroy and nd_set_config wait for the network's own work (its event)
+    and return its buffers to the stream-ordered pool; long torch work queued on
+    another stream keeps running meanwhile.  A network created afterwards reuses
+    pool memory and still matches its oracle run."""
+    import torch
+    p = nd.problem(nd.ND_KURAMOTO, nd.ND_RING, 1024, [0.0, 1.0, 1.46], radius=256)
+    y0 = inputs.kuramoto_phases(31, 1024)
+    h = nd.nd_create(p)
+    nd.nd_set_state(h, y0, on_device=0)
+    nd.nd_run(h, 0.01, 10)
+    nd.nd_sync(h)
+    other = torch.cuda.Stream()
+    a = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(other):
+        e0.record()
+        b = a
+        for _ in range(60):
+            b = torch.mm(b, a) * 1e-3
+        e1.record()
+    t0 = time.perf_counter()
+    c = nd.nd_get_config(h)
+    nd.nd_set_config(h, c)   # rebuilds the per-work-item buffers
+    nd.nd_destroy(h)
+    host_s = time.perf_counter() - t0
+    other.synchronize()
+    gpu_s = e0.elapsed_time(e1) / 1e3
+    print(f"destroy {host_s * 1e3:.2f} ms while the other stream ran {gpu_s * 1e3:.1f} ms")
+    assert gpu_s > 0.05 and host_s < 0.25 * gpu_s
+    y, _, _ = nd.simulate(p, y0, 0.01, 10)
+    ref, _, _ = O.run(O.ring(O.KURAMOTO, 1024, 256, [0.0, 1.0, 1.46]), y0, 0.01, 10)
+    assert np.max(np.abs(y - ref)) < 1e-12
+
+
 @pytest.mark.parametrize("kind", ["ring_resident", "ring_tiled", "cube", "ball", "ball_scatter", "links", "csr"])
 def test_nonfinite_state_is_reported_for_that_network_only(nd, kind):
     """A NaN planted in one network's device state: after a batched run the next
