@@ -32,6 +32,10 @@ def cases(nd, small):
          inputs.kuramoto_phases(64, 20 ** 3), 0.05),
         (nd.problem(nd.ND_FHN, nd.ND_RING, 9000, FHN_PRM, precision=1, radius=2500), inputs.fhn_circle(65, 9000),
          0.01),
+        # a ball in plane-scatter form (radius 3)
+        (nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, 14 ** 3, [0.0, 0.5, 0.45, 1.0, 0.05], radius=3,
+                    dims=(14,) * 3),
+         np.concatenate([inputs.kuramoto_phases(66, 14 ** 3), np.zeros(14 ** 3)]), 0.05),
     ]
 
 
