@@ -21,7 +21,8 @@
 //     bookkeeping of the 13-access schedule; its own operands were prefetched
 //     one output plane ahead.
 // Each output's sum visits the runs in (dz, dy) order, the order of the gather
-// form, so both forms give bitwise identical stage values.  With the radius
+// form, so both forms give bitwise identical stage values when their x tilings
+// agree (the row prefix sums then start at the same halo column).  With the radius
 // fixed at compile time every run's LDS offset is a constant relative to the
 // thread's row base, so the sums carry no per-run address arithmetic.
 #include <utility>

@@ -58,9 +58,10 @@ struct Net {
     hipGraphExec_t solo_graph[2] = {nullptr, nullptr};
     int solo_graph_key[2][2] = {{0, 0}, {0, 0}};
     std::vector<void*> allocs;
-    // Stream-ordered mode (networks the server owns): buffers come from the device's
-    // stream-ordered pool (hipMallocAsync / hipFreeAsync on `astream`), set-up copies
-    // are enqueued on it, and the pinned status word is supplied by the owner.
+    // Buffers come from the device's stream-ordered pool.  Networks the server
+    // owns allocate and free on `astream`, enqueue their set-up copies on it and
+    // use a pinned status word the owner supplies; others allocate on the
+    // library's own stream and free there after their last work (free_buf).
     hipStream_t astream = nullptr;
     bool own_status_host = true;
     int dev = 0;  // device the network's buffers live on
