@@ -212,6 +212,45 @@ def test_ball_default_config_forms(nd):
         nd.nd_destroy(h)
 
 
+@pytest.fixture(scope="module")
+def ball100_p6_one_step():
+    """The ball workload's state (100^3, radius 6, 925 links, Sec. V: m = 1,
+    eps = 0.05, mu = 0.01, alpha = 0.45, planted coherent ball, psi = 0) and the
+    oracle's result after one step."""
+    n1, P = 100, 6
+    n = n1 ** 3
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(1000, n1), np.zeros(n)])
+    ref, Rref, _ = O.run(O.ball(n1, P, prm, model=O.INERTIA), y0, 0.05, 1, record_every=1)
+    return n1, P, prm, y0, ref, Rref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ball_full_100_p6_one_step(nd, ball100_p6_one_step, prec):
+    """The ball workload at full size in its launch configuration (the default:
+    plane-scatter form, two workgroups per CU), one step, every element and R
+    against the oracle."""
+    print(f"case full 100^3 ball P=6 prec={prec}, one step", flush=True)
+    n1, P, prm, y0, ref, Rref = ball100_p6_one_step
+    n = n1 ** 3
+    p = nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, precision=prec, radius=P, dims=(n1,) * 3)
+    h = nd.nd_create(p)
+    try:
+        assert nd.nd_get_config(h).block == 512
+        nd.nd_set_state(h, y0, on_device=0)
+        nd.nd_run(h, 0.05, 1, nd.observe(1, -1))
+        y = np.empty_like(y0)
+        nd.nd_get_state(h, y, on_device=0)
+        R = np.empty(2)
+        nd.nd_get_observables(h, R=R, on_device=0)
+    finally:
+        nd.nd_destroy(h)
+    e = normwise(y, ref, 2)
+    print(f"ball 100^3 P=6 prec={prec} one-step error {e:.3e}")
+    assert e < (1e-12 if prec == 0 else 1e-4)
+    assert np.max(np.abs(R - Rref)) < (1e-12 if prec == 0 else 1e-4)
+
+
 def case2d(nd, model, n1, n2, P, seed, steps, prec=0, cfg=None, record_every=0):
     n = n1 * n2
     phases = inputs.kuramoto_phases(seed, n)
