@@ -113,6 +113,29 @@ def test_fp32_bulk_long_horizon_inertia_ball(nd):
     assert err[1] <= max(1e-3, 2 * floor[1])
 
 
+def test_fp32_bulk_long_horizon_inertia_ball_p6(nd):
+    """The paper's 925-link state (ball of radius 6, the plane-scatter form) on
+    60^3 over 100 time units: FP32-bulk statistics against FP64, the FP64 floor
+    from the gather form (another summation grouping at the same x tiling is
+    bitwise equal, so the floor takes a different x tiling)."""
+    from paper_2410_19075_amd import inputs
+    n1, steps = 60, 2000
+    n = n1 ** 3
+    prm = [0.0, 0.01, 0.45, 1.0, 0.05]
+    y0 = np.concatenate([inputs.cube_phases_with_patch(22, n1), np.zeros(n)])
+    mk = lambda prec: nd.problem(nd.ND_KURAMOTO_INERTIA, nd.ND_BALL3D, n, prm, precision=prec, radius=6,
+                                 dims=(n1,) * 3)
+    half = steps // 2
+    a64 = run_cfg(nd, mk(0), y0, steps, 0.05, half)
+    b64 = run_cfg(nd, mk(0), y0, steps, 0.05, half, dict(tile=17, tile_y=11, tile_z=20, block=1024))
+    a32 = run_cfg(nd, mk(1), y0, steps, 0.05, half)
+    floor, err = stats_gap(a64, b64, half), stats_gap(a64, a32, half)
+    print(f"inertia ball P=6: fp64 floor {floor}; fp32-bulk {err}")
+    assert np.all(np.isfinite(a32[0])) and np.all(np.isfinite(a32[1]))
+    assert err[0] <= max(1e-3, 2 * floor[0])
+    assert err[1] <= max(1e-3, 2 * floor[1])
+
+
 def test_fp32_bulk_long_horizon_links_small_world(nd):
     """FHN on a small-world coupling matrix (ring of radius 300 plus 2000
     shortcuts, compressed) over 10^4 steps; the FP64 floor from a one-ulp
