@@ -80,7 +80,7 @@ __device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const 
     // slopes of stage value z: map, block prefix sums, window sums, RHS
     auto slopes = [&](const double (&z)[EPT][V], double (&kout)[EPT][V]) {
         double2 x[EPT];
-        double tot[2] = {0.0, 0.0}, none[2] = {0.0, 0.0};
+        double tot[2] = {0.0, 0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = tid * EPT + e;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void ring_dopri(const NetDesc* __restrict__ D, const 
             pf[tid * EPT + e] = tot[0];
             pf[T + tid * EPT + e] = tot[1];
         }
-        block_sum_and_exscan<kDpBS, 2, 2>(none, tot, lds);
+        block_exscan<kDpBS, 2>(tot, lds);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             pf[tid * EPT + e] += tot[0];
@@ -405,8 +405,8 @@ __global__ __launch_bounds__(kDtBS) void k_dt_offsets(const DtNet* __restrict__ 
     for (int b0 = 0; b0 < r.G; b0 += kDtBS) {
         const int q = b0 + (int)threadIdx.x;
         const double own0 = q < r.G ? r.tot[q] : 0.0, own1 = q < r.G ? r.tot[r.G + q] : 0.0;
-        double v[2] = {own0, own1}, none[1] = {0.0};
-        block_sum_and_exscan<kDtBS, 1, 2>(none, v, lds);  // v: exclusive prefix in this chunk
+        double v[2] = {own0, own1};
+        block_exscan<kDtBS, 2>(v, lds);  // v: exclusive prefix in this chunk
         if (threadIdx.x == kDtBS - 1) {
             chunk[0] = v[0] + own0;
             chunk[1] = v[1] + own1;
@@ -449,12 +449,12 @@ __global__ __launch_bounds__(kDtBS) void k_dt_rhs(const DtNet* __restrict__ R, c
         // each thread adds a run of consecutive tile totals; the block scans the
         // runs' sums; every workgroup of the ring computes the same offsets
         const int per = (G + kDtBS - 1) / kDtBS, u0 = min(tid * per, G), u1 = min(u0 + per, G);
-        double v[2] = {0.0, 0.0}, none[1] = {0.0};
+        double v[2] = {0.0, 0.0};
         for (int u = u0; u < u1; ++u) {
             v[0] += r.tot[u];
             v[1] += r.tot[G + u];
         }
-        block_sum_and_exscan<kDtBS, 1, 2>(none, v, lds);
+        block_exscan<kDtBS, 2>(v, lds);
         for (int u = u0; u < u1; ++u) {
             dt_off[u] = v[0];
             dt_off[G + u] = v[1];

@@ -224,4 +224,31 @@ __device__ __forceinline__ void block_sum_and_exscan(double (&r)[NR], double (&s
     lds_barrier();
 }
 
+// Block-exclusive prefix (thread order) of NS values, in every thread: the scan
+// half of block_sum_and_exscan, for callers with no block sums to take along.
+// lds: NS * (BS/64) doubles.
+template <int BS, int NS>
+__device__ __forceinline__ void block_exscan(double (&s)[NS], double* lds) {
+    constexpr int NW = BS / kWave;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    double incl[NS], excl[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        incl[q] = wave_incl_scan(s[q]);
+        excl[q] = wave_shift_up1(incl[q]);
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) lds[q * NW + wid] = incl[q];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double a = 0.0;
+        for (int w = 0; w < wid; ++w) a += lds[q * NW + w];
+        s[q] = a + excl[q];
+    }
+    lds_barrier();
+}
+
 }  // namespace nd

@@ -385,7 +385,10 @@ __global__ __launch_bounds__(BS) void k_ring_resident(const NetDesc* __restrict_
                         }
                     }
                 }
-                block_sum_and_exscan<BS, 2, 2>(ru, tot, lds);
+                if constexpr (MODEL == ND_FHN)
+                    block_sum_and_exscan<BS, 2, 2>(ru, tot, lds);
+                else
+                    block_exscan<BS, 2>(tot, lds);  // R comes from the prefix totals
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
                     pf[px(tid * EPT + e)] = tot[0] + pf[px(tid * EPT + e)];
