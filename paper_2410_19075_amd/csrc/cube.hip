@@ -18,9 +18,9 @@
 //     y-pass (2H+1 terms) finish the cube sum for the cx x cy outputs;
 //   * the RHS and the RK bookkeeping follow the 13-access schedule of the ring
 //     kernels (y double-buffered, k in the bulk type).
-// The next plane's column values and RK operands are prefetched one plane
-// ahead, and the plane loop synchronises through LDS-only barriers so those
-// loads stay in flight.  All sums are double and every sum has a fixed order.
+// The coming planes' column values and RK operands are prefetched one to three
+// planes ahead (as registers allow), and the plane loop synchronises through
+// LDS-only barriers so those loads stay in flight.  All sums are double and every sum has a fixed order.
 #include <type_traits>
 
 #include "models.h"
@@ -156,7 +156,9 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         // prefetched operands, PF planes ahead (a shift queue with static
         // indices): the column value of the plane entering the z window and
         // the RK operands of the output plane
-        constexpr int PF = sizeof(KT) == 8 ? 1 : 2;  // FP64 registers are the tighter budget
+        // FP64 registers are the tighter budget: two planes ahead in the stages
+        // with room under 128 VGPRs (1 and 3), one in the others; FP32-bulk three
+        constexpr int PF = sizeof(KT) == 8 ? ((STAGE == 1 || STAGE == 3) ? 2 : 1) : 3;
         double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
         auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
             // operands of output plane z0 + ahead (clamped inside this work item)
