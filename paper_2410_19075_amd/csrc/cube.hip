@@ -156,9 +156,11 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         // prefetched operands, PF planes ahead (a shift queue with static
         // indices): the column value of the plane entering the z window and
         // the RK operands of the output plane
-        // FP64 registers are the tighter budget: two planes ahead in the stages
-        // with room under 128 VGPRs (1 and 3), one in the others; FP32-bulk three
-        constexpr int PF = sizeof(KT) == 8 ? ((STAGE == 1 || STAGE == 3) ? 2 : 1) : 3;
+        // as far ahead as 128 VGPRs allow: for the one-variable model two planes
+        // in FP64 stages 1 and 3 and one in stages 2 and 4, three in FP32-bulk;
+        // the inertia model (its psi operands besides) one in FP64, two in FP32-bulk
+        constexpr int PF = V == 1 ? (sizeof(KT) == 8 ? ((STAGE == 1 || STAGE == 3) ? 2 : 1) : 3)
+                                  : (sizeof(KT) == 8 ? 1 : 2);
         double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
         auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
             // operands of output plane z0 + ahead (clamped inside this work item)
