@@ -20,7 +20,10 @@
 //     kernels (y double-buffered, k in the bulk type).
 // The coming planes' column values and RK operands are prefetched one to three
 // planes ahead (as registers allow), and the plane loop synchronises through
-// LDS-only barriers so those loads stay in flight.  All sums are double and every sum has a fixed order.
+// LDS-only barriers so those loads stay in flight.  In FP64 runs of the
+// one-variable model the three passes work on consecutive planes at once (the
+// z-sums of plane i, the x-pass of plane i-1, the outputs of plane i-2) with one
+// barrier per plane.  All sums are double and every sum has a fixed order.
 #include <type_traits>
 
 #include "models.h"
@@ -104,9 +107,18 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
             if (tid == 0) gp(d.R)[g / d.r_every] = sqrt(s[0] * s[0] + s[1] * s[1]) / (double)n;
         }
 
-        double2* S1 = smem;                  // [2][HY][HX] z-sums per halo column
-        double2* S0 = S1 + 2 * HX * HY;      // [2][cy][cx] mapped centre values
-        double2* S2 = S0 + 2 * cx * cy;      // [2][HY][cx] x-pass sums
+        // The plane loop runs in one of two schedules that do the same arithmetic
+        // per output (each written out in full: sharing the passes as lambdas
+        // changed the register allocation and cost FP32-bulk 10 %).  Two-phase: the column threads' z-sums of plane i, a
+        // barrier, the x-pass of plane i, a barrier, the y-pass and RHS of plane i
+        // (two LDS buffers per array).  Pipelined (FP64, one-variable model): in
+        // one phase the column threads do plane i, the x-pass plane i-1 and the
+        // output threads plane i-2, then one barrier (three LDS buffers).
+        constexpr bool kPipe = sizeof(KT) == 8 && V == 1;
+        constexpr int NB = kPipe ? 3 : 2;    // LDS buffers per array (cube_lds_buffers)
+        double2* S1 = smem;                  // [NB][HY][HX] z-sums per halo column
+        double2* S0 = S1 + NB * HX * HY;     // [NB][cy][cx] mapped centre values
+        double2* S2 = S0 + NB * cx * cy;     // [NB][HY][cx] x-pass sums
 
         // halo-column thread
         const bool col = tid < HX * HY;
@@ -153,136 +165,277 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
             zsy += (double)rb[u].y;
         }
         rb[2 * H] = to_rb(make_double2(0.0, 0.0));
-        // prefetched operands, PF planes ahead (a shift queue with static
-        // indices): the column value of the plane entering the z window and
-        // the RK operands of the output plane
-        // as far ahead as 128 VGPRs allow: for the one-variable model two planes
-        // in FP64 stages 1 and 3 and one in stages 2 and 4, three in FP32-bulk;
-        // the inertia model (its psi operands besides) one in FP64, two in FP32-bulk
-        constexpr int PF = V == 1 ? (sizeof(KT) == 8 ? ((STAGE == 1 || STAGE == 3) ? 2 : 1) : 3)
-                                  : (sizeof(KT) == 8 ? 1 : 2);
-        double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
-        auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
-            // operands of output plane z0 + ahead (clamped inside this work item)
-            const int zo_ = z0 + min(ahead, nz - 1);
-            const uint32_t ci = colbase + plane * (uint32_t)wrapm(zo_ + H, n3);
-            cy_ = ld32(y, ci);
-            ck_ = stage != 1 ? (double)ld32(kp, ci) : 0.0;
-            const uint32_t oi = obase + plane * (uint32_t)zo_;
-            ry_ = ld32(y, oi);
-            rk_ = (stage == 2 || stage == 4) ? (double)ld32(kp, oi) : 0.0;
-            ra_ = stage == 4 ? ld32(acc, oi) : 0.0;
-        };
-#pragma unroll
-        for (int f = 0; f < PF; ++f) fetch(f, qy[f], qk[f], qry[f], qrk[f], qra[f]);
         double part[2] = {0.0, 0.0};  // stage 1: sums of map(y) for R
-        for (int zb = 0; zb < nz; zb += S) {
+        if constexpr (!kPipe) {
+            // two-phase schedule; prefetched operands PF planes ahead (a shift
+            // queue with static indices): the column value of the plane entering
+            // the z window and the RK operands of the output plane, as far ahead as
+            // 128 VGPRs allow: three planes in FP32-bulk for the one-variable model;
+            // the inertia model (its psi operands besides) one in FP64, two in FP32-bulk
+            constexpr int PF = V == 1 ? 3 : (sizeof(KT) == 8 ? 1 : 2);
+            double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
+            auto fetch = [&](int ahead, double& cy_, double& ck_, double& ry_, double& rk_, double& ra_) {
+                // operands of output plane z0 + ahead (clamped inside this work item)
+                const int zo_ = z0 + min(ahead, nz - 1);
+                const uint32_t ci = colbase + plane * (uint32_t)wrapm(zo_ + H, n3);
+                cy_ = ld32(y, ci);
+                ck_ = stage != 1 ? (double)ld32(kp, ci) : 0.0;
+                const uint32_t oi = obase + plane * (uint32_t)zo_;
+                ry_ = ld32(y, oi);
+                rk_ = (stage == 2 || stage == 4) ? (double)ld32(kp, oi) : 0.0;
+                ra_ = stage == 4 ? ld32(acc, oi) : 0.0;
+            };
 #pragma unroll
-            for (int u = 0; u < S; ++u) {
-                if (zb + u < nz) {
-                    const int zo = z0 + zb + u;
-                    const double zc = stage == 1 ? qy[0] : fma(cdt, qk[0], qy[0]);
-                    const double cry = qry[0], crk = qrk[0], cra = qra[0];
+            for (int f = 0; f < PF; ++f) fetch(f, qy[f], qk[f], qry[f], qrk[f], qra[f]);
+            for (int zb = 0; zb < nz; zb += S) {
 #pragma unroll
-                    for (int f = 0; f + 1 < PF; ++f) {
-                        qy[f] = qy[f + 1];
-                        qk[f] = qk[f + 1];
-                        qry[f] = qry[f + 1];
-                        qrk[f] = qrk[f + 1];
-                        qra[f] = qra[f + 1];
-                    }
-                    fetch(zb + u + PF, qy[PF - 1], qk[PF - 1], qry[PF - 1], qrk[PF - 1], qra[PF - 1]);
-                    // z window of output plane zo: planes zo-H .. zo+H; the new
-                    // plane enters the running sum, the oldest leaves it after
-                    {
-                        double z[1] = {zc};
-                        rb[(u + 2 * H) % S] = to_rb(M::map(z));
-                    }
-                    const double2 sz = make_double2(zsx + (double)rb[(u + 2 * H) % S].x,
-                                                    zsy + (double)rb[(u + 2 * H) % S].y);
-                    zsx = sz.x - (double)rb[u % S].x;
-                    zsy = sz.y - (double)rb[u % S].y;
-                    const int buf = (zb + u) & 1;
-                    if (col) S1[buf * HX * HY + tid] = sz;
-                    if (inner)
-                        S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
-                            make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
-                    lds_barrier();
-                    // x-pass over the HY rows
-                    if (xr) {
-                        const double2* src = S1 + buf * HX * HY + xrow * HX + xs0;
-                        double2* dst = S2 + buf * HY * cx + xrow * cx + xs0;
-                        double2 a = make_double2(0.0, 0.0);
+                for (int u = 0; u < S; ++u) {
+                    if (zb + u < nz) {
+                        const int zo = z0 + zb + u;
+                        const double zc = stage == 1 ? qy[0] : fma(cdt, qk[0], qy[0]);
+                        const double cry = qry[0], crk = qrk[0], cra = qra[0];
 #pragma unroll
-                        for (int dx = 0; dx < S; ++dx) {
-                            a.x += src[dx].x;
-                            a.y += src[dx].y;
+                        for (int f = 0; f + 1 < PF; ++f) {
+                            qy[f] = qy[f + 1];
+                            qk[f] = qk[f + 1];
+                            qry[f] = qry[f + 1];
+                            qrk[f] = qrk[f + 1];
+                            qra[f] = qra[f + 1];
                         }
-                        dst[0] = a;
-                        if constexpr (!kDirectX) {
+                        fetch(zb + u + PF, qy[PF - 1], qk[PF - 1], qry[PF - 1], qrk[PF - 1], qra[PF - 1]);
+                        // z window of output plane zo: planes zo-H .. zo+H; the new
+                        // plane enters the running sum, the oldest leaves it after
+                        {
+                            double z[1] = {zc};
+                            rb[(u + 2 * H) % S] = to_rb(M::map(z));
+                        }
+                        const double2 sz = make_double2(zsx + (double)rb[(u + 2 * H) % S].x,
+                                                        zsy + (double)rb[(u + 2 * H) % S].y);
+                        zsx = sz.x - (double)rb[u % S].x;
+                        zsy = sz.y - (double)rb[u % S].y;
+                        const int buf = (zb + u) & 1;
+                        if (col) S1[buf * HX * HY + tid] = sz;
+                        if (inner)
+                            S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
+                                make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
+                        lds_barrier();
+                        // x-pass over the HY rows
+                        if (xr) {
+                            const double2* src = S1 + buf * HX * HY + xrow * HX + xs0;
+                            double2* dst = S2 + buf * HY * cx + xrow * cx + xs0;
+                            double2 a = make_double2(0.0, 0.0);
 #pragma unroll
-                            for (int r = 1; r < kRunX; ++r) {
-                                if (r < xcnt) {
-                                    const double2 in = src[r + 2 * H], out = src[r - 1];
-                                    a.x = (a.x + in.x) - out.x;
-                                    a.y = (a.y + in.y) - out.y;
-                                    dst[r] = a;
+                            for (int dx = 0; dx < S; ++dx) {
+                                a.x += src[dx].x;
+                                a.y += src[dx].y;
+                            }
+                            dst[0] = a;
+                            if constexpr (!kDirectX) {
+#pragma unroll
+                                for (int r = 1; r < kRunX; ++r) {
+                                    if (r < xcnt) {
+                                        const double2 in = src[r + 2 * H], out = src[r - 1];
+                                        a.x = (a.x + in.x) - out.x;
+                                        a.y = (a.y + in.y) - out.y;
+                                        dst[r] = a;
+                                    }
+                                }
+                            }
+                        }
+                        lds_barrier();
+                        // y-pass, RHS, RK bookkeeping
+                        if (outv) {
+                            const double2* src = S2 + buf * HY * cx + oy * cx + ox;
+                            double2 bsum = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int dy = 0; dy < S; ++dy) {
+                                bsum.x += src[dy * cx].x;
+                                bsum.y += src[dy * cx].y;
+                            }
+                            const double2 xo = S0[buf * cx * cy + oy * cx + ox];
+                            const double2 W = make_double2(bsum.x - xo.x, bsum.y - xo.y);
+                            const uint32_t q = obase + plane * (uint32_t)zo;
+                            // variable 1 (psi, inertia only): operands read here, not prefetched
+                            double y1 = 0.0, kp1 = 0.0, a1 = 0.0;
+                            double zz[V];
+                            zz[0] = 0.0;  // the phase enters through xo
+                            if constexpr (V == 2) {
+                                y1 = ld32(y + n, q);
+                                kp1 = stage != 1 ? (double)ld32(kp + n, q) : 0.0;
+                                a1 = stage == 4 ? ld32(acc + n, q) : 0.0;
+                                zz[V - 1] = stage == 1 ? y1 : fma(cdt, kp1, y1);
+                            }
+                            double k[V];
+                            M::rhs(d, zz, xo, W, k);
+                            const double kk = kq<KT>(k[0]);
+                            if constexpr (V == 2) {
+                                const double kk1 = kq<KT>(k[1]);
+                                if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + n, q, (KT)kk1);
+                                if (stage == 2) st32(gp(d.acc) + n, q, fma(d.dt3, kk1, fma(d.dt6, kp1, y1)));
+                                if (stage == 4) {
+                                    const double yo1 = fma(d.dt6, kk1, fma(d.dt3, kp1, a1));
+                                    st32(gp(d.y[par ^ 1]) + n, q, yo1);
+                                    flag_nonfinite(d, yo1);
+                                }
+                            }
+                            if (stage == 1) {
+                                st32(gp((KT*)d.k[0]), q, (KT)kk);
+                                part[0] += xo.x;
+                                part[1] += xo.y;
+                                if (MV && (d.obs & OBS_MV) && g == d.mv_start) st32(gp(d.mv), q, cry);
+                            } else if (stage == 2) {
+                                st32(gp((KT*)d.k[1]), q, (KT)kk);
+                                st32(gp(d.acc), q, fma(d.dt3, kk, fma(d.dt6, crk, cry)));
+                            } else if (stage == 3) {
+                                st32(gp((KT*)d.k[2]), q, (KT)kk);
+                            } else {
+                                const double yo = fma(d.dt6, kk, fma(d.dt3, crk, cra));
+                                st32(gp(d.y[par ^ 1]), q, yo);
+                                flag_nonfinite(d, yo);
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+            // pipelined schedule: column values PF planes ahead of the column
+            // pass, RK operands PF planes ahead of the output pass (two planes in
+            // stages 1 and 3, one in 2 and 4, within 128 VGPRs)
+            constexpr int PF = (STAGE == 1 || STAGE == 3) ? 2 : 1;
+            double qy[PF], qk[PF], qry[PF], qrk[PF], qra[PF];
+            auto fetch_col = [&](int ahead, double& cy_, double& ck_) {
+                const int zo_ = z0 + min(ahead, nz - 1);
+                const uint32_t ci = colbase + plane * (uint32_t)wrapm(zo_ + H, n3);
+                cy_ = ld32(y, ci);
+                ck_ = stage != 1 ? (double)ld32(kp, ci) : 0.0;
+            };
+            auto fetch_rk = [&](int ahead, double& ry_, double& rk_, double& ra_) {
+                const int zo_ = z0 + min(ahead, nz - 1);
+                const uint32_t oi = obase + plane * (uint32_t)zo_;
+                ry_ = ld32(y, oi);
+                rk_ = (stage == 2 || stage == 4) ? (double)ld32(kp, oi) : 0.0;
+                ra_ = stage == 4 ? ld32(acc, oi) : 0.0;
+            };
+#pragma unroll
+            for (int f = 0; f < PF; ++f) fetch_col(f, qy[f], qk[f]);
+#pragma unroll
+            for (int f = 0; f < PF; ++f) fetch_rk(f, qry[f], qrk[f], qra[f]);
+            const int nit = nz + 2;
+            for (int zb = 0; zb < nit; zb += S) {
+#pragma unroll
+                for (int u = 0; u < S; ++u) {
+                    const int i = zb + u;
+                    if (i >= nit) continue;  // uniform
+                    if (i < nz) {  // column pass, plane i
+                        const double zc = stage == 1 ? qy[0] : fma(cdt, qk[0], qy[0]);
+#pragma unroll
+                        for (int f = 0; f + 1 < PF; ++f) {
+                            qy[f] = qy[f + 1];
+                            qk[f] = qk[f + 1];
+                        }
+                        fetch_col(i + PF, qy[PF - 1], qk[PF - 1]);
+                        {
+                            double z[1] = {zc};
+                            rb[(u + 2 * H) % S] = to_rb(M::map(z));
+                        }
+                        const double2 sz = make_double2(zsx + (double)rb[(u + 2 * H) % S].x,
+                                                        zsy + (double)rb[(u + 2 * H) % S].y);
+                        zsx = sz.x - (double)rb[u % S].x;
+                        zsy = sz.y - (double)rb[u % S].y;
+                        const int buf = i % NB;
+                        if (col) S1[buf * HX * HY + tid] = sz;
+                        if (inner)
+                            S0[buf * cx * cy + (hy - H) * cx + (hx - H)] =
+                                make_double2((double)rb[(u + H) % S].x, (double)rb[(u + H) % S].y);
+                    }
+                    if (i >= 1 && i - 1 < nz) {  // x-pass over the HY rows, plane i - 1
+                        const int buf = (i - 1) % NB;
+                        if (xr) {
+                            const double2* src = S1 + buf * HX * HY + xrow * HX + xs0;
+                            double2* dst = S2 + buf * HY * cx + xrow * cx + xs0;
+                            double2 a = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int dx = 0; dx < S; ++dx) {
+                                a.x += src[dx].x;
+                                a.y += src[dx].y;
+                            }
+                            dst[0] = a;
+                            if constexpr (!kDirectX) {
+#pragma unroll
+                                for (int r = 1; r < kRunX; ++r) {
+                                    if (r < xcnt) {
+                                        const double2 in = src[r + 2 * H], out = src[r - 1];
+                                        a.x = (a.x + in.x) - out.x;
+                                        a.y = (a.y + in.y) - out.y;
+                                        dst[r] = a;
+                                    }
                                 }
                             }
                         }
                     }
-                    lds_barrier();
-                    // y-pass, RHS, RK bookkeeping
-                    if (outv) {
-                        const double2* src = S2 + buf * HY * cx + oy * cx + ox;
-                        double2 bsum = make_double2(0.0, 0.0);
+                    if (i >= 2) {                                    // output plane i - 2
+                        const int io = i - 2;
+                        const double cry = qry[0], crk = qrk[0], cra = qra[0];
 #pragma unroll
-                        for (int dy = 0; dy < S; ++dy) {
-                            bsum.x += src[dy * cx].x;
-                            bsum.y += src[dy * cx].y;
+                        for (int f = 0; f + 1 < PF; ++f) {
+                            qry[f] = qry[f + 1];
+                            qrk[f] = qrk[f + 1];
+                            qra[f] = qra[f + 1];
                         }
-                        const double2 xo = S0[buf * cx * cy + oy * cx + ox];
-                        const double2 W = make_double2(bsum.x - xo.x, bsum.y - xo.y);
-                        const uint32_t q = obase + plane * (uint32_t)zo;
-                        // variable 1 (psi, inertia only): operands read here, not prefetched
-                        double y1 = 0.0, kp1 = 0.0, a1 = 0.0;
-                        double zz[V];
-                        zz[0] = 0.0;  // the phase enters through xo
-                        if constexpr (V == 2) {
-                            y1 = ld32(y + n, q);
-                            kp1 = stage != 1 ? (double)ld32(kp + n, q) : 0.0;
-                            a1 = stage == 4 ? ld32(acc + n, q) : 0.0;
-                            zz[V - 1] = stage == 1 ? y1 : fma(cdt, kp1, y1);
-                        }
-                        double k[V];
-                        M::rhs(d, zz, xo, W, k);
-                        const double kk = kq<KT>(k[0]);
-                        if constexpr (V == 2) {
-                            const double kk1 = kq<KT>(k[1]);
-                            if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + n, q, (KT)kk1);
-                            if (stage == 2) st32(gp(d.acc) + n, q, fma(d.dt3, kk1, fma(d.dt6, kp1, y1)));
-                            if (stage == 4) {
-                                const double yo1 = fma(d.dt6, kk1, fma(d.dt3, kp1, a1));
-                                st32(gp(d.y[par ^ 1]) + n, q, yo1);
-                                flag_nonfinite(d, yo1);
+                        fetch_rk(io + PF, qry[PF - 1], qrk[PF - 1], qra[PF - 1]);
+                        const int zo = z0 + io, buf = io % NB;
+                        if (outv) {
+                            const double2* src = S2 + buf * HY * cx + oy * cx + ox;
+                            double2 bsum = make_double2(0.0, 0.0);
+#pragma unroll
+                            for (int dy = 0; dy < S; ++dy) {
+                                bsum.x += src[dy * cx].x;
+                                bsum.y += src[dy * cx].y;
+                            }
+                            const double2 xo = S0[buf * cx * cy + oy * cx + ox];
+                            const double2 W = make_double2(bsum.x - xo.x, bsum.y - xo.y);
+                            const uint32_t q = obase + plane * (uint32_t)zo;
+                            // variable 1 (psi, inertia only): operands read here, not prefetched
+                            double y1 = 0.0, kp1 = 0.0, a1 = 0.0;
+                            double zz[V];
+                            zz[0] = 0.0;  // the phase enters through xo
+                            if constexpr (V == 2) {
+                                y1 = ld32(y + n, q);
+                                kp1 = stage != 1 ? (double)ld32(kp + n, q) : 0.0;
+                                a1 = stage == 4 ? ld32(acc + n, q) : 0.0;
+                                zz[V - 1] = stage == 1 ? y1 : fma(cdt, kp1, y1);
+                            }
+                            double k[V];
+                            M::rhs(d, zz, xo, W, k);
+                            const double kk = kq<KT>(k[0]);
+                            if constexpr (V == 2) {
+                                const double kk1 = kq<KT>(k[1]);
+                                if (stage <= 3) st32(gp((KT*)d.k[stage - 1]) + n, q, (KT)kk1);
+                                if (stage == 2) st32(gp(d.acc) + n, q, fma(d.dt3, kk1, fma(d.dt6, kp1, y1)));
+                                if (stage == 4) {
+                                    const double yo1 = fma(d.dt6, kk1, fma(d.dt3, kp1, a1));
+                                    st32(gp(d.y[par ^ 1]) + n, q, yo1);
+                                    flag_nonfinite(d, yo1);
+                                }
+                            }
+                            if (stage == 1) {
+                                st32(gp((KT*)d.k[0]), q, (KT)kk);
+                                part[0] += xo.x;
+                                part[1] += xo.y;
+                                if (MV && (d.obs & OBS_MV) && g == d.mv_start) st32(gp(d.mv), q, cry);
+                            } else if (stage == 2) {
+                                st32(gp((KT*)d.k[1]), q, (KT)kk);
+                                st32(gp(d.acc), q, fma(d.dt3, kk, fma(d.dt6, crk, cry)));
+                            } else if (stage == 3) {
+                                st32(gp((KT*)d.k[2]), q, (KT)kk);
+                            } else {
+                                const double yo = fma(d.dt6, kk, fma(d.dt3, crk, cra));
+                                st32(gp(d.y[par ^ 1]), q, yo);
+                                flag_nonfinite(d, yo);
                             }
                         }
-                        if (stage == 1) {
-                            st32(gp((KT*)d.k[0]), q, (KT)kk);
-                            part[0] += xo.x;
-                            part[1] += xo.y;
-                            if (MV && (d.obs & OBS_MV) && g == d.mv_start) st32(gp(d.mv), q, cry);
-                        } else if (stage == 2) {
-                            st32(gp((KT*)d.k[1]), q, (KT)kk);
-                            st32(gp(d.acc), q, fma(d.dt3, kk, fma(d.dt6, crk, cry)));
-                        } else if (stage == 3) {
-                            st32(gp((KT*)d.k[2]), q, (KT)kk);
-                        } else {
-                            const double yo = fma(d.dt6, kk, fma(d.dt3, crk, cra));
-                            st32(gp(d.y[par ^ 1]), q, yo);
-                            flag_nonfinite(d, yo);
-                        }
                     }
+                    lds_barrier();
                 }
             }
         }
@@ -653,9 +806,11 @@ bool cube_select(int model, int prec, int h, CubeLaunch* out) {
     return false;
 }
 
-size_t cube_smem_bytes(int h, int cx, int cy) {
+int cube_lds_buffers(int model, int prec) { return model == ND_KURAMOTO && prec == ND_FP64 ? 3 : 2; }
+
+size_t cube_smem_bytes(int h, int cx, int cy, int nb) {
     const size_t HX = cx + 2 * h, HY = cy + 2 * h;
-    return (2 * HX * HY + 2 * (size_t)cx * cy + 2 * HY * cx) * sizeof(double2);
+    return (nb * HX * HY + nb * (size_t)cx * cy + nb * HY * cx) * sizeof(double2);
 }
 
 int cube_block(int h, int cx, int cy) {

@@ -165,7 +165,10 @@ inline int ball_pz(int topo, int64_t P) { return topo == ND_DISK2D ? 0 : (int)P;
 constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB per CU, minus statics)
 int64_t ball_points(int64_t P);
 int64_t disk_points(int64_t P);
-size_t cube_smem_bytes(int h, int cx, int cy);
+// LDS buffers per array of the cube stage kernel: 3 in its pipelined schedule
+// (FP64, one-variable model), else 2
+int cube_lds_buffers(int model, int prec);
+size_t cube_smem_bytes(int h, int cx, int cy, int nb);
 int cube_block(int h, int cx, int cy);
 hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,
                              const int2* work, const int* nwork, int stage, int j, bool mv);
