@@ -20,10 +20,10 @@
 //     kernels (y double-buffered, k in the bulk type).
 // The coming planes' column values and RK operands are prefetched one to three
 // planes ahead (as registers allow), and the plane loop synchronises through
-// LDS-only barriers so those loads stay in flight.  In FP64 runs of the
-// one-variable model the three passes work on consecutive planes at once (the
-// z-sums of plane i, the x-pass of plane i-1, the outputs of plane i-2) with one
-// barrier per plane.  All sums are double and every sum has a fixed order.
+// LDS-only barriers so those loads stay in flight.  In FP64 runs (the inertia
+// model up to half-width 2) the three passes work on consecutive planes at once
+// (the z-sums of plane i, the x-pass of plane i-1, the outputs of plane i-2)
+// with one barrier per plane.  All sums are double and every sum has a fixed order.
 #include <type_traits>
 
 #include "models.h"
@@ -111,10 +111,11 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         // per output (each written out in full: sharing the passes as lambdas
         // changed the register allocation and cost FP32-bulk 10 %).  Two-phase: the column threads' z-sums of plane i, a
         // barrier, the x-pass of plane i, a barrier, the y-pass and RHS of plane i
-        // (two LDS buffers per array).  Pipelined (FP64, one-variable model): in
+        // (two LDS buffers per array).  Pipelined (FP64: the one-variable model,
+        // and the inertia model for half-widths up to 2, where registers allow): in
         // one phase the column threads do plane i, the x-pass plane i-1 and the
         // output threads plane i-2, then one barrier (three LDS buffers).
-        constexpr bool kPipe = sizeof(KT) == 8 && V == 1;
+        constexpr bool kPipe = sizeof(KT) == 8 && (V == 1 || H <= 2);
         constexpr int NB = kPipe ? 3 : 2;    // LDS buffers per array (cube_lds_buffers)
         double2* S1 = smem;                  // [NB][HY][HX] z-sums per halo column
         double2* S0 = S1 + NB * HX * HY;     // [NB][cy][cx] mapped centre values
@@ -806,7 +807,9 @@ bool cube_select(int model, int prec, int h, CubeLaunch* out) {
     return false;
 }
 
-int cube_lds_buffers(int model, int prec) { return model == ND_KURAMOTO && prec == ND_FP64 ? 3 : 2; }
+int cube_lds_buffers(int model, int prec, int h) {
+    return prec == ND_FP64 && (model == ND_KURAMOTO || h <= 2) ? 3 : 2;
+}
 
 size_t cube_smem_bytes(int h, int cx, int cy, int nb) {
     const size_t HX = cx + 2 * h, HY = cy + 2 * h;

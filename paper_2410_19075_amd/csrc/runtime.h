@@ -166,8 +166,8 @@ constexpr size_t kBallSmemMax = 156 * 1024;  // LDS for the prefix ring (160 KB 
 int64_t ball_points(int64_t P);
 int64_t disk_points(int64_t P);
 // LDS buffers per array of the cube stage kernel: 3 in its pipelined schedule
-// (FP64, one-variable model), else 2
-int cube_lds_buffers(int model, int prec);
+// (FP64: the one-variable model, and the inertia model for h <= 2), else 2
+int cube_lds_buffers(int model, int prec, int h);
 size_t cube_smem_bytes(int h, int cx, int cy, int nb);
 int cube_block(int h, int cx, int cy);
 hipError_t cube_launch_stage(const CubeLaunch& L, int grid, int block, size_t smem, hipStream_t s, NetDesc* D,

@@ -840,7 +840,7 @@ nd_status enqueue_chunk(const Group& g, int chunk, hipStream_t st) {
         if (!cube_select(g.model, g.prec, g.h, &L))
             return fail(ND_ERR_UNSUPPORTED, "no cube kernel for model %d, h = %d", g.model, g.h);
         const int block = cube_block(g.h, g.tile, g.tile_y);
-        const size_t smem = cube_smem_bytes(g.h, g.tile, g.tile_y, cube_lds_buffers(g.model, g.prec));
+        const size_t smem = cube_smem_bytes(g.h, g.tile, g.tile_y, cube_lds_buffers(g.model, g.prec, g.h));
         for (int j = 0; j < chunk; ++j)
             for (int s = 1; s <= 4; ++s)
                 if ((e = cube_launch_stage(L, grid, block, smem, st, g.desc, g.work, g.nwork, s, j, g.mv)) != hipSuccess)
