@@ -108,13 +108,14 @@ __global__ __launch_bounds__(1024) void k_cube_stage(const NetDesc* __restrict__
         }
 
         // The plane loop runs in one of two schedules that do the same arithmetic
-        // per output (each written out in full: sharing the passes as lambdas
-        // changed the register allocation and cost FP32-bulk 10 %).  Two-phase: the column threads' z-sums of plane i, a
+        // per output.  Two-phase: the column threads' z-sums of plane i, a
         // barrier, the x-pass of plane i, a barrier, the y-pass and RHS of plane i
         // (two LDS buffers per array).  Pipelined (FP64: the one-variable model,
-        // and the inertia model for half-widths up to 2, where registers allow): in
-        // one phase the column threads do plane i, the x-pass plane i-1 and the
-        // output threads plane i-2, then one barrier (three LDS buffers).
+        // and the inertia model for half-widths up to 2, where registers allow):
+        // in one phase the column threads do plane i, the x-pass plane i-1 and
+        // the output threads plane i-2, then one barrier (three LDS buffers).
+        // Each schedule is written out in full: sharing the passes as lambdas
+        // changed the register allocation and cost FP32-bulk 10 %.
         constexpr bool kPipe = sizeof(KT) == 8 && (V == 1 || H <= 2);
         constexpr int NB = kPipe ? 3 : 2;    // LDS buffers per array (cube_lds_buffers)
         double2* S1 = smem;                  // [NB][HY][HX] z-sums per halo column
